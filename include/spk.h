@@ -1,0 +1,407 @@
+/*
+ * spk.h -- C ABI of libspk, autotuned bandwidth-bound sparse and vector
+ * kernels for AMD Instinct MI355X (gfx950).
+ *
+ * The library implements, as hand-written HIP kernels, the operations the
+ * paper's annotation-based autotuning targets (Mametjanov & Norris,
+ * "Software Autotuning for Sustainable Performance Portability"):
+ *   - the vector update of Figure 1, read as WAXPY  w = alpha*x + y, with its
+ *     in-place form AXPY and the dot product;
+ *   - the sparse kernels of the prior GPU work cited in Section 3 (CSR
+ *     sparse matrix-vector product y = A*x), in several storage formats;
+ *   - one Krylov-style step fusing both: y = A*x, w = alpha*y + x;
+ *   - the tuning method of Section 2: enumerate code variants over the
+ *     parameters listed in Section 3 (threads per block, blocks per grid,
+ *     asynchronous streams, cache-sized staging, unroll factor), run each,
+ *     compare its outputs with a reference run, and keep the fastest;
+ *   - batched and served execution driven by the tuned variants.
+ *
+ * General conventions (apply to every function below)
+ *   - Every function is extern "C", returns spk_status and never throws.
+ *   - Arrays named "device" are GPU memory owned by the caller (e.g. torch
+ *     tensors).  The library never frees them; a call borrows them until its
+ *     work on the given stream has completed.
+ *   - Kernels are enqueued asynchronously on the caller's stream (a
+ *     hipStream_t passed as spk_stream; NULL is the null stream).  Only
+ *     spk_tune*, spk_matrix_register, spk_batch_plan and spk_serve_*
+ *     synchronise.
+ *   - Argument, shape and dtype errors are reported before any HIP call.
+ *     HIP failures map to SPK_ERR_HIP; spk_last_error() then holds the HIP
+ *     message.  A device fault in asynchronous work surfaces at the caller's
+ *     next synchronisation (or spk_check()).
+ *   - Indices are int32 (nnz < 2^31); sizes are int64.
+ *   - Floating point is IEEE round-to-nearest without flush-to-zero; every
+ *     multiply-add is fused.  FP32 data are accumulated in FP64 and rounded
+ *     once per output.
+ *   - n == 0 or nrows == 0 is valid and launches nothing.
+ */
+#ifndef SPK_H
+#define SPK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPK_ABI_VERSION 1
+
+typedef enum {
+    SPK_OK = 0,
+    SPK_ERR_NULL = 1,        /* a required pointer or handle is NULL */
+    SPK_ERR_SHAPE = 2,       /* negative or inconsistent sizes */
+    SPK_ERR_DTYPE = 3,       /* unknown dtype or mixed dtypes */
+    SPK_ERR_ALIAS = 4,       /* forbidden overlap between inputs and outputs */
+    SPK_ERR_CSR = 5,         /* malformed row_ptr / col_idx (registration only) */
+    SPK_ERR_OOM = 6,         /* device allocation failed */
+    SPK_ERR_BUDGET = 7,      /* request exceeds the server's HBM budget */
+    SPK_ERR_HIP = 8,         /* a HIP runtime call failed */
+    SPK_ERR_VALIDATION = 9,  /* no variant reproduced the reference output */
+    SPK_ERR_NOT_FOUND = 10,  /* unknown id or variant */
+    SPK_ERR_ARG = 11,        /* other invalid argument (options, variant fields) */
+    SPK_ERR_STATE = 12       /* call not allowed in the object's current state */
+} spk_status;
+
+typedef enum { SPK_F32 = 0, SPK_F64 = 1 } spk_dtype;
+
+typedef enum {
+    SPK_OP_SPMV = 0,        /* y = A*x */
+    SPK_OP_WAXPY = 1,       /* w = alpha*x + y */
+    SPK_OP_AXPY = 2,        /* y = alpha*x + y */
+    SPK_OP_DOT = 3,         /* d = sum x_i*y_i */
+    SPK_OP_SPMV_WAXPY = 4   /* y = A*x; w = alpha*y + x */
+} spk_op;
+
+/* Storage format / kernel family of a SpMV variant. */
+typedef enum {
+    SPK_FMT_AUTO = 0,       /* let the library choose (tuned plan or default) */
+    SPK_FMT_SCALAR = 1,     /* CSR, one lane per row */
+    SPK_FMT_VECTOR = 2,     /* CSR, `group` lanes per row (64 = one wavefront) */
+    SPK_FMT_SELL = 3,       /* sliced ELL, `group` rows per slice, column-major slices */
+    SPK_FMT_ADAPTIVE = 4    /* CSR row blocks staged through LDS (`lds` entries per block) */
+} spk_format;
+
+typedef void *spk_stream;                 /* hipStream_t */
+typedef struct spk_ctx *spk_handle;       /* library-owned: device, plan DB, scratch */
+typedef struct spk_mat *spk_matrix;       /* library-owned resident matrix */
+typedef struct spk_batch_s *spk_batch;    /* library-owned batched plan */
+typedef struct spk_server_s *spk_server;  /* library-owned serving loop */
+
+/* Borrowed view of a CSR matrix.  row_ptr[nrows+1] (row_ptr[0] == 0,
+ * non-decreasing, row_ptr[nrows] == nnz), col_idx[nnz] in [0, ncols),
+ * val[nnz] of `dtype`.  Unsorted rows, duplicate columns and explicit zeros
+ * are allowed: every stored entry contributes.  Whether the arrays are host
+ * or device memory is stated by each function. */
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    int32_t dtype;                 /* spk_dtype */
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const void *val;
+} spk_csr;
+
+/* One point of the tuning space (Section 3 lists the parameters: threads per
+ * block, blocks per grid, streams, cache size, unroll).  Fields that do not
+ * apply to an operation must be 0.
+ *   format  spk_format (SpMV only)
+ *   block   threads per workgroup (64..1024, power of two)
+ *   group   SpMV VECTOR: lanes per row (2..64); SELL: rows per slice
+ *   unroll  independent loads in flight per lane (1, 2, 4 or 8)
+ *   vec     vector ops: elements per lane load (1, 2 or 4; at most 16 bytes)
+ *   grid    vector ops: 0 = one pass, else workgroups per compute unit of a
+ *           grid-stride launch
+ *   streams SpMV: split rows over this many streams (1, 2 or 4)
+ *   lds     SpMV VECTOR: 1 = stage row_ptr in LDS; ADAPTIVE: LDS tile in
+ *           entries per workgroup (the "L1 size" knob; gfx950 has no L1/LDS
+ *           split, so the staged tile size takes its place) */
+typedef struct {
+    int32_t format, block, group, unroll, vec, grid, streams, lds;
+} spk_variant;
+
+/* ------------------------------------------------------------- library -- */
+
+/* SPK_ABI_VERSION of the loaded library. */
+int spk_abi_version(void);
+
+/* Human-readable name of a status code (static storage). */
+const char *spk_status_str(spk_status s);
+
+/* Creates a handle on HIP device `device`.  `db_path` (nullable) names a
+ * tuning database file: winners found by spk_tune are appended there and
+ * loaded by later handles; entries from another GPU architecture or library
+ * build are ignored.  Environment: SPK_PLAIN=1 makes every call use the
+ * fixed plain variants; SPK_DB_PATH supplies db_path when it is NULL. */
+spk_status spk_create(int device, const char *db_path, spk_handle *out);
+
+/* Releases the handle and everything it owns (matrices and batches created
+ * from it must be released first). */
+spk_status spk_destroy(spk_handle h);
+
+/* Message of the calling thread's last non-OK status (static per thread). */
+const char *spk_last_error(void);
+
+/* Waits for `stream` and reports any asynchronous HIP error. */
+spk_status spk_check(spk_handle h, spk_stream stream);
+
+/* Selects how untuned calls pick variants: 0 = plan DB, else built-in
+ * default; 1 = always the fixed plain variants (the untuned baseline). */
+spk_status spk_set_plain(spk_handle h, int plain);
+
+/* Number of compute units, device name and measured-free info. */
+spk_status spk_device_info(spk_handle h, int32_t *num_cu, char *name, int32_t name_cap);
+
+/* ------------------------------------------------------- vector kernels -- */
+
+/* WAXPY (the vector update of Figure 1): w_i = alpha*x_i + y_i, one fused
+ * rounding.  x, y, w: device arrays of n elements of `dtype`.  w may be
+ * identical to x or y (element-wise update); any other overlap is
+ * SPK_ERR_ALIAS.  For SPK_F32, alpha is rounded to float first.  alpha == 0
+ * is not special-cased (0*Inf = NaN propagates). */
+spk_status spk_waxpy(spk_handle h, int32_t dtype, int64_t n, double alpha,
+                     const void *x, const void *y, void *w, spk_stream stream);
+
+/* AXPY: y_i <- alpha*x_i + y_i (WAXPY with w == y).  x may equal y. */
+spk_status spk_axpy(spk_handle h, int32_t dtype, int64_t n, double alpha,
+                    const void *x, void *y, spk_stream stream);
+
+/* Dot product d = sum_i x_i*y_i accumulated in FP64 and written to
+ * d_result[0] (device, one double, also for SPK_F32).  The reduction order
+ * is fixed for a given (n, variant), so repeated calls are bit-identical.
+ * Calls on one handle and one stream are serialised by the stream; calls on
+ * different streams use separate scratch. */
+spk_status spk_dot(spk_handle h, int32_t dtype, int64_t n, const void *x, const void *y,
+                   double *d_result, spk_stream stream);
+
+/* ----------------------------------------------------------------- SpMV -- */
+
+/* y = A*x for a borrowed CSR matrix (all arrays device).  x has A->ncols
+ * elements, y has A->nrows; both of A->dtype.  y must not overlap x
+ * (SPK_ERR_ALIAS).  Only O(1) facts are checked; row_ptr/col_idx contents
+ * are trusted (use spk_matrix_register(validate=1) to check them).  Formats
+ * that need derived data (SELL, ADAPTIVE) are only available on registered
+ * matrices, so this call uses the SCALAR/VECTOR families. */
+spk_status spk_spmv_csr(spk_handle h, const spk_csr *A, const void *x, void *y, spk_stream stream);
+
+/* Copies a CSR matrix into library-owned device memory and derives the
+ * metadata its formats need (row statistics, LDS row blocks, sliced ELL on
+ * first use).  `where`: 0 = the arrays of A are host memory, 1 = device
+ * memory.  validate != 0 checks row_ptr monotonicity, row_ptr[0] == 0,
+ * row_ptr[nrows] == nnz and 0 <= col_idx < ncols (SPK_ERR_CSR otherwise).
+ * The caller may free its arrays when this returns. */
+spk_status spk_matrix_register(spk_handle h, const spk_csr *A, int32_t where, int32_t validate,
+                               spk_matrix *out);
+
+spk_status spk_matrix_release(spk_handle h, spk_matrix A);
+
+/* Bytes of device memory held by a registered matrix (CSR plus derived
+ * formats built so far). */
+spk_status spk_matrix_bytes(spk_handle h, spk_matrix A, int64_t *bytes);
+
+/* y = A*x on a registered matrix, with the tuned variant of its shape class
+ * (or the default when none is recorded). */
+spk_status spk_spmv_mat(spk_handle h, spk_matrix A, const void *x, void *y, spk_stream stream);
+
+/* One Krylov-style step on a square registered matrix: y = A*x, then
+ * w_i = alpha*y_i + x_i from the rounded y_i, in one kernel.  w must not
+ * overlap x or y; y must not overlap x. */
+spk_status spk_spmv_waxpy(spk_handle h, spk_matrix A, double alpha, const void *x, void *y,
+                          void *w, spk_stream stream);
+
+/* ------------------------------------------------- variants and tuning -- */
+
+/* A problem for spk_run / spk_tune.  SPMV/SPMV_WAXPY use A (registered) and
+ * x, y (and w); WAXPY uses x, y, w; AXPY x, y; DOT x, y and d_result. */
+typedef struct {
+    int32_t op;          /* spk_op */
+    int32_t dtype;       /* vector ops; SpMV takes A's dtype */
+    int64_t n;           /* vector ops */
+    double alpha;
+    spk_matrix A;
+    const void *x;
+    void *y;
+    void *w;
+    double *d_result;
+} spk_problem;
+
+/* Runs `problem` with an explicit variant (NULL = the dispatcher's choice).
+ * Used by the tuner and by tests that exercise every compiled variant. */
+spk_status spk_run(spk_handle h, const spk_problem *problem, const spk_variant *variant,
+                   spk_stream stream);
+
+/* The variant space compiled into the library for an op and dtype:
+ * spk_variant_count gives its size, spk_variant_get the i-th point. */
+spk_status spk_variant_count(int32_t op, int32_t dtype, int32_t *count);
+spk_status spk_variant_get(int32_t op, int32_t dtype, int32_t index, spk_variant *out);
+
+/* The fixed "plain" variants, the analogue of the paper's unannotated
+ * -O3 baseline (Figure 1): one element per thread and 256 threads for the
+ * vector ops; for SpMV index 0 = one lane per row, 1 = one wavefront per
+ * row, both 256 threads, no unroll, no LDS, plain CSR. */
+spk_status spk_plain_variant(int32_t op, int32_t which, spk_variant *out);
+
+typedef struct {
+    int32_t reps;            /* timed repetitions per variant (0 -> 10) */
+    int32_t warmup;          /* untimed runs per variant (0 -> 2) */
+    int32_t flush;           /* 1: evict the last-level cache before each timed rep */
+    int32_t max_variants;    /* 0 = the whole pruned space */
+    double tau;              /* per-row tolerance factor (0 -> 1e-12 FP64, 1e-5 FP32) */
+    const double *ref_host;  /* optional host reference: y (SpMV), w (WAXPY/AXPY,
+                              * as doubles), d (DOT, one double); NULL = a run of
+                              * the plain variant is the reference (Section 2) */
+    const double *ref_scale; /* with ref_host: per-output tolerance scale
+                              * (SpMV: sum_k |a_ik x_k|; DOT: sum |x_i y_i|);
+                              * NULL = computed on the device */
+    int32_t record;          /* 1: store the winner in the handle's plan DB */
+    int32_t verbose;         /* 1: print one line per variant to stderr */
+} spk_tune_opts;
+
+typedef struct {
+    spk_variant best;
+    double best_us;          /* median time of the winner */
+    double plain_us;         /* median time of the better plain variant */
+    int32_t tried;           /* variants timed */
+    int32_t rejected;        /* variants whose output failed validation */
+    int32_t pruned;          /* variants skipped by the byte model */
+    char class_key[96];      /* plan DB key the winner is filed under */
+} spk_tune_report;
+
+/* The tuning loop of Section 2: for every variant of the (pruned) space run
+ * the problem, compare its output with the reference (per row
+ * |out - ref| <= tau*scale; NaN/Inf positions must match; WAXPY/AXPY within
+ * one ulp), discard it on mismatch, otherwise time it (median of reps,
+ * HIP events) and keep the fastest.  Work buffers y/w/d_result are
+ * overwritten.  Synchronises the handle's internal stream. */
+spk_status spk_tune(spk_handle h, const spk_problem *problem, const spk_tune_opts *opts,
+                    spk_tune_report *report);
+
+/* Shape class a problem is filed under in the plan DB (for inspection). */
+spk_status spk_class_key(spk_handle h, const spk_problem *problem, char *out, int32_t cap);
+
+/* Looks up / stores a plan DB entry directly. */
+spk_status spk_plan_get(spk_handle h, const char *class_key, spk_variant *out);
+spk_status spk_plan_put(spk_handle h, const char *class_key, const spk_variant *v);
+
+/* ------------------------------------------------------------- batching -- */
+
+/* Many independent square CSR instances stored back to back (instance i:
+ * row_ptr[rp_off[i] .. rp_off[i]+m[i]] with values local to the instance,
+ * entries col_idx/val[nz_off[i] .. nz_off[i]+nnz[i]) with local column
+ * indices, vectors x/y/w[vec_off[i] .. vec_off[i]+m[i])).  Size and offset
+ * arrays are host memory; row_ptr, col_idx and val are device memory;
+ * row_ptr_host (nullable) is a host copy of row_ptr used for planning. */
+typedef struct {
+    int64_t count;
+    int32_t dtype;
+    const int64_t *m, *nnz, *rp_off, *nz_off, *vec_off;   /* host */
+    const int32_t *row_ptr, *col_idx;                       /* device */
+    const void *val;                                        /* device */
+    const int32_t *row_ptr_host;                            /* host, nullable */
+} spk_batch_desc;
+
+typedef struct {
+    int32_t persistent;      /* 1 (default): one persistent launch with a tile
+                              * queue; 0: one workgroup per tile */
+    int32_t use_graph;       /* 1 (default): replay a captured hipGraph */
+    int32_t block;           /* threads per workgroup (0 -> 256) */
+    int32_t tile_nnz;        /* target entries per tile (0 -> 2048) */
+    int32_t waves_per_cu;    /* persistent residency (0 -> from occupancy) */
+} spk_batch_opts;
+
+/* Plans the batch: instances -> shape classes -> tiles, each class served by
+ * the variant recorded for it (see spk_batch_tune), tiles ordered largest
+ * first.  The descriptor arrays are copied; the device arrays are borrowed
+ * for the batch's lifetime. */
+spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *desc, const spk_batch_opts *opts,
+                          spk_batch *out);
+
+/* One step over every instance: y = A_i*x_i, w = alpha*y + x (w may be NULL
+ * for SpMV only), all instances in one launch.  With use_graph the launch is
+ * captured once per (x, y, w, alpha) and replayed. */
+spk_status spk_batch_run(spk_handle h, spk_batch b, double alpha, const void *x, void *y, void *w,
+                         spk_stream stream);
+
+/* Tunes the tile kernel per shape class on this batch (Section 2's search
+ * applied to each class separately), validating every candidate against
+ * the current plan's output, then re-plans the tiles. */
+spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x, void *y, void *w,
+                          const spk_tune_opts *opts, spk_tune_report *report);
+
+/* Number of tiles and classes and the algorithmic bytes of one step. */
+spk_status spk_batch_info(spk_handle h, spk_batch b, int64_t *tiles, int32_t *classes,
+                          int64_t *bytes);
+
+spk_status spk_batch_free(spk_handle h, spk_batch b);
+
+/* -------------------------------------------------------------- serving -- */
+
+typedef struct {
+    int32_t streams;          /* device streams used concurrently (0 -> 4) */
+    int32_t max_inflight;     /* request slots (0 -> 256) */
+    int32_t max_batch;        /* requests per launch (0 -> 64) */
+    int32_t mode;             /* 0 = continuous batching; 1 = FIFO, one request per
+                               * launch with the plain kernels (baseline) */
+    int64_t hbm_budget;       /* bytes for resident matrices + in-flight vectors
+                               * (0 -> 200 GB) */
+    double alpha;             /* step coefficient (w = alpha*y + x) */
+} spk_serve_opts;
+
+typedef struct {
+    int64_t submitted, completed, rejected;
+    int64_t batches;          /* launches issued */
+    int64_t uploads, evictions;
+    int64_t resident_bytes, peak_bytes;
+    double p50_us, p99_us, mean_us, max_us;   /* arrival -> result on host */
+    double wall_s;            /* first arrival -> last completion */
+    double bytes_moved;       /* algorithmic bytes of completed requests */
+} spk_serve_stats;
+
+/* Starts a serving loop on the handle's device (a scheduler thread). */
+spk_status spk_serve_create(spk_handle h, const spk_serve_opts *opts, spk_server *out);
+
+/* Adds a matrix to the server's pool.  A's arrays are host memory and are
+ * copied; the matrix is uploaded (made resident) when a request needs it
+ * and evicted, least recently used first, only while idle. */
+spk_status spk_serve_add_matrix(spk_server s, const spk_csr *A, int32_t *id);
+
+/* Submits one request: y = A_id*x, w = alpha*y + x.  x is host memory of
+ * ncols elements (copied at admission); y and w are host memory of nrows
+ * elements filled in before the request is reported complete.  The buffers
+ * stay borrowed until then.  *req receives the request id. */
+spk_status spk_serve_submit(spk_server s, int32_t mat_id, const void *x, void *y, void *w,
+                            int64_t *req);
+
+/* Completed request ids since the last poll (up to cap). */
+spk_status spk_serve_poll(spk_server s, int64_t *ids, int32_t cap, int32_t *n);
+
+/* Blocks until every submitted request has completed. */
+spk_status spk_serve_drain(spk_server s);
+
+/* Open-loop replay: submits request i at arrival_s[i] seconds after the
+ * call (by the library's own clock) and returns when all have completed. */
+spk_status spk_serve_replay(spk_server s, int64_t n, const double *arrival_s, const int32_t *mat_ids,
+                            const void *const *x, void *const *y, void *const *w);
+
+spk_status spk_serve_stats_get(spk_server s, spk_serve_stats *out);
+
+/* Per-request latency in microseconds, by request id (cap entries). */
+spk_status spk_serve_latencies(spk_server s, double *out_us, int64_t cap, int64_t *n);
+
+spk_status spk_serve_destroy(spk_server s);
+
+/* --------------------------------------------------------- measurement -- */
+
+/* STREAM-style probes on device arrays of n doubles: kind 0 = copy
+ * (c = a; b unused), 1 = triad (c = a + 3*b).  Used for the measured
+ * bandwidth roofline and to calibrate byte counters. */
+spk_status spk_stream_probe(spk_handle h, int32_t kind, int64_t n, const double *a, const double *b,
+                            double *c, spk_stream stream);
+
+/* Writes a library-owned 512 MiB buffer so the next kernel starts with a
+ * cold last-level cache. */
+spk_status spk_flush_cache(spk_handle h, spk_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPK_H */

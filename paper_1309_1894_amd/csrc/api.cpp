@@ -1,0 +1,1105 @@
+// api.cpp -- the C ABI of libspk: handles, argument checks, dispatch of
+// WAXPY/AXPY/dot and CSR SpMV variants, matrix registration, plan DB.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace spk {
+
+namespace {
+thread_local char g_err[1024] = "";
+}
+
+spk_status fail(spk_status s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+spk_status hip_fail(hipError_t e, const char *what)
+{
+    snprintf(g_err, sizeof g_err, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return SPK_ERR_OOM;
+    return SPK_ERR_HIP;
+}
+
+const char *dtype_name(int dtype) { return dtype == SPK_F64 ? "f64" : "f32"; }
+
+double now_seconds()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+int64_t spmv_bytes(int64_t m, int64_t n, int64_t nnz, int dtype, bool fused)
+{
+    const int64_t s = (int64_t)dtype_size(dtype);
+    int64_t b = nnz * (s + 4) + 4 * (m + 1) + n * s + m * s;
+    if (fused) b += m * s;  // w
+    return b;
+}
+
+// ------------------------------------------------------------ variants --
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+const VecEntry *find_vec_entry(int op, int dtype, const spk_variant &v)
+{
+    int n = 0;
+    const VecEntry *t = (op == SPK_OP_DOT) ? dot_table(&n) : waxpy_table(&n);
+    for (int i = 0; i < n; ++i)
+        if (t[i].block == v.block && t[i].vec == v.vec && t[i].unroll == v.unroll && t[i].fn[dtype]) return &t[i];
+    return nullptr;
+}
+
+const SpmvEntry *find_spmv_entry(const spk_variant &v)
+{
+    int n = 0;
+    const SpmvEntry *t = spmv_table(&n);
+    for (int i = 0; i < n; ++i) {
+        const SpmvEntry &e = t[i];
+        if (e.format != v.format || e.block != v.block || e.unroll != v.unroll) continue;
+        if (e.format == SPK_FMT_VECTOR && (e.group != v.group || e.lds != v.lds)) continue;
+        if (e.format == SPK_FMT_SELL && e.group != v.group) continue;
+        if (e.format == SPK_FMT_ADAPTIVE && e.lds != v.lds) continue;
+        return &e;
+    }
+    return nullptr;
+}
+
+spk_status check_variant(int op, int dtype, const spk_variant &v)
+{
+    if (op == SPK_OP_WAXPY || op == SPK_OP_AXPY || op == SPK_OP_DOT) {
+        if (!find_vec_entry(op, dtype, v))
+            return fail(SPK_ERR_NOT_FOUND, "no compiled %s variant block=%d vec=%d unroll=%d for %s",
+                        op == SPK_OP_DOT ? "dot" : "waxpy", v.block, v.vec, v.unroll, dtype_name(dtype));
+        if (v.grid < 0 || v.grid > 1024) return fail(SPK_ERR_ARG, "grid %d out of range", v.grid);
+        return SPK_OK;
+    }
+    if (op == SPK_OP_SPMV || op == SPK_OP_SPMV_WAXPY) {
+        if (!find_spmv_entry(v))
+            return fail(SPK_ERR_NOT_FOUND, "no compiled SpMV variant format=%d block=%d group=%d unroll=%d lds=%d",
+                        v.format, v.block, v.group, v.unroll, v.lds);
+        if (!(v.streams == 1 || v.streams == 2 || v.streams == 4))
+            return fail(SPK_ERR_ARG, "streams must be 1, 2 or 4 (got %d)", v.streams);
+        return SPK_OK;
+    }
+    return fail(SPK_ERR_ARG, "unknown op %d", op);
+}
+
+spk_variant plain_variant(int op, int which)
+{
+    spk_variant v{};
+    if (op == SPK_OP_SPMV || op == SPK_OP_SPMV_WAXPY) {
+        v.format = which == 0 ? SPK_FMT_SCALAR : SPK_FMT_VECTOR;
+        v.block = 256;
+        v.group = which == 0 ? 1 : 64;
+        v.unroll = 1;
+        v.streams = 1;
+    } else {
+        v.block = 256;
+        v.vec = 1;
+        v.unroll = 1;
+        v.grid = 0;
+    }
+    return v;
+}
+
+static int pow2_ceil(double x)
+{
+    int p = 1;
+    while (p < x && p < (1 << 30)) p <<= 1;
+    return p;
+}
+
+spk_variant default_variant(spk_handle h, const spk_problem &p, const spk_csr *csr)
+{
+    (void)h;
+    spk_variant v{};
+    switch (p.op) {
+    case SPK_OP_WAXPY:
+    case SPK_OP_AXPY:
+        v.block = 256;
+        v.vec = p.dtype == SPK_F64 ? 2 : 4;
+        v.unroll = 2;
+        v.grid = 0;
+        return v;
+    case SPK_OP_DOT:
+        v.block = 256;
+        v.vec = p.dtype == SPK_F64 ? 2 : 4;
+        v.unroll = 4;
+        v.grid = 8;
+        return v;
+    default:
+        break;
+    }
+    v.streams = 1;
+    v.unroll = 1;
+    if (p.A) {
+        v.format = SPK_FMT_ADAPTIVE;
+        v.block = 256;
+        v.group = 1;
+        v.lds = 2048;
+        return v;
+    }
+    const double mean = csr && csr->nrows > 0 ? (double)csr->nnz / (double)csr->nrows : 1.0;
+    v.format = SPK_FMT_VECTOR;
+    v.block = 256;
+    v.group = std::min(64, std::max(2, pow2_ceil(mean)));
+    return v;
+}
+
+static int ilog2_ceil(double x)
+{
+    int k = 0;
+    while ((double)(1ll << k) < x && k < 62) ++k;
+    return k;
+}
+
+std::string class_key(const spk_problem &p, const spk_csr *csr)
+{
+    char buf[128];
+    switch (p.op) {
+    case SPK_OP_WAXPY:
+    case SPK_OP_AXPY:
+    case SPK_OP_DOT: {
+        const char *nm = p.op == SPK_OP_WAXPY ? "waxpy" : p.op == SPK_OP_AXPY ? "axpy" : "dot";
+        snprintf(buf, sizeof buf, "%s:%s:n%d", nm, dtype_name(p.dtype), ilog2_ceil((double)std::max<int64_t>(1, p.n)));
+        return buf;
+    }
+    default:
+        break;
+    }
+    const char *nm = p.op == SPK_OP_SPMV ? "spmv" : "spmv_waxpy";
+    if (p.A) {
+        const spk_mat *A = p.A;
+        const double mean = std::max(1.0, A->mean_len);
+        const double ratio = (double)std::max<int64_t>(1, A->max_len) / mean;
+        const int skew = ratio <= 2.0 ? 0 : ratio <= 16.0 ? 1 : 2;
+        snprintf(buf, sizeof buf, "%s:%s:m%d:l%d:s%d", nm, dtype_name(A->dtype),
+                 ilog2_ceil((double)std::max<int64_t>(1, A->nrows)), (int)std::lround(std::log2(mean)), skew);
+        return buf;
+    }
+    const double mean = csr && csr->nrows > 0 ? std::max(1.0, (double)csr->nnz / (double)csr->nrows) : 1.0;
+    snprintf(buf, sizeof buf, "spmv_csr:%s:m%d:l%d", csr ? dtype_name(csr->dtype) : "f64",
+             ilog2_ceil((double)std::max<int64_t>(1, csr ? csr->nrows : 1)), (int)std::lround(std::log2(mean)));
+    return buf;
+}
+
+// ------------------------------------------------------- vector kernels --
+
+spk_status run_waxpy(spk_handle h, int dtype, int64_t n, double alpha, const void *x, const void *y, void *w,
+                     const spk_variant &v, hipStream_t s)
+{
+    if (n == 0) return SPK_OK;
+    spk_variant vv = v;
+    const size_t bytes = (size_t)vv.vec * dtype_size(dtype);
+    // vector accesses need every pointer aligned to the access size
+    if (vv.vec > 1 && (((uintptr_t)x | (uintptr_t)y | (uintptr_t)w) % bytes) != 0) vv.vec = 1;
+    const VecEntry *e = find_vec_entry(SPK_OP_WAXPY, dtype, vv);
+    if (!e) return fail(SPK_ERR_NOT_FOUND, "waxpy variant not compiled");
+    VecLaunch L{};
+    L.n = n;
+    L.alpha = dtype == SPK_F32 ? (double)(float)alpha : alpha;
+    L.x = x;
+    L.y = y;
+    L.w = w;
+    const int64_t per = vec_per_block(*e);
+    int64_t g = (n + per - 1) / per;
+    if (vv.grid > 0) g = std::min<int64_t>(g, (int64_t)vv.grid * h->num_cu);
+    L.grid = std::max<int64_t>(1, g);
+    SPK_HIP(e->fn[dtype](L, s));
+    return SPK_OK;
+}
+
+static spk_status dot_scratch(spk_handle h, hipStream_t s, int64_t need, DotScratch **out)
+{
+    std::lock_guard<std::mutex> lk(h->mu);
+    DotScratch &d = h->dot[s];
+    if (d.cap < need) {
+        if (d.partial) {
+            // the stream may still use the old buffers
+            SPK_HIP(hipStreamSynchronize(s));
+            SPK_HIP(hipFree(d.partial));
+            SPK_HIP(hipFree(d.ticket));
+            d.partial = nullptr;
+            d.ticket = nullptr;
+        }
+        const int64_t cap = std::max<int64_t>(need, 4096);
+        SPK_HIP(hipMalloc(&d.partial, (size_t)cap * sizeof(double)));
+        SPK_HIP(hipMalloc(&d.ticket, 256));
+        SPK_HIP(hipMemsetAsync(d.ticket, 0, 256, s));
+        d.cap = cap;
+    }
+    *out = &d;
+    return SPK_OK;
+}
+
+spk_status run_dot(spk_handle h, int dtype, int64_t n, const void *x, const void *y, double *out,
+                   const spk_variant &v, hipStream_t s)
+{
+    spk_variant vv = v;
+    const size_t bytes = (size_t)vv.vec * dtype_size(dtype);
+    if (vv.vec > 1 && (((uintptr_t)x | (uintptr_t)y) % bytes) != 0) vv.vec = 1;
+    const VecEntry *e = find_vec_entry(SPK_OP_DOT, dtype, vv);
+    if (!e) return fail(SPK_ERR_NOT_FOUND, "dot variant not compiled");
+    const int64_t per = vec_per_block(*e);
+    int64_t g = (n + per - 1) / per;
+    if (vv.grid > 0) g = std::min<int64_t>(g, (int64_t)vv.grid * h->num_cu);
+    g = std::max<int64_t>(1, g);
+    DotScratch *d = nullptr;
+    SPK_TRY(dot_scratch(h, s, g, &d));
+    VecLaunch L{};
+    L.n = n;
+    L.x = x;
+    L.y = y;
+    L.partial = d->partial;
+    L.ticket = d->ticket;
+    L.out = out;
+    L.grid = g;
+    SPK_HIP(e->fn[dtype](L, s));
+    return SPK_OK;
+}
+
+// ----------------------------------------------------------------- SpMV --
+
+// Row boundaries splitting [0, m) into `parts` pieces of similar nnz.
+static std::vector<int64_t> split_rows(const spk_mat *A, int64_t m, int parts, int align)
+{
+    std::vector<int64_t> cut(parts + 1, 0);
+    cut[parts] = m;
+    for (int i = 1; i < parts; ++i) {
+        int64_t r;
+        if (A && !A->rp_host.empty()) {
+            const int64_t target = (int64_t)((double)A->nnz * i / parts);
+            r = std::lower_bound(A->rp_host.begin(), A->rp_host.end(), (int32_t)target) - A->rp_host.begin();
+        } else {
+            r = m * i / parts;
+        }
+        r = (r / align) * align;
+        cut[i] = std::max(cut[i - 1], std::min(r, m));
+    }
+    return cut;
+}
+
+template <typename T>
+static void fill_args(SpmvArgs<T> &a, const SpmvProblem &p, const int32_t *rp, const int32_t *ci, const void *val)
+{
+    a.rp = rp;
+    a.ci = ci;
+    a.val = (const T *)val;
+    a.x = (const T *)p.x;
+    a.y = (T *)p.y;
+    a.w = (T *)p.w;
+    a.alpha = (T)p.alpha;
+}
+
+spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hipStream_t s)
+{
+    const int64_t m = p.mat ? p.mat->nrows : p.csr->nrows;
+    const int dtype = p.mat ? p.mat->dtype : p.csr->dtype;
+    if (m == 0) return SPK_OK;
+    const SpmvEntry *e = find_spmv_entry(v);
+    if (!e) return fail(SPK_ERR_NOT_FOUND, "SpMV variant not compiled");
+    if (!p.mat && (v.format == SPK_FMT_SELL || v.format == SPK_FMT_ADAPTIVE))
+        return fail(SPK_ERR_ARG, "format %d needs a registered matrix", v.format);
+    const int32_t *rp = p.mat ? p.mat->rp : p.csr->row_ptr;
+    const int32_t *ci = p.mat ? p.mat->ci : p.csr->col_idx;
+    const void *val = p.mat ? p.mat->val : p.csr->val;
+    SpmvFn fn = e->fn[dtype][p.fused ? 1 : 0];
+
+    SellData *sd = nullptr;
+    BlockData *bd = nullptr;
+    if (v.format == SPK_FMT_SELL) SPK_TRY(get_sell(h, p.mat, v.group, &sd));
+    if (v.format == SPK_FMT_ADAPTIVE) SPK_TRY(get_blocks(h, p.mat, v.block, v.lds, &bd));
+
+    const int parts = std::max(1, v.streams);
+    // launch pieces: rows [cut[i], cut[i+1]) or row blocks for ADAPTIVE
+    std::vector<int64_t> cut;
+    if (v.format == SPK_FMT_ADAPTIVE) {
+        cut.assign(parts + 1, 0);
+        for (int i = 0; i <= parts; ++i) cut[i] = (int64_t)bd->nblk * i / parts;
+    } else {
+        cut = split_rows(p.mat, m, parts, v.format == SPK_FMT_SELL ? v.group : 1);
+    }
+
+    auto launch_piece = [&](int i, hipStream_t st) -> spk_status {
+        const int64_t lo = cut[i], hi = cut[i + 1];
+        if (hi <= lo) return SPK_OK;
+        union {
+            SpmvArgs<float> f;
+            SpmvArgs<double> d;
+        } args;
+        memset(&args, 0, sizeof args);
+        dim3 grid;
+        auto setup = [&](auto &a) {
+            using A = std::remove_reference_t<decltype(a)>;
+            using T = std::remove_pointer_t<decltype(A::val)>;
+            fill_args<std::remove_const_t<T>>(a, p, rp, ci, val);
+            if (v.format == SPK_FMT_ADAPTIVE) {
+                a.blocks = bd->blk;
+                a.blk0 = (int32_t)lo;
+                a.nblk = (int32_t)(hi - lo);
+                grid = dim3((unsigned)(hi - lo));
+            } else {
+                a.row0 = (int32_t)lo;
+                a.m = (int32_t)(hi - lo);
+                int64_t rows_per_block = v.block;
+                if (v.format == SPK_FMT_VECTOR) rows_per_block = v.block / v.group;
+                grid = dim3((unsigned)((hi - lo + rows_per_block - 1) / rows_per_block));
+                if (sd) {
+                    a.sell_ptr = sd->ptr;
+                    a.sell_len = sd->len;
+                    a.sell_ci = sd->ci;
+                    a.sell_val = (decltype(a.sell_val))sd->val;
+                }
+            }
+        };
+        if (dtype == SPK_F64) setup(args.d); else setup(args.f);
+        SPK_HIP(fn(dtype == SPK_F64 ? (const void *)&args.d : (const void *)&args.f, grid, st));
+        return SPK_OK;
+    };
+
+    if (parts == 1) return launch_piece(0, s);
+    // fork onto the handle's streams and join back on the caller's stream
+    SPK_HIP(hipEventRecord(h->ev_fork, s));
+    for (int i = 0; i < parts; ++i) {
+        SPK_HIP(hipStreamWaitEvent(h->sub[i], h->ev_fork, 0));
+        SPK_TRY(launch_piece(i, h->sub[i]));
+        SPK_HIP(hipEventRecord(h->ev_join[i], h->sub[i]));
+        SPK_HIP(hipStreamWaitEvent(s, h->ev_join[i], 0));
+    }
+    return SPK_OK;
+}
+
+// ------------------------------------------------------ derived formats --
+
+int64_t sell_padded_entries(const spk_mat *A, int C)
+{
+    int64_t total = 0;
+    for (int64_t s0 = 0; s0 < A->nrows; s0 += C) {
+        int64_t wmax = 0;
+        const int64_t s1 = std::min<int64_t>(A->nrows, s0 + C);
+        for (int64_t r = s0; r < s1; ++r) wmax = std::max<int64_t>(wmax, A->rp_host[r + 1] - A->rp_host[r]);
+        total += wmax * C;
+    }
+    return total;
+}
+
+spk_status get_sell(spk_handle h, spk_mat *A, int C, SellData **out)
+{
+    std::lock_guard<std::mutex> lk(h->mu);
+    auto it = A->sell.find(C);
+    if (it != A->sell.end()) {
+        *out = &it->second;
+        return SPK_OK;
+    }
+    SellData d;
+    d.C = C;
+    d.nslices = (A->nrows + C - 1) / C;
+    std::vector<int64_t> ptr(d.nslices + 1, 0);
+    for (int64_t s = 0; s < d.nslices; ++s) {
+        int64_t wmax = 0;
+        const int64_t r1 = std::min<int64_t>(A->nrows, (s + 1) * C);
+        for (int64_t r = s * C; r < r1; ++r) wmax = std::max<int64_t>(wmax, A->rp_host[r + 1] - A->rp_host[r]);
+        ptr[s + 1] = ptr[s] + wmax * C;
+    }
+    d.padded = ptr[d.nslices];
+    const size_t vs = dtype_size(A->dtype);
+    SPK_HIP(hipMalloc(&d.ptr, sizeof(int64_t) * (d.nslices + 1)));
+    SPK_HIP(hipMalloc(&d.len, sizeof(int32_t) * std::max<int64_t>(1, A->nrows)));
+    SPK_HIP(hipMalloc(&d.ci, sizeof(int32_t) * std::max<int64_t>(1, d.padded)));
+    SPK_HIP(hipMalloc(&d.val, vs * std::max<int64_t>(1, d.padded)));
+    // everything on the handle's work stream, in order, then wait
+    SPK_HIP(hipMemcpyAsync(d.ptr, ptr.data(), sizeof(int64_t) * (d.nslices + 1), hipMemcpyHostToDevice, h->work));
+    SPK_HIP(hipMemsetAsync(d.ci, 0, sizeof(int32_t) * std::max<int64_t>(1, d.padded), h->work));
+    SPK_HIP(hipMemsetAsync(d.val, 0, vs * std::max<int64_t>(1, d.padded), h->work));
+    SPK_HIP(launch_csr_to_sell(A->dtype, (int32_t)A->nrows, C, A->rp, A->ci, A->val, d.ptr, d.len, d.ci, d.val,
+                               h->work));
+    SPK_HIP(hipStreamSynchronize(h->work));
+    d.bytes = (int64_t)(sizeof(int64_t) * (d.nslices + 1) + 4 * A->nrows + (4 + vs) * d.padded);
+    A->bytes += d.bytes;
+    auto res = A->sell.emplace(C, d);
+    *out = &res.first->second;
+    return SPK_OK;
+}
+
+// Row blocks for the LDS-staged kernel: runs of short rows whose entries
+// fit `tile` (at most 2*block rows), up to block/64 medium rows handled one
+// wavefront each, and single long rows handled by a whole workgroup.
+static void make_blocks(const std::vector<int32_t> &rp, int64_t m, int block, int tile, std::vector<uint32_t> &out)
+{
+    const int64_t kShort = std::min<int64_t>(96, tile);
+    const int64_t kLong = (int64_t)block * 8;
+    const int64_t row_cap = 2 * (int64_t)block;
+    const int64_t waves = block / 64;
+    out.clear();
+    int64_t r = 0;
+    while (r < m) {
+        const int64_t len = rp[r + 1] - rp[r];
+        if (len > kLong) {
+            out.push_back((uint32_t)r | (kBlkBlock << 30));
+            ++r;
+        } else if (len > kShort) {
+            out.push_back((uint32_t)r | (kBlkWave << 30));
+            int64_t c = 0;
+            while (r < m && c < waves) {
+                const int64_t l = rp[r + 1] - rp[r];
+                if (l <= kShort || l > kLong) break;
+                ++r;
+                ++c;
+            }
+        } else {
+            out.push_back((uint32_t)r | (kBlkStream << 30));
+            int64_t nz = 0, c = 0;
+            while (r < m && c < row_cap) {
+                const int64_t l = rp[r + 1] - rp[r];
+                if (l > kShort || nz + l > tile) break;
+                nz += l;
+                ++r;
+                ++c;
+            }
+        }
+    }
+    out.push_back((uint32_t)m);
+}
+
+spk_status get_blocks(spk_handle h, spk_mat *A, int block, int tile, BlockData **out)
+{
+    std::lock_guard<std::mutex> lk(h->mu);
+    const auto key = std::make_pair(block, tile);
+    auto it = A->blocks.find(key);
+    if (it != A->blocks.end()) {
+        *out = &it->second;
+        return SPK_OK;
+    }
+    BlockData d;
+    make_blocks(A->rp_host, A->nrows, block, tile, d.host);
+    d.nblk = (int32_t)d.host.size() - 1;
+    SPK_HIP(hipMalloc(&d.blk, sizeof(uint32_t) * d.host.size()));
+    SPK_HIP(hipMemcpyAsync(d.blk, d.host.data(), sizeof(uint32_t) * d.host.size(), hipMemcpyHostToDevice, h->work));
+    SPK_HIP(hipStreamSynchronize(h->work));
+    d.bytes = (int64_t)(sizeof(uint32_t) * d.host.size());
+    A->bytes += d.bytes;
+    auto res = A->blocks.emplace(key, std::move(d));
+    *out = &res.first->second;
+    return SPK_OK;
+}
+
+// --------------------------------------------------------------- plan DB --
+
+void db_load(spk_handle h)
+{
+    if (h->db_path.empty()) return;
+    std::ifstream f(h->db_path);
+    std::string line;
+    while (std::getline(f, line)) {
+        char key[128] = {0}, arch[64] = {0}, build[64] = {0};
+        spk_variant v{};
+        double us = 0;
+        const int got = sscanf(line.c_str(),
+                               "{\"key\": \"%127[^\"]\", \"arch\": \"%63[^\"]\", \"build\": \"%63[^\"]\", "
+                               "\"v\": [%d, %d, %d, %d, %d, %d, %d, %d], \"us\": %lf}",
+                               key, arch, build, &v.format, &v.block, &v.group, &v.unroll, &v.vec, &v.grid,
+                               &v.streams, &v.lds, &us);
+        if (got != 12) continue;
+        if (strcmp(arch, h->arch) != 0 || strcmp(build, SPK_BUILD_ID) != 0) continue;
+        h->plans[key] = v;
+    }
+}
+
+void db_append(spk_handle h, const std::string &key, const spk_variant &v, double us)
+{
+    if (h->db_path.empty()) return;
+    FILE *f = fopen(h->db_path.c_str(), "a");
+    if (!f) return;
+    fprintf(f,
+            "{\"key\": \"%s\", \"arch\": \"%s\", \"build\": \"%s\", \"v\": [%d, %d, %d, %d, %d, %d, %d, %d], "
+            "\"us\": %.3f}\n",
+            key.c_str(), h->arch, SPK_BUILD_ID, v.format, v.block, v.group, v.unroll, v.vec, v.grid, v.streams, v.lds,
+            us);
+    fclose(f);
+}
+
+}  // namespace spk
+
+using namespace spk;
+
+// ================================================================= C ABI ==
+
+extern "C" {
+
+int spk_abi_version(void) { return SPK_ABI_VERSION; }
+
+const char *spk_status_str(spk_status s)
+{
+    switch (s) {
+    case SPK_OK: return "SPK_OK";
+    case SPK_ERR_NULL: return "SPK_ERR_NULL";
+    case SPK_ERR_SHAPE: return "SPK_ERR_SHAPE";
+    case SPK_ERR_DTYPE: return "SPK_ERR_DTYPE";
+    case SPK_ERR_ALIAS: return "SPK_ERR_ALIAS";
+    case SPK_ERR_CSR: return "SPK_ERR_CSR";
+    case SPK_ERR_OOM: return "SPK_ERR_OOM";
+    case SPK_ERR_BUDGET: return "SPK_ERR_BUDGET";
+    case SPK_ERR_HIP: return "SPK_ERR_HIP";
+    case SPK_ERR_VALIDATION: return "SPK_ERR_VALIDATION";
+    case SPK_ERR_NOT_FOUND: return "SPK_ERR_NOT_FOUND";
+    case SPK_ERR_ARG: return "SPK_ERR_ARG";
+    case SPK_ERR_STATE: return "SPK_ERR_STATE";
+    }
+    return "SPK_ERR_UNKNOWN";
+}
+
+const char *spk_last_error(void) { return g_err; }
+
+spk_status spk_create(int device, const char *db_path, spk_handle *out)
+{
+    if (!out) return fail(SPK_ERR_NULL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    SPK_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(SPK_ERR_ARG, "device %d not present (%d devices)", device, ndev);
+    spk_ctx *h = new spk_ctx();
+    h->device = device;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    hipError_t e = hipSetDevice(device);
+    hipDeviceProp_t prop;
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipGetDeviceProperties");
+    }
+    h->num_cu = prop.multiProcessorCount;
+    snprintf(h->name, sizeof h->name, "%s", prop.name);
+    snprintf(h->arch, sizeof h->arch, "%s", prop.gcnArchName);
+    char *colon = strchr(h->arch, ':');
+    if (colon) *colon = 0;
+    const char *plain = getenv("SPK_PLAIN");
+    h->plain = plain && plain[0] == '1';
+    if (db_path && db_path[0]) h->db_path = db_path;
+    else if (getenv("SPK_DB_PATH")) h->db_path = getenv("SPK_DB_PATH");
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&h->sub[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->work, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&h->ev_join[i], hipEventDisableTiming);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        spk_status s = hip_fail(e, "stream/event creation");
+        delete h;
+        return s;
+    }
+    db_load(h);
+    *out = h;
+    return SPK_OK;
+}
+
+static void free_mat(spk_mat *A)
+{
+    (void)hipFree(A->rp);
+    (void)hipFree(A->ci);
+    (void)hipFree(A->val);
+    for (auto &kv : A->sell) {
+        (void)hipFree(kv.second.ptr);
+        (void)hipFree(kv.second.len);
+        (void)hipFree(kv.second.ci);
+        (void)hipFree(kv.second.val);
+    }
+    for (auto &kv : A->blocks) hipFree(kv.second.blk);
+    delete A;
+}
+
+spk_status spk_destroy(spk_handle h)
+{
+    if (!h) return fail(SPK_ERR_NULL, "handle is NULL");
+    DeviceGuard g(h);
+    (void)hipDeviceSynchronize();
+    for (spk_mat *A : h->mats) free_mat(A);
+    for (auto &kv : h->dot) {
+        (void)hipFree(kv.second.partial);
+        (void)hipFree(kv.second.ticket);
+    }
+    if (h->flush_buf) (void)hipFree(h->flush_buf);
+    for (int i = 0; i < 4; ++i) {
+        if (h->sub[i]) (void)hipStreamDestroy(h->sub[i]);
+        if (h->ev_join[i]) (void)hipEventDestroy(h->ev_join[i]);
+    }
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->work) (void)hipStreamDestroy(h->work);
+    delete h;
+    return SPK_OK;
+}
+
+spk_status spk_check(spk_handle h, spk_stream stream)
+{
+    if (!h) return fail(SPK_ERR_NULL, "handle is NULL");
+    DeviceGuard g(h);
+    SPK_HIP(hipStreamSynchronize((hipStream_t)stream));
+    SPK_HIP(hipGetLastError());
+    return SPK_OK;
+}
+
+spk_status spk_set_plain(spk_handle h, int plain)
+{
+    if (!h) return fail(SPK_ERR_NULL, "handle is NULL");
+    h->plain = plain != 0;
+    return SPK_OK;
+}
+
+spk_status spk_device_info(spk_handle h, int32_t *num_cu, char *name, int32_t name_cap)
+{
+    if (!h) return fail(SPK_ERR_NULL, "handle is NULL");
+    if (num_cu) *num_cu = h->num_cu;
+    if (name && name_cap > 0) snprintf(name, (size_t)name_cap, "%s (%s)", h->name, h->arch);
+    return SPK_OK;
+}
+
+// ----------------------------------------------------------- vector ops --
+
+static spk_status resolve(spk_handle h, const spk_problem &p, const spk_csr *csr, spk_variant *v)
+{
+    if (h->plain) {
+        *v = plain_variant(p.op, 0);
+        if ((p.op == SPK_OP_SPMV || p.op == SPK_OP_SPMV_WAXPY) && csr && csr->nrows > 0 &&
+            (double)csr->nnz / (double)csr->nrows > 8.0)
+            *v = plain_variant(p.op, 1);
+        if ((p.op == SPK_OP_SPMV || p.op == SPK_OP_SPMV_WAXPY) && p.A && p.A->mean_len > 8.0)
+            *v = plain_variant(p.op, 1);
+        return SPK_OK;
+    }
+    const std::string key = class_key(p, csr);
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        auto it = h->plans.find(key);
+        if (it != h->plans.end()) {
+            *v = it->second;
+            return SPK_OK;
+        }
+    }
+    *v = default_variant(h, p, csr);
+    return SPK_OK;
+}
+
+spk_status spk_waxpy(spk_handle h, int32_t dtype, int64_t n, double alpha, const void *x, const void *y, void *w,
+                     spk_stream stream)
+{
+    if (!h) return fail(SPK_ERR_NULL, "handle is NULL");
+    if (!dtype_ok(dtype)) return fail(SPK_ERR_DTYPE, "bad dtype %d", dtype);
+    if (n < 0) return fail(SPK_ERR_SHAPE, "n = %lld < 0", (long long)n);
+    if (n == 0) return SPK_OK;
+    if (!x || !y || !w) return fail(SPK_ERR_NULL, "x, y and w must be non-NULL");
+    const size_t nb = (size_t)n * dtype_size(dtype);
+    if ((w != x && overlaps(w, nb, x, nb)) || (w != y && overlaps(w, nb, y, nb)))
+        return fail(SPK_ERR_ALIAS, "w partially overlaps x or y");
+    spk_problem p{};
+    p.op = SPK_OP_WAXPY;
+    p.dtype = dtype;
+    p.n = n;
+    spk_variant v;
+    SPK_TRY(resolve(h, p, nullptr, &v));
+    DeviceGuard g(h);
+    return run_waxpy(h, dtype, n, alpha, x, y, w, v, (hipStream_t)stream);
+}
+
+spk_status spk_axpy(spk_handle h, int32_t dtype, int64_t n, double alpha, const void *x, void *y, spk_stream stream)
+{
+    if (!h) return fail(SPK_ERR_NULL, "handle is NULL");
+    if (!dtype_ok(dtype)) return fail(SPK_ERR_DTYPE, "bad dtype %d", dtype);
+    if (n < 0) return fail(SPK_ERR_SHAPE, "n = %lld < 0", (long long)n);
+    if (n == 0) return SPK_OK;
+    if (!x || !y) return fail(SPK_ERR_NULL, "x and y must be non-NULL");
+    const size_t nb = (size_t)n * dtype_size(dtype);
+    if (x != y && overlaps(x, nb, y, nb)) return fail(SPK_ERR_ALIAS, "y partially overlaps x");
+    spk_problem p{};
+    p.op = SPK_OP_AXPY;
+    p.dtype = dtype;
+    p.n = n;
+    spk_variant v;
+    SPK_TRY(resolve(h, p, nullptr, &v));
+    DeviceGuard g(h);
+    return run_waxpy(h, dtype, n, alpha, x, y, y, v, (hipStream_t)stream);
+}
+
+spk_status spk_dot(spk_handle h, int32_t dtype, int64_t n, const void *x, const void *y, double *d_result,
+                   spk_stream stream)
+{
+    if (!h) return fail(SPK_ERR_NULL, "handle is NULL");
+    if (!dtype_ok(dtype)) return fail(SPK_ERR_DTYPE, "bad dtype %d", dtype);
+    if (n < 0) return fail(SPK_ERR_SHAPE, "n = %lld < 0", (long long)n);
+    if (!d_result) return fail(SPK_ERR_NULL, "d_result is NULL");
+    if (n > 0 && (!x || !y)) return fail(SPK_ERR_NULL, "x and y must be non-NULL");
+    const size_t nb = (size_t)n * dtype_size(dtype);
+    if (overlaps(d_result, 8, x, nb) || overlaps(d_result, 8, y, nb))
+        return fail(SPK_ERR_ALIAS, "d_result overlaps x or y");
+    spk_problem p{};
+    p.op = SPK_OP_DOT;
+    p.dtype = dtype;
+    p.n = n;
+    spk_variant v;
+    SPK_TRY(resolve(h, p, nullptr, &v));
+    DeviceGuard g(h);
+    return run_dot(h, dtype, n, x, y, d_result, v, (hipStream_t)stream);
+}
+
+// ----------------------------------------------------------------- SpMV --
+
+static spk_status check_csr_view(const spk_csr *A)
+{
+    if (!A) return fail(SPK_ERR_NULL, "A is NULL");
+    if (!dtype_ok(A->dtype)) return fail(SPK_ERR_DTYPE, "bad dtype %d", A->dtype);
+    if (A->nrows < 0 || A->ncols < 0 || A->nnz < 0) return fail(SPK_ERR_SHAPE, "negative size");
+    if (A->nnz >= (1ll << 31)) return fail(SPK_ERR_SHAPE, "nnz must be < 2^31 (int32 indices)");
+    if (A->nrows >= (1ll << 30) || A->ncols >= (1ll << 31)) return fail(SPK_ERR_SHAPE, "matrix too large");
+    if (A->nrows > 0 && !A->row_ptr) return fail(SPK_ERR_NULL, "row_ptr is NULL");
+    if (A->nnz > 0 && (!A->col_idx || !A->val)) return fail(SPK_ERR_NULL, "col_idx/val are NULL");
+    if (A->nnz > 0 && A->ncols == 0) return fail(SPK_ERR_SHAPE, "entries in a matrix with no columns");
+    return SPK_OK;
+}
+
+spk_status spk_spmv_csr(spk_handle h, const spk_csr *A, const void *x, void *y, spk_stream stream)
+{
+    if (!h) return fail(SPK_ERR_NULL, "handle is NULL");
+    SPK_TRY(check_csr_view(A));
+    if (A->nrows == 0) return SPK_OK;
+    if (!y || (A->ncols > 0 && !x)) return fail(SPK_ERR_NULL, "x/y are NULL");
+    const size_t s = dtype_size(A->dtype);
+    if (overlaps(x, (size_t)A->ncols * s, y, (size_t)A->nrows * s)) return fail(SPK_ERR_ALIAS, "y overlaps x");
+    spk_problem p{};
+    p.op = SPK_OP_SPMV;
+    p.dtype = A->dtype;
+    spk_variant v;
+    SPK_TRY(resolve(h, p, A, &v));
+    if (v.format == SPK_FMT_SELL || v.format == SPK_FMT_ADAPTIVE) v = default_variant(h, p, A);
+    SpmvProblem q;
+    q.csr = A;
+    q.x = x;
+    q.y = y;
+    DeviceGuard g(h);
+    return run_spmv(h, q, v, (hipStream_t)stream);
+}
+
+spk_status spk_matrix_register(spk_handle h, const spk_csr *A, int32_t where, int32_t validate, spk_matrix *out)
+{
+    if (!h || !out) return fail(SPK_ERR_NULL, "handle/out is NULL");
+    *out = nullptr;
+    SPK_TRY(check_csr_view(A));
+    if (where != 0 && where != 1) return fail(SPK_ERR_ARG, "where must be 0 (host) or 1 (device)");
+    DeviceGuard g(h);
+    const hipMemcpyKind kind = where == 0 ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    std::vector<int32_t> rp((size_t)A->nrows + 1, 0);
+    if (A->nrows > 0) {
+        if (where == 0) memcpy(rp.data(), A->row_ptr, sizeof(int32_t) * rp.size());
+        else {
+            SPK_HIP(hipDeviceSynchronize());  // the caller's pending writes to its arrays
+            SPK_HIP(hipMemcpy(rp.data(), A->row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost));
+        }
+    }
+    if (validate) {
+        if (rp[0] != 0) return fail(SPK_ERR_CSR, "row_ptr[0] = %d, expected 0", rp[0]);
+        for (int64_t i = 0; i < A->nrows; ++i)
+            if (rp[i + 1] < rp[i]) return fail(SPK_ERR_CSR, "row_ptr decreases at row %lld", (long long)i);
+        if (rp[A->nrows] != A->nnz)
+            return fail(SPK_ERR_CSR, "row_ptr[nrows] = %d, expected nnz = %lld", rp[A->nrows], (long long)A->nnz);
+    }
+    spk_mat *M = new spk_mat();
+    M->h = h;
+    M->nrows = A->nrows;
+    M->ncols = A->ncols;
+    M->nnz = A->nnz;
+    M->dtype = A->dtype;
+    M->rp_host = std::move(rp);
+    const size_t vs = dtype_size(A->dtype);
+    auto cleanup = [&](spk_status s) {
+        free_mat(M);
+        return s;
+    };
+    hipError_t e = hipMalloc(&M->rp, sizeof(int32_t) * (M->nrows + 1));
+    if (e == hipSuccess) e = hipMalloc(&M->ci, sizeof(int32_t) * std::max<int64_t>(1, M->nnz));
+    if (e == hipSuccess) e = hipMalloc(&M->val, vs * std::max<int64_t>(1, M->nnz));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(M->rp, M->rp_host.data(), sizeof(int32_t) * (M->nrows + 1), hipMemcpyHostToDevice, h->work);
+    if (e == hipSuccess && M->nnz > 0) e = hipMemcpyAsync(M->ci, A->col_idx, sizeof(int32_t) * M->nnz, kind, h->work);
+    if (e == hipSuccess && M->nnz > 0) e = hipMemcpyAsync(M->val, A->val, vs * M->nnz, kind, h->work);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->work);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "matrix upload"));
+    if (validate && M->nnz > 0) {
+        unsigned long long *bad = nullptr, hbad = 0;
+        e = hipMalloc(&bad, sizeof *bad);
+        if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof *bad, h->work);
+        if (e == hipSuccess) e = launch_csr_colcheck(M->nnz, M->ci, M->ncols, bad, h->work);
+        if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, h->work);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->work);
+        (void)hipFree(bad);
+        if (e != hipSuccess) return cleanup(hip_fail(e, "column check"));
+        if (hbad) return cleanup(fail(SPK_ERR_CSR, "%llu column indices outside [0, %lld)", hbad, (long long)M->ncols));
+    }
+    int64_t mx = 0;
+    for (int64_t i = 0; i < M->nrows; ++i) mx = std::max<int64_t>(mx, M->rp_host[i + 1] - M->rp_host[i]);
+    M->max_len = mx;
+    M->mean_len = M->nrows ? (double)M->nnz / (double)M->nrows : 0.0;
+    M->bytes = (int64_t)(4 * (M->nrows + 1) + (4 + vs) * M->nnz);
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        h->mats.insert(M);
+    }
+    *out = M;
+    return SPK_OK;
+}
+
+spk_status spk_matrix_release(spk_handle h, spk_matrix A)
+{
+    if (!h || !A) return fail(SPK_ERR_NULL, "handle/matrix is NULL");
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        if (!h->mats.erase(A)) return fail(SPK_ERR_NOT_FOUND, "matrix not owned by this handle");
+    }
+    DeviceGuard g(h);
+    (void)hipDeviceSynchronize();
+    free_mat(A);
+    return SPK_OK;
+}
+
+spk_status spk_matrix_bytes(spk_handle h, spk_matrix A, int64_t *bytes)
+{
+    if (!h || !A || !bytes) return fail(SPK_ERR_NULL, "NULL argument");
+    *bytes = A->bytes;
+    return SPK_OK;
+}
+
+static spk_status spmv_mat_common(spk_handle h, spk_matrix A, bool fused, double alpha, const void *x, void *y,
+                                  void *w, spk_stream stream, const spk_variant *forced)
+{
+    if (!h || !A) return fail(SPK_ERR_NULL, "handle/matrix is NULL");
+    if (A->nrows == 0) return SPK_OK;
+    if (!y || (A->ncols > 0 && !x)) return fail(SPK_ERR_NULL, "x/y are NULL");
+    const size_t s = dtype_size(A->dtype);
+    if (overlaps(x, (size_t)A->ncols * s, y, (size_t)A->nrows * s)) return fail(SPK_ERR_ALIAS, "y overlaps x");
+    if (fused) {
+        if (A->nrows != A->ncols) return fail(SPK_ERR_SHAPE, "the fused step needs a square matrix");
+        if (!w) return fail(SPK_ERR_NULL, "w is NULL");
+        if (overlaps(w, (size_t)A->nrows * s, x, (size_t)A->ncols * s) ||
+            overlaps(w, (size_t)A->nrows * s, y, (size_t)A->nrows * s))
+            return fail(SPK_ERR_ALIAS, "w overlaps x or y");
+    }
+    spk_problem p{};
+    p.op = fused ? SPK_OP_SPMV_WAXPY : SPK_OP_SPMV;
+    p.dtype = A->dtype;
+    p.A = A;
+    spk_variant v;
+    if (forced) {
+        v = *forced;
+        SPK_TRY(check_variant(p.op, A->dtype, v));
+    } else {
+        SPK_TRY(resolve(h, p, nullptr, &v));
+    }
+    SpmvProblem q;
+    q.mat = A;
+    q.fused = fused;
+    q.alpha = alpha;
+    q.x = x;
+    q.y = y;
+    q.w = w;
+    DeviceGuard g(h);
+    return run_spmv(h, q, v, (hipStream_t)stream);
+}
+
+spk_status spk_spmv_mat(spk_handle h, spk_matrix A, const void *x, void *y, spk_stream stream)
+{
+    return spmv_mat_common(h, A, false, 0.0, x, y, nullptr, stream, nullptr);
+}
+
+spk_status spk_spmv_waxpy(spk_handle h, spk_matrix A, double alpha, const void *x, void *y, void *w,
+                          spk_stream stream)
+{
+    return spmv_mat_common(h, A, true, alpha, x, y, w, stream, nullptr);
+}
+
+// -------------------------------------------------- variants and plans --
+
+spk_status spk_run(spk_handle h, const spk_problem *p, const spk_variant *variant, spk_stream stream)
+{
+    if (!h || !p) return fail(SPK_ERR_NULL, "handle/problem is NULL");
+    switch (p->op) {
+    case SPK_OP_WAXPY:
+    case SPK_OP_AXPY:
+    case SPK_OP_DOT: {
+        if (!dtype_ok(p->dtype)) return fail(SPK_ERR_DTYPE, "bad dtype %d", p->dtype);
+        if (!variant) {
+            if (p->op == SPK_OP_WAXPY) return spk_waxpy(h, p->dtype, p->n, p->alpha, p->x, p->y, p->w, stream);
+            if (p->op == SPK_OP_AXPY) return spk_axpy(h, p->dtype, p->n, p->alpha, p->x, p->y, stream);
+            return spk_dot(h, p->dtype, p->n, p->x, p->y, p->d_result, stream);
+        }
+        SPK_TRY(check_variant(p->op, p->dtype, *variant));
+        if (p->n < 0) return fail(SPK_ERR_SHAPE, "n < 0");
+        const size_t nb = (size_t)p->n * dtype_size(p->dtype);
+        DeviceGuard g(h);
+        if (p->op == SPK_OP_DOT) {
+            if (!p->d_result || (p->n > 0 && (!p->x || !p->y))) return fail(SPK_ERR_NULL, "NULL operand");
+            return run_dot(h, p->dtype, p->n, p->x, p->y, p->d_result, *variant, (hipStream_t)stream);
+        }
+        if (p->n == 0) return SPK_OK;
+        void *w = p->op == SPK_OP_AXPY ? p->y : p->w;
+        if (!p->x || !p->y || !w) return fail(SPK_ERR_NULL, "NULL operand");
+        if ((w != p->x && overlaps(w, nb, p->x, nb)) || (w != p->y && overlaps(w, nb, p->y, nb)))
+            return fail(SPK_ERR_ALIAS, "output partially overlaps an input");
+        return run_waxpy(h, p->dtype, p->n, p->alpha, p->x, p->y, w, *variant, (hipStream_t)stream);
+    }
+    case SPK_OP_SPMV:
+    case SPK_OP_SPMV_WAXPY:
+        if (!p->A) return fail(SPK_ERR_NULL, "problem.A is NULL");
+        return spmv_mat_common(h, p->A, p->op == SPK_OP_SPMV_WAXPY, p->alpha, p->x, p->y, p->w, stream, variant);
+    default:
+        return fail(SPK_ERR_ARG, "unknown op %d", p->op);
+    }
+}
+
+static void vec_space(int op, int dtype, std::vector<spk_variant> &out)
+{
+    static const int grids[] = {0, 1, 2, 4, 8, 16, 32};
+    int n = 0;
+    const VecEntry *t = op == SPK_OP_DOT ? dot_table(&n) : waxpy_table(&n);
+    // plain variant first
+    out.push_back(plain_variant(op, 0));
+    for (int i = 0; i < n; ++i) {
+        if (!t[i].fn[dtype]) continue;
+        if ((size_t)t[i].vec * dtype_size(dtype) > 16) continue;
+        for (int g : grids) {
+            spk_variant v{};
+            v.block = t[i].block;
+            v.vec = t[i].vec;
+            v.unroll = t[i].unroll;
+            v.grid = g;
+            if (v.block == 256 && v.vec == 1 && v.unroll == 1 && v.grid == 0) continue;
+            out.push_back(v);
+        }
+    }
+}
+
+static void spmv_space(std::vector<spk_variant> &out)
+{
+    int n = 0;
+    const SpmvEntry *t = spmv_table(&n);
+    for (int i = 0; i < n; ++i) {
+        spk_variant v{};
+        v.format = t[i].format;
+        v.block = t[i].block;
+        v.group = t[i].group;
+        v.unroll = t[i].unroll;
+        v.lds = t[i].lds;
+        v.streams = 1;
+        out.push_back(v);
+    }
+}
+
+spk_status spk_variant_count(int32_t op, int32_t dtype, int32_t *count)
+{
+    if (!count) return fail(SPK_ERR_NULL, "count is NULL");
+    if (!dtype_ok(dtype)) return fail(SPK_ERR_DTYPE, "bad dtype %d", dtype);
+    std::vector<spk_variant> s;
+    if (op == SPK_OP_SPMV || op == SPK_OP_SPMV_WAXPY) spmv_space(s);
+    else if (op == SPK_OP_WAXPY || op == SPK_OP_AXPY || op == SPK_OP_DOT) vec_space(op, dtype, s);
+    else return fail(SPK_ERR_ARG, "unknown op %d", op);
+    *count = (int32_t)s.size();
+    return SPK_OK;
+}
+
+spk_status spk_variant_get(int32_t op, int32_t dtype, int32_t index, spk_variant *out)
+{
+    if (!out) return fail(SPK_ERR_NULL, "out is NULL");
+    if (!dtype_ok(dtype)) return fail(SPK_ERR_DTYPE, "bad dtype %d", dtype);
+    std::vector<spk_variant> s;
+    if (op == SPK_OP_SPMV || op == SPK_OP_SPMV_WAXPY) spmv_space(s);
+    else if (op == SPK_OP_WAXPY || op == SPK_OP_AXPY || op == SPK_OP_DOT) vec_space(op, dtype, s);
+    else return fail(SPK_ERR_ARG, "unknown op %d", op);
+    if (index < 0 || index >= (int32_t)s.size()) return fail(SPK_ERR_NOT_FOUND, "variant index %d out of range", index);
+    *out = s[index];
+    return SPK_OK;
+}
+
+spk_status spk_plain_variant(int32_t op, int32_t which, spk_variant *out)
+{
+    if (!out) return fail(SPK_ERR_NULL, "out is NULL");
+    if (op < SPK_OP_SPMV || op > SPK_OP_SPMV_WAXPY) return fail(SPK_ERR_ARG, "unknown op %d", op);
+    if (which != 0 && which != 1) return fail(SPK_ERR_ARG, "which must be 0 or 1");
+    if (which == 1 && op != SPK_OP_SPMV && op != SPK_OP_SPMV_WAXPY)
+        return fail(SPK_ERR_ARG, "vector ops have one plain variant");
+    *out = plain_variant(op, which);
+    return SPK_OK;
+}
+
+spk_status spk_class_key(spk_handle h, const spk_problem *p, char *out, int32_t cap)
+{
+    if (!h || !p || !out || cap <= 0) return fail(SPK_ERR_NULL, "NULL argument");
+    const std::string k = class_key(*p, nullptr);
+    snprintf(out, (size_t)cap, "%s", k.c_str());
+    return SPK_OK;
+}
+
+spk_status spk_plan_get(spk_handle h, const char *class_key_, spk_variant *out)
+{
+    if (!h || !class_key_ || !out) return fail(SPK_ERR_NULL, "NULL argument");
+    std::lock_guard<std::mutex> lk(h->mu);
+    auto it = h->plans.find(class_key_);
+    if (it == h->plans.end()) return fail(SPK_ERR_NOT_FOUND, "no plan for %s", class_key_);
+    *out = it->second;
+    return SPK_OK;
+}
+
+spk_status spk_plan_put(spk_handle h, const char *class_key_, const spk_variant *v)
+{
+    if (!h || !class_key_ || !v) return fail(SPK_ERR_NULL, "NULL argument");
+    std::lock_guard<std::mutex> lk(h->mu);
+    h->plans[class_key_] = *v;
+    return SPK_OK;
+}
+
+// ------------------------------------------------------------ measurement --
+
+spk_status spk_stream_probe(spk_handle h, int32_t kind, int64_t n, const double *a, const double *b, double *c,
+                            spk_stream stream)
+{
+    if (!h) return fail(SPK_ERR_NULL, "handle is NULL");
+    if (n < 0) return fail(SPK_ERR_SHAPE, "n < 0");
+    if (n == 0) return SPK_OK;
+    DeviceGuard g(h);
+    if (kind == 0) {
+        if (!a || !c) return fail(SPK_ERR_NULL, "a/c are NULL");
+        SPK_HIP(launch_copy(n, a, c, (hipStream_t)stream));
+    } else if (kind == 1) {
+        if (!a || !b || !c) return fail(SPK_ERR_NULL, "a/b/c are NULL");
+        SPK_HIP(launch_triad(n, a, b, 3.0, c, (hipStream_t)stream));
+    } else {
+        return fail(SPK_ERR_ARG, "kind must be 0 (copy) or 1 (triad)");
+    }
+    return SPK_OK;
+}
+
+spk_status spk_flush_cache(spk_handle h, spk_stream stream)
+{
+    if (!h) return fail(SPK_ERR_NULL, "handle is NULL");
+    DeviceGuard g(h);
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        if (!h->flush_buf) {
+            h->flush_bytes = 512ll << 20;
+            SPK_HIP(hipMalloc(&h->flush_buf, (size_t)h->flush_bytes));
+        }
+    }
+    static std::atomic<uint32_t> pattern{1};
+    SPK_HIP(launch_fill(h->flush_buf, h->flush_bytes, pattern++, (hipStream_t)stream));
+    return SPK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,509 @@
+// batch.cpp -- many independent CSR instances in one launch.
+//
+// Planning: each instance gets a shape class (ceil(log2) of its mean row
+// length); each class is served by one tile kernel (LDS row stream, or G
+// lanes per row), taken from the plan DB or from spk_batch_tune.  Instances
+// are cut into tiles of about `tile_nnz` entries; tiles are listed instance
+// by instance and executed by one persistent launch that pulls them from a
+// queue (or one workgroup per tile).  The launch is captured in a hipGraph
+// once per (x, y, w, alpha) and replayed.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "device_common.h"
+#include "internal.h"
+
+struct spk_batch_s {
+    spk_handle h = nullptr;
+    int32_t dtype = SPK_F64;
+    int64_t count = 0;
+    std::vector<int64_t> m, nnz, rp_off, nz_off, vec_off;
+    std::vector<int32_t> rp_host;         // concatenated row_ptr (host copy)
+    const int32_t *rp = nullptr, *ci = nullptr;
+    const void *val = nullptr;
+    spk_batch_opts opts{};
+    const spk::BatchEntry *entry = nullptr;
+    std::vector<int> cls;                 // class per instance
+    std::map<int, int> mode;              // class -> tile mode
+    std::vector<spk::BatchTile> tiles;
+    spk::BatchInst *d_inst = nullptr;
+    spk::BatchTile *d_tiles = nullptr;
+    int64_t d_tiles_cap = 0;
+    uint32_t *d_ctr = nullptr;            // [0] queue head, [1] done count
+    int64_t grid_persistent = 0;
+    // captured launch
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void *gx = nullptr;
+    void *gy = nullptr, *gw = nullptr;
+    double galpha = 0.0;
+};
+
+namespace spk {
+
+int batch_class(int64_t m, int64_t nnz)
+{
+    const double mean = m > 0 ? (double)nnz / (double)m : 0.0;
+    int c = 0;
+    while ((double)(1 << c) < mean && c < 20) ++c;
+    return c;
+}
+
+int batch_default_mode(int cls, int tile)
+{
+    // mean row length <= 2^cls: short rows go through the LDS stream
+    const int mean = 1 << cls;
+    if (mean <= 32 && mean * 4 <= tile) return 0;
+    return std::min(64, std::max(8, mean / 2));
+}
+
+std::string batch_key(int dtype, int cls)
+{
+    char b[64];
+    snprintf(b, sizeof b, "batch:%s:c%d", dtype_name(dtype), cls);
+    return b;
+}
+
+const BatchEntry *batch_entry(int block, int tile)
+{
+    int n = 0;
+    const BatchEntry *t = batch_table(&n);
+    for (int i = 0; i < n; ++i)
+        if (t[i].block == block && t[i].tile == tile) return &t[i];
+    return nullptr;
+}
+
+void cut_rows(const int32_t *rp, int64_t m, int mode, int block, int tile, int64_t target, int32_t inst,
+              std::vector<BatchTile> &out)
+{
+    int64_t r = 0;
+    while (r < m) {
+        BatchTile t{inst, (int32_t)r, 0, mode};
+        if (mode == 0) {
+            if (rp[r + 1] - rp[r] > tile) {
+                // a row that does not fit the LDS tile gets one wavefront
+                t.mode = 64;
+                t.r1 = (int32_t)(r + 1);
+                out.push_back(t);
+                ++r;
+                continue;
+            }
+            int64_t nz = 0, c = 0;
+            while (r < m && c < 2 * (int64_t)block) {
+                const int64_t l = rp[r + 1] - rp[r];
+                if (nz + l > tile) break;
+                nz += l;
+                ++r;
+                ++c;
+            }
+            t.r1 = (int32_t)r;
+        } else {
+            const int64_t rows_per_pass = block / mode;
+            int64_t r1 = r, nz = 0;
+            while (r1 < m && nz < target) {
+                const int64_t r2 = std::min<int64_t>(m, r1 + rows_per_pass);
+                nz += rp[r2] - rp[r1];
+                r1 = r2;
+            }
+            t.r1 = (int32_t)r1;
+            r = r1;
+        }
+        out.push_back(t);
+    }
+}
+
+spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchInst *d_inst, const BatchTile *d_tiles,
+                        int64_t ntiles, double alpha, const void *x, void *y, void *w, uint32_t *next,
+                        int64_t persistent_grid, hipStream_t s)
+{
+    if (ntiles == 0) return SPK_OK;
+    union {
+        BatchArgs<float> f;
+        BatchArgs<double> d;
+    } a;
+    memset(&a, 0, sizeof a);
+    auto fill = [&](auto &q) {
+        using Q = std::remove_reference_t<decltype(q)>;
+        using T = std::remove_const_t<std::remove_pointer_t<decltype(Q::x)>>;
+        q.inst = d_inst;
+        q.tiles = d_tiles;
+        q.ntiles = (int32_t)ntiles;
+        q.x = (const T *)x;
+        q.y = (T *)y;
+        q.w = (T *)w;
+        q.alpha = (T)alpha;
+        q.next = next;
+        q.done = next ? next + 1 : nullptr;
+    };
+    if (dtype == SPK_F64) fill(a.d); else fill(a.f);
+    const bool pers = next != nullptr;
+    const dim3 grid((unsigned)(pers ? std::min<int64_t>(persistent_grid, ntiles) : ntiles));
+    SPK_HIP(e->fn[dtype][pers ? 1 : 0](dtype == SPK_F64 ? (const void *)&a.d : (const void *)&a.f, grid, s));
+    return SPK_OK;
+}
+
+namespace {
+
+void invalidate_graph(spk_batch b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Tiles of instance i under `mode`.
+void cut_instance(const spk_batch b, int64_t i, int mode, std::vector<BatchTile> &out)
+{
+    cut_rows(b->rp_host.data() + b->rp_off[i], b->m[i], mode, b->entry->block, b->entry->tile, b->opts.tile_nnz,
+             (int32_t)i, out);
+}
+
+spk_status upload_tiles(spk_batch b, const std::vector<BatchTile> &tiles)
+{
+    if ((int64_t)tiles.size() > b->d_tiles_cap) {
+        if (b->d_tiles) SPK_HIP(hipFree(b->d_tiles));
+        b->d_tiles = nullptr;
+        const int64_t cap = std::max<int64_t>(1, (int64_t)tiles.size());
+        SPK_HIP(hipMalloc(&b->d_tiles, sizeof(BatchTile) * cap));
+        b->d_tiles_cap = cap;
+    }
+    // ordered after any launch already queued on the work stream that reads the old tiles
+    if (!tiles.empty()) {
+        SPK_HIP(hipMemcpyAsync(b->d_tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice,
+                               b->h->work));
+        SPK_HIP(hipStreamSynchronize(b->h->work));
+    }
+    return SPK_OK;
+}
+
+spk_status replan(spk_batch b)
+{
+    b->tiles.clear();
+    for (int64_t i = 0; i < b->count; ++i) cut_instance(b, i, b->mode[b->cls[i]], b->tiles);
+    invalidate_graph(b);
+    return upload_tiles(b, b->tiles);
+}
+
+// Launches the tile kernel over `ntiles` tiles already on the device.
+spk_status launch(spk_batch b, int64_t ntiles, double alpha, const void *x, void *y, void *w, hipStream_t s)
+{
+    return launch_tiles(b->entry, b->dtype, b->d_inst, b->d_tiles, ntiles, alpha, x, y, w,
+                        b->opts.persistent ? b->d_ctr : nullptr, b->grid_persistent, s);
+}
+
+spk_status occupancy(spk_batch b)
+{
+    int64_t per_cu = b->entry->occupancy[b->dtype]();
+    if (b->opts.waves_per_cu > 0) per_cu = std::max<int64_t>(1, b->opts.waves_per_cu / (b->entry->block / 64));
+    b->grid_persistent = per_cu * b->h->num_cu;
+    return SPK_OK;
+}
+
+}  // namespace
+
+}  // namespace spk
+
+using namespace spk;
+
+extern "C" {
+
+spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *d, const spk_batch_opts *opts, spk_batch *out)
+{
+    if (!h || !d || !out) return fail(SPK_ERR_NULL, "NULL argument");
+    *out = nullptr;
+    if (!dtype_ok(d->dtype)) return fail(SPK_ERR_DTYPE, "bad dtype %d", d->dtype);
+    if (d->count < 0) return fail(SPK_ERR_SHAPE, "count < 0");
+    if (d->count > 0 && (!d->m || !d->nnz || !d->rp_off || !d->nz_off || !d->vec_off))
+        return fail(SPK_ERR_NULL, "size/offset arrays are NULL");
+    if (d->count > 0 && (!d->row_ptr || !d->col_idx || !d->val)) return fail(SPK_ERR_NULL, "device arrays are NULL");
+    spk_batch_opts o{};
+    o.persistent = 1;
+    o.use_graph = 1;
+    if (opts) {
+        o = *opts;
+    }
+    if (o.block == 0) o.block = 256;
+    if (o.tile_nnz == 0) o.tile_nnz = 2048;
+    const int lds_tile = o.tile_nnz <= 1024 ? 1024 : o.tile_nnz <= 2048 ? 2048 : 4096;
+    const BatchEntry *e = batch_entry(o.block, lds_tile);
+    if (!e) e = batch_entry(o.block, 2048);
+    if (!e) return fail(SPK_ERR_ARG, "no batched kernel with block %d", o.block);
+
+    int64_t rp_total = 0;
+    for (int64_t i = 0; i < d->count; ++i) {
+        if (d->m[i] < 0 || d->nnz[i] < 0 || d->m[i] >= (1ll << 30)) return fail(SPK_ERR_SHAPE, "instance %lld size", (long long)i);
+        rp_total = std::max<int64_t>(rp_total, d->rp_off[i] + d->m[i] + 1);
+    }
+    DeviceGuard g(h);
+    spk_batch b = new spk_batch_s();
+    b->h = h;
+    b->dtype = d->dtype;
+    b->count = d->count;
+    b->opts = o;
+    b->entry = e;
+    b->rp = d->row_ptr;
+    b->ci = d->col_idx;
+    b->val = d->val;
+    b->m.assign(d->m, d->m + d->count);
+    b->nnz.assign(d->nnz, d->nnz + d->count);
+    b->rp_off.assign(d->rp_off, d->rp_off + d->count);
+    b->nz_off.assign(d->nz_off, d->nz_off + d->count);
+    b->vec_off.assign(d->vec_off, d->vec_off + d->count);
+    b->rp_host.resize((size_t)rp_total);
+    auto bail = [&](spk_status s) {
+        spk_batch_free(h, b);
+        return s;
+    };
+    if (rp_total > 0) {
+        if (d->row_ptr_host) {
+            memcpy(b->rp_host.data(), d->row_ptr_host, sizeof(int32_t) * rp_total);
+        } else {
+            hipError_t he = hipDeviceSynchronize();
+            if (he == hipSuccess)
+                he = hipMemcpy(b->rp_host.data(), d->row_ptr, sizeof(int32_t) * rp_total, hipMemcpyDeviceToHost);
+            if (he != hipSuccess) return bail(hip_fail(he, "row_ptr download"));
+        }
+    }
+    for (int64_t i = 0; i < b->count; ++i) {
+        const int32_t *rp = b->rp_host.data() + b->rp_off[i];
+        if (rp[0] != 0 || rp[b->m[i]] != b->nnz[i])
+            return bail(fail(SPK_ERR_CSR, "instance %lld: row_ptr does not span [0, nnz]", (long long)i));
+    }
+    b->cls.resize((size_t)b->count);
+    for (int64_t i = 0; i < b->count; ++i) {
+        const int c = batch_class(b->m[i], b->nnz[i]);
+        b->cls[i] = c;
+        if (!b->mode.count(c)) {
+            spk_variant v{};
+            if (spk_plan_get(h, batch_key(b->dtype, c).c_str(), &v) == SPK_OK && (v.group == 0 || v.group >= 2))
+                b->mode[c] = v.group;
+            else
+                b->mode[c] = batch_default_mode(c, e->tile);
+        }
+    }
+    std::vector<BatchInst> inst((size_t)b->count);
+    const size_t vs = dtype_size(b->dtype);
+    for (int64_t i = 0; i < b->count; ++i)
+        inst[i] = BatchInst{b->rp + b->rp_off[i], b->ci + b->nz_off[i], (const char *)b->val + vs * b->nz_off[i],
+                            b->vec_off[i], (int32_t)b->m[i], 0};
+    hipError_t he = hipMalloc(&b->d_inst, sizeof(BatchInst) * std::max<int64_t>(1, b->count));
+    if (he == hipSuccess && b->count)
+        he = hipMemcpyAsync(b->d_inst, inst.data(), sizeof(BatchInst) * b->count, hipMemcpyHostToDevice, h->work);
+    if (he == hipSuccess) he = hipMalloc(&b->d_ctr, 256);
+    if (he == hipSuccess) he = hipMemsetAsync(b->d_ctr, 0, 256, h->work);
+    if (he == hipSuccess) he = hipStreamSynchronize(h->work);
+    if (he != hipSuccess) return bail(hip_fail(he, "batch descriptors"));
+    spk_status st = occupancy(b);
+    if (st == SPK_OK) st = replan(b);
+    if (st != SPK_OK) return bail(st);
+    *out = b;
+    return SPK_OK;
+}
+
+spk_status spk_batch_run(spk_handle h, spk_batch b, double alpha, const void *x, void *y, void *w, spk_stream stream)
+{
+    if (!h || !b) return fail(SPK_ERR_NULL, "handle/batch is NULL");
+    if (b->h != h) return fail(SPK_ERR_ARG, "batch belongs to another handle");
+    if (b->count == 0 || b->tiles.empty()) return SPK_OK;
+    if (!x || !y) return fail(SPK_ERR_NULL, "x/y are NULL");
+    DeviceGuard g(h);
+    hipStream_t s = (hipStream_t)stream;
+    if (!b->opts.use_graph) return launch(b, (int64_t)b->tiles.size(), alpha, x, y, w, s);
+    if (!b->exec || b->gx != x || b->gy != y || b->gw != w || b->galpha != alpha) {
+        invalidate_graph(b);
+        SPK_HIP(hipStreamSynchronize(h->work));
+        SPK_HIP(hipStreamBeginCapture(h->work, hipStreamCaptureModeThreadLocal));
+        spk_status st = launch(b, (int64_t)b->tiles.size(), alpha, x, y, w, h->work);
+        hipGraph_t graph = nullptr;
+        const hipError_t ce = hipStreamEndCapture(h->work, &graph);
+        if (st != SPK_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+        b->graph = graph;
+        SPK_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->gx = x;
+        b->gy = y;
+        b->gw = w;
+        b->galpha = alpha;
+    }
+    SPK_HIP(hipGraphLaunch(b->exec, s));
+    return SPK_OK;
+}
+
+spk_status spk_batch_info(spk_handle h, spk_batch b, int64_t *tiles, int32_t *classes, int64_t *bytes)
+{
+    if (!h || !b) return fail(SPK_ERR_NULL, "handle/batch is NULL");
+    if (tiles) *tiles = (int64_t)b->tiles.size();
+    if (classes) *classes = (int32_t)b->mode.size();
+    if (bytes) {
+        int64_t t = 0;
+        for (int64_t i = 0; i < b->count; ++i) t += spmv_bytes(b->m[i], b->m[i], b->nnz[i], b->dtype, true);
+        *bytes = t;
+    }
+    return SPK_OK;
+}
+
+spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x, void *y, void *w,
+                          const spk_tune_opts *opts, spk_tune_report *report)
+{
+    if (!h || !b || !report) return fail(SPK_ERR_NULL, "NULL argument");
+    if (!x || !y) return fail(SPK_ERR_NULL, "x/y are NULL");
+    spk_tune_opts o{};
+    if (opts) o = *opts;
+    const int reps = o.reps > 0 ? o.reps : 10;
+    const int warmup = o.warmup > 0 ? o.warmup : 2;
+    const double tau = o.tau > 0 ? o.tau : (b->dtype == SPK_F64 ? 1e-12 : 1e-5);
+    memset(report, 0, sizeof *report);
+    DeviceGuard g(h);
+    SPK_HIP(hipDeviceSynchronize());
+    hipStream_t s = h->work;
+    const size_t vs = dtype_size(b->dtype);
+    int64_t nvec = 0;
+    for (int64_t i = 0; i < b->count; ++i) nvec = std::max<int64_t>(nvec, b->vec_off[i] + b->m[i]);
+    if (nvec == 0) return SPK_OK;
+
+    // reference: the current plan's output, and the row tolerance scales
+    double *ref_y = nullptr, *ref_w = nullptr, *scale = nullptr, *scale_w = nullptr;
+    unsigned long long *bad = nullptr, *hbad = nullptr;
+    struct Free {
+        std::vector<void *> d;
+        void *hp = nullptr;
+        ~Free()
+        {
+            for (void *p : d) hipFree(p);
+            if (hp) (void)hipHostFree(hp);
+        }
+    } fr;
+    SPK_HIP(hipMalloc(&ref_y, 8 * nvec)); fr.d.push_back(ref_y);
+    SPK_HIP(hipMalloc(&scale, 8 * nvec)); fr.d.push_back(scale);
+    SPK_HIP(hipMalloc(&bad, 8)); fr.d.push_back(bad);
+    SPK_HIP(hipHostMalloc((void **)&hbad, 8, hipHostMallocDefault)); fr.hp = hbad;
+    if (w) {
+        SPK_HIP(hipMalloc(&ref_w, 8 * nvec)); fr.d.push_back(ref_w);
+        SPK_HIP(hipMalloc(&scale_w, 8 * nvec)); fr.d.push_back(scale_w);
+    }
+    SPK_TRY(launch(b, (int64_t)b->tiles.size(), alpha, x, y, w, s));
+    SPK_HIP(launch_widen(b->dtype, nvec, y, ref_y, s));
+    if (w) SPK_HIP(launch_widen(b->dtype, nvec, w, ref_w, s));
+    for (int64_t i = 0; i < b->count; ++i) {
+        const char *xv = (const char *)x + vs * b->vec_off[i];
+        SPK_HIP(launch_row_absum(b->dtype, (int32_t)b->m[i], b->rp + b->rp_off[i], b->ci + b->nz_off[i],
+                                 (const char *)b->val + vs * b->nz_off[i], xv, scale + b->vec_off[i], s));
+    }
+    if (w) {
+        std::vector<double> sc((size_t)nvec), wr((size_t)nvec);
+        SPK_HIP(hipMemcpyAsync(sc.data(), scale, 8 * nvec, hipMemcpyDeviceToHost, s));
+        SPK_HIP(hipMemcpyAsync(wr.data(), ref_w, 8 * nvec, hipMemcpyDeviceToHost, s));
+        SPK_HIP(hipStreamSynchronize(s));
+        const double eps = b->dtype == SPK_F64 ? 0x1p-52 : 0x1p-23;
+        for (int64_t i = 0; i < nvec; ++i) sc[i] = std::fabs(alpha) * sc[i] + 2.0 * eps * std::fabs(wr[i]) / tau;
+        SPK_HIP(hipMemcpyAsync(scale_w, sc.data(), 8 * nvec, hipMemcpyHostToDevice, s));
+    }
+    SPK_HIP(hipStreamSynchronize(s));
+
+    std::vector<hipEvent_t> ev(2 * (size_t)reps);
+    for (auto &e : ev) SPK_HIP(hipEventCreate(&e));
+    struct EvFree {
+        std::vector<hipEvent_t> &e;
+        ~EvFree() { for (auto x : e) hipEventDestroy(x); }
+    } ef{ev};
+
+    int tried = 0, rejected = 0;
+    double total_best = 0.0, total_plain = 0.0;
+    std::map<int, std::vector<int64_t>> by_class;
+    for (int64_t i = 0; i < b->count; ++i) by_class[b->cls[i]].push_back(i);
+    for (auto &kv : by_class) {
+        const int c = kv.first;
+        double best = 1e300;
+        int best_mode = b->mode[c];
+        double plain_time = -1.0;
+        for (int mode : {0, 2, 4, 8, 16, 32, 64}) {
+            std::vector<BatchTile> tl;
+            for (int64_t i : kv.second) cut_instance(b, i, mode, tl);
+            SPK_TRY(upload_tiles(b, tl));
+            // validate: only this class's rows are rewritten
+            SPK_HIP(hipMemsetAsync(bad, 0, 8, s));
+            SPK_TRY(launch(b, (int64_t)tl.size(), alpha, x, y, w, s));
+            SPK_HIP(launch_check(b->dtype, 0, nvec, y, ref_y, scale, tau, bad, s));
+            if (w) SPK_HIP(launch_check(b->dtype, 0, nvec, w, ref_w, scale_w, tau, bad, s));
+            SPK_HIP(hipMemcpyAsync(hbad, bad, 8, hipMemcpyDeviceToHost, s));
+            SPK_HIP(hipStreamSynchronize(s));
+            if (*hbad) {
+                ++rejected;
+                continue;
+            }
+            for (int r = 0; r < warmup; ++r) SPK_TRY(launch(b, (int64_t)tl.size(), alpha, x, y, w, s));
+            for (int r = 0; r < reps; ++r) {
+                if (o.flush) SPK_TRY(spk_flush_cache(h, (spk_stream)s));
+                SPK_HIP(hipEventRecord(ev[2 * r], s));
+                SPK_TRY(launch(b, (int64_t)tl.size(), alpha, x, y, w, s));
+                SPK_HIP(hipEventRecord(ev[2 * r + 1], s));
+            }
+            SPK_HIP(hipStreamSynchronize(s));
+            std::vector<double> t;
+            for (int r = 0; r < reps; ++r) {
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]);
+                t.push_back(ms * 1e3);
+            }
+            std::sort(t.begin(), t.end());
+            const double med = t[t.size() / 2];
+            ++tried;
+            if (o.verbose) fprintf(stderr, "spk_batch_tune: class %d mode %d: %.2f us\n", c, mode, med);
+            if (mode == batch_default_mode(c, b->entry->tile)) plain_time = med;
+            if (med < best) {
+                best = med;
+                best_mode = mode;
+            }
+        }
+        b->mode[c] = best_mode;
+        total_best += best;
+        total_plain += plain_time > 0 ? plain_time : best;
+        if (o.record) {
+            spk_variant v{};
+            v.format = best_mode == 0 ? SPK_FMT_ADAPTIVE : SPK_FMT_VECTOR;
+            v.block = b->entry->block;
+            v.group = best_mode;
+            v.lds = b->entry->tile;
+            v.streams = 1;
+            const std::string key = batch_key(b->dtype, c);
+            spk_plan_put(h, key.c_str(), &v);
+            db_append(h, key, v, best);
+        }
+    }
+    SPK_TRY(replan(b));
+    // leave a full-batch result in the caller's buffers
+    SPK_TRY(launch(b, (int64_t)b->tiles.size(), alpha, x, y, w, s));
+    SPK_HIP(hipStreamSynchronize(s));
+    report->tried = tried;
+    report->rejected = rejected;
+    report->best_us = total_best;
+    report->plain_us = total_plain;
+    report->best.block = b->entry->block;
+    report->best.lds = b->entry->tile;
+    snprintf(report->class_key, sizeof report->class_key, "batch:%s:%d-classes", dtype_name(b->dtype),
+             (int)by_class.size());
+    if (tried == 0) return fail(SPK_ERR_VALIDATION, "no tile kernel reproduced the reference");
+    return SPK_OK;
+}
+
+spk_status spk_batch_free(spk_handle h, spk_batch b)
+{
+    if (!h || !b) return fail(SPK_ERR_NULL, "handle/batch is NULL");
+    DeviceGuard g(h);
+    (void)hipDeviceSynchronize();
+    invalidate_graph(b);
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_ctr) (void)hipFree(b->d_ctr);
+    delete b;
+    return SPK_OK;
+}
+
+}  // extern "C"

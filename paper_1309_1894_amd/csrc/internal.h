@@ -1,0 +1,201 @@
+// internal.h -- host-side state of libspk shared by the API, tuner, batch
+// planner and serving loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdarg>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/spk.h"
+#include "batch_types.h"
+#include "kernels.h"
+
+#ifndef SPK_BUILD_ID
+#define SPK_BUILD_ID "dev"
+#endif
+
+namespace spk {
+
+// ---------------------------------------------------------------- errors
+
+spk_status fail(spk_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+spk_status hip_fail(hipError_t e, const char *what);
+
+#define SPK_HIP(call)                                       \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return ::spk::hip_fail(e_, #call); \
+    } while (0)
+
+#define SPK_TRY(call)                          \
+    do {                                       \
+        spk_status s_ = (call);                \
+        if (s_ != SPK_OK) return s_;           \
+    } while (0)
+
+inline size_t dtype_size(int dtype) { return dtype == SPK_F64 ? 8 : 4; }
+inline bool dtype_ok(int dtype) { return dtype == SPK_F32 || dtype == SPK_F64; }
+const char *dtype_name(int dtype);
+
+// True when [a, a+na) and [b, b+nb) share a byte.
+inline bool overlaps(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return na && nb && x < y + nb && y < x + na;
+}
+
+// ------------------------------------------------------------- matrices
+
+struct SellData {
+    int32_t C = 0;
+    int64_t nslices = 0, padded = 0;
+    int64_t *ptr = nullptr;     // nslices + 1
+    int32_t *len = nullptr;     // nrows
+    int32_t *ci = nullptr;      // padded
+    void *val = nullptr;        // padded
+    int64_t bytes = 0;
+};
+
+struct BlockData {
+    uint32_t *blk = nullptr;    // nblk + 1 entries (start row | mode << 30)
+    int32_t nblk = 0;
+    std::vector<uint32_t> host;
+    int64_t bytes = 0;
+};
+
+}  // namespace spk
+
+struct spk_mat {
+    spk_handle h = nullptr;
+    int64_t nrows = 0, ncols = 0, nnz = 0;
+    int32_t dtype = SPK_F64;
+    int32_t *rp = nullptr;
+    int32_t *ci = nullptr;
+    void *val = nullptr;
+    std::vector<int32_t> rp_host;
+    double mean_len = 0.0;
+    int64_t max_len = 0;
+    int64_t bytes = 0;
+    std::map<int, spk::SellData> sell;                       // by slice height
+    std::map<std::pair<int, int>, spk::BlockData> blocks;    // by (block, tile)
+};
+
+namespace spk {
+
+struct DotScratch {
+    double *partial = nullptr;
+    uint32_t *ticket = nullptr;
+    int64_t cap = 0;
+};
+
+}  // namespace spk
+
+struct spk_ctx {
+    int device = 0;
+    int num_cu = 0;
+    char name[256] = {0};
+    char arch[64] = {0};
+    bool plain = false;
+    std::string db_path;
+    std::mutex mu;
+    std::map<std::string, spk_variant> plans;
+    std::map<hipStream_t, spk::DotScratch> dot;
+    void *flush_buf = nullptr;
+    int64_t flush_bytes = 0;
+    hipStream_t sub[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipStream_t work = nullptr;   // tuner / planner stream
+    std::set<spk_mat *> mats;
+};
+
+namespace spk {
+
+// Makes the handle's device current for the scope.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(spk_handle h)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != h->device) (void)hipSetDevice(h->device);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// ------------------------------------------------------------- dispatch
+
+// Selection of the kernel entry for a variant (nullptr if not compiled).
+const VecEntry *find_vec_entry(int op, int dtype, const spk_variant &v);
+const SpmvEntry *find_spmv_entry(const spk_variant &v);
+
+spk_status check_variant(int op, int dtype, const spk_variant &v);
+
+spk_status run_waxpy(spk_handle h, int dtype, int64_t n, double alpha, const void *x, const void *y, void *w,
+                     const spk_variant &v, hipStream_t s);
+spk_status run_dot(spk_handle h, int dtype, int64_t n, const void *x, const void *y, double *out,
+                   const spk_variant &v, hipStream_t s);
+
+// SpMV (optionally fused) on a registered matrix or a borrowed CSR view
+// (mat == nullptr; then only SCALAR/VECTOR apply).
+struct SpmvProblem {
+    spk_mat *mat = nullptr;
+    const spk_csr *csr = nullptr;
+    bool fused = false;
+    double alpha = 0.0;
+    const void *x = nullptr;
+    void *y = nullptr;
+    void *w = nullptr;
+};
+
+spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hipStream_t s);
+
+// Variant used when the caller does not name one.
+spk_variant default_variant(spk_handle h, const spk_problem &p, const spk_csr *csr);
+spk_variant plain_variant(int op, int which);
+
+// Shape-class key of a problem (plan DB key).
+std::string class_key(const spk_problem &p, const spk_csr *csr);
+
+// Derived formats of a registered matrix (built on first use; synchronous).
+spk_status get_sell(spk_handle h, spk_mat *A, int C, SellData **out);
+spk_status get_blocks(spk_handle h, spk_mat *A, int block, int tile, BlockData **out);
+int64_t sell_padded_entries(const spk_mat *A, int C);
+
+// Plan DB persistence.
+void db_load(spk_handle h);
+void db_append(spk_handle h, const std::string &key, const spk_variant &v, double us);
+
+// Algorithmic bytes of one SpMV (+ step) on a matrix.
+int64_t spmv_bytes(int64_t m, int64_t n, int64_t nnz, int dtype, bool fused);
+
+double now_seconds();
+
+// ------------------------------------------------------- batched tiles
+
+int batch_class(int64_t m, int64_t nnz);
+int batch_default_mode(int cls, int tile);
+std::string batch_key(int dtype, int cls);
+const BatchEntry *batch_entry(int block, int tile);
+
+// Cuts rows [0, m) of one CSR (host row_ptr) into tiles for `mode`
+// (0 = LDS stream of at most `tile` entries and 2*block rows; G = G lanes
+// per row, about `target` entries per tile).
+void cut_rows(const int32_t *rp, int64_t m, int mode, int block, int tile, int64_t target, int32_t inst,
+              std::vector<BatchTile> &out);
+
+// One launch of the tile kernel (persistent when `next` is non-null).
+spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchInst *d_inst, const BatchTile *d_tiles,
+                        int64_t ntiles, double alpha, const void *x, void *y, void *w, uint32_t *next,
+                        int64_t persistent_grid, hipStream_t s);
+
+}  // namespace spk

@@ -1,0 +1,101 @@
+// kernels.h -- host-visible registry of the compiled kernel variants.
+//
+// Each kernel family is a C++ template whose parameters are the tuning knobs
+// (threads per block, lanes per row, unroll, vector width, LDS tile).  The
+// instantiations compiled into the library are listed in tables; the
+// dispatcher and the tuner pick entries from them at run time.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spk {
+
+// ----------------------------------------------------------- vector kernels
+
+struct VecLaunch {
+    int64_t n;
+    double alpha;
+    const void *x;
+    const void *y;
+    void *w;             // WAXPY/AXPY output
+    double *partial;     // DOT: one double per workgroup
+    uint32_t *ticket;    // DOT: zero on entry, left zero on exit
+    double *out;         // DOT: result
+    int64_t grid;        // workgroups to launch
+};
+
+using VecFn = hipError_t (*)(const VecLaunch &, hipStream_t);
+
+struct VecEntry {
+    int block, vec, unroll;
+    VecFn fn[2];         // [SPK_F32, SPK_F64]; null when vec*sizeof(T) > 16
+};
+
+const VecEntry *waxpy_table(int *count);
+const VecEntry *dot_table(int *count);
+
+// Elements covered by one workgroup in one pass.
+inline int64_t vec_per_block(const VecEntry &e) { return (int64_t)e.block * e.vec * e.unroll; }
+
+// ------------------------------------------------------------- SpMV kernels
+
+// `args` points at a SpmvArgs<T> of the entry's dtype.
+using SpmvFn = hipError_t (*)(const void *args, dim3 grid, hipStream_t);
+
+struct SpmvEntry {
+    int format, block, group, unroll, lds;
+    SpmvFn fn[2][2];     // [dtype][fused]
+};
+
+const SpmvEntry *spmv_table(int *count);
+
+// --------------------------------------------------------- batched kernels
+
+using BatchFn = hipError_t (*)(const void *args, dim3 grid, hipStream_t);
+
+struct BatchEntry {
+    int block, tile;     // threads per workgroup, LDS tile (entries)
+    BatchFn fn[2][2];    // [dtype][persistent]
+    int (*occupancy[2])();  // [dtype] resident workgroups per CU (persistent kernel)
+};
+
+const BatchEntry *batch_table(int *count);
+
+// ------------------------------------------------------------- utilities
+
+// Counts outputs that fail the acceptance test against a reference held in
+// double: mode 0 = per-element |out - ref| <= tau*scale (scale null -> 0),
+// mode 1 = ulp distance <= 1 after rounding ref to T.  NaN/Inf must match.
+hipError_t launch_check(int dtype, int mode, int64_t n, const void *out, const double *ref,
+                        const double *scale, double tau, unsigned long long *bad, hipStream_t s);
+
+// out[i] = (double)in[i]
+hipError_t launch_widen(int dtype, int64_t n, const void *in, double *out, hipStream_t s);
+
+// scale_i = sum_k |a_ik * x_k| over rows [0, m)
+hipError_t launch_row_absum(int dtype, int32_t m, const int32_t *rp, const int32_t *ci,
+                            const void *val, const void *x, double *scale, hipStream_t s);
+
+// scale_i = |x_i * y_i| summed into one double (dot tolerance scale)
+hipError_t launch_dot_absum(int dtype, int64_t n, const void *x, const void *y, double *out,
+                            hipStream_t s);
+
+// Fills n bytes (n a multiple of 16) with a pattern: evicts caches.
+hipError_t launch_fill(void *p, int64_t n, uint32_t pattern, hipStream_t s);
+
+// STREAM copy (b = a) and triad (c = a + s*b) on doubles.
+hipError_t launch_copy(int64_t n, const double *a, double *b, hipStream_t s);
+hipError_t launch_triad(int64_t n, const double *a, const double *b, double s_, double *c,
+                        hipStream_t s);
+
+// Counts malformed CSR entries: columns outside [0, ncols).
+hipError_t launch_csr_colcheck(int64_t nnz, const int32_t *ci, int64_t ncols,
+                               unsigned long long *bad, hipStream_t s);
+
+// Scatters CSR rows into sliced-ELL storage (C rows per slice).
+hipError_t launch_csr_to_sell(int dtype, int32_t m, int32_t C, const int32_t *rp, const int32_t *ci,
+                              const void *val, const int64_t *sell_ptr, int32_t *sell_len,
+                              int32_t *sell_ci, void *sell_val, hipStream_t s);
+
+}  // namespace spk

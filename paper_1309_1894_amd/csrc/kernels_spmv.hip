@@ -1,0 +1,223 @@
+// kernels_spmv.hip -- CSR sparse matrix-vector product y = A*x for gfx950,
+// optionally fused with the step w = alpha*y + x.
+//
+// Four kernel families (the code variants the tuner searches):
+//   SCALAR   one lane per row: each lane walks its own row.
+//   VECTOR   G lanes per row (G = 2..64; 64 is one wavefront per row): the
+//            lanes of a group stride the row with coalesced loads and meet
+//            in a DPP/ds_swizzle group reduction.  Optionally stages the
+//            workgroup's row_ptr slice in LDS.
+//   SELL     sliced ELL: slices of C rows stored column-major, one lane per
+//            row, fully coalesced, no reduction; rows keep their own length
+//            so padding is never read.
+//   ADAPTIVE precomputed row blocks: runs of short rows whose entries fit an
+//            LDS tile are streamed into LDS with coalesced loads and summed
+//            per row from LDS; rows of medium length get one wavefront,
+//            very long rows one whole workgroup.
+// Products are formed and accumulated in FP64 (FP32 operands are widened
+// first, so their products are exact) and each output is rounded once.
+#include "device_common.h"
+#include "device_rows.h"
+#include "kernels.h"
+
+namespace spk {
+
+template <typename T, bool FUSED>
+__device__ __forceinline__ void store_row(const SpmvArgs<T> &a, int row, double acc)
+{
+    const T yt = (T)acc;
+    a.y[row] = yt;
+    if constexpr (FUSED) a.w[row] = fma_t(a.alpha, yt, a.x[row]);
+}
+
+// --------------------------------------------------------------- SCALAR --
+
+template <typename T, int BS, int UNR, bool FUSED>
+__global__ __launch_bounds__(BS) void k_spmv_scalar(SpmvArgs<T> a)
+{
+    const int row = a.row0 + (int)blockIdx.x * BS + (int)threadIdx.x;
+    if (row >= a.row0 + a.m) return;
+    const int s = a.rp[row], e = a.rp[row + 1];
+    double acc[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) acc[u] = 0.0;
+    int k = s;
+    for (; k + UNR <= e; k += UNR) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            acc[u] = fma_t((double)a.val[k + u], (double)a.x[a.ci[k + u]], acc[u]);
+    }
+    for (; k < e; ++k) acc[0] = fma_t((double)a.val[k], (double)a.x[a.ci[k]], acc[0]);
+    double sum = acc[0];
+#pragma unroll
+    for (int u = 1; u < UNR; ++u) sum += acc[u];
+    store_row<T, FUSED>(a, row, sum);
+}
+
+// --------------------------------------------------------------- VECTOR --
+
+template <typename T, int BS, int G, int UNR, bool LDSRP, bool FUSED>
+__global__ __launch_bounds__(BS) void k_spmv_vector(SpmvArgs<T> a)
+{
+    constexpr int RPB = BS / G;  // rows per workgroup
+    const int t = threadIdx.x;
+    const int lane = t & (G - 1);
+    const int rbase = a.row0 + (int)blockIdx.x * RPB;
+    const int rend = a.row0 + a.m;
+    const int row = rbase + t / G;
+    int s = 0, e = 0;
+    if constexpr (LDSRP) {
+        __shared__ int srp[RPB + 1];
+        for (int i = t; i <= RPB; i += BS) srp[i] = a.rp[min(rbase + i, rend)];
+        __syncthreads();
+        s = srp[t / G];
+        e = srp[t / G + 1];
+    } else if (row < rend) {
+        s = a.rp[row];
+        e = a.rp[row + 1];
+    }
+    double acc[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) acc[u] = 0.0;
+    for (int k = s + lane; k < e; k += G * UNR) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int kk = k + u * G;
+            if (kk < e) acc[u] = fma_t((double)a.val[kk], (double)a.x[a.ci[kk]], acc[u]);
+        }
+    }
+    double sum = acc[0];
+#pragma unroll
+    for (int u = 1; u < UNR; ++u) sum += acc[u];
+    sum = group_sum<G>(sum);  // every lane of the wavefront takes part
+    if (lane == 0 && row < rend) store_row<T, FUSED>(a, row, sum);
+}
+
+// ----------------------------------------------------------------- SELL --
+
+template <typename T, int BS, int C, int UNR, bool FUSED>
+__global__ __launch_bounds__(BS) void k_spmv_sell(SpmvArgs<T> a)
+{
+    const int row = a.row0 + (int)blockIdx.x * BS + (int)threadIdx.x;
+    if (row >= a.row0 + a.m) return;
+    const int slice = row / C;
+    const int64_t base = a.sell_ptr[slice] + (row - slice * C);
+    const int len = a.sell_len[row];
+    double acc[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) acc[u] = 0.0;
+    int k = 0;
+    for (; k + UNR <= len; k += UNR) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int64_t p = base + (int64_t)(k + u) * C;
+            acc[u] = fma_t((double)a.sell_val[p], (double)a.x[a.sell_ci[p]], acc[u]);
+        }
+    }
+    for (; k < len; ++k) {
+        const int64_t p = base + (int64_t)k * C;
+        acc[0] = fma_t((double)a.sell_val[p], (double)a.x[a.sell_ci[p]], acc[0]);
+    }
+    double sum = acc[0];
+#pragma unroll
+    for (int u = 1; u < UNR; ++u) sum += acc[u];
+    store_row<T, FUSED>(a, row, sum);
+}
+
+// ------------------------------------------------------------- ADAPTIVE --
+
+template <typename T, int BS, int TILE, bool FUSED>
+__global__ __launch_bounds__(BS) void k_spmv_adaptive(SpmvArgs<T> a)
+{
+    __shared__ T sv[TILE];
+    __shared__ T sx[TILE];
+    __shared__ double red[BS / kWave];
+    const int b = a.blk0 + (int)blockIdx.x;
+    const uint32_t e0 = a.blocks[b], e1 = a.blocks[b + 1];
+    const int r0 = (int)(e0 & kBlkRowMask), r1 = (int)(e1 & kBlkRowMask);
+    const uint32_t mode = e0 >> 30;
+    T *w = FUSED ? a.w : nullptr;
+    if (mode == kBlkStream) {
+        stream_rows<T, BS, TILE>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, r1, sv, sx);
+    } else if (mode == kBlkWave) {
+        group_rows<T, BS, kWave>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, r1);
+    } else {
+        block_row<T, BS>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, red);
+    }
+}
+
+// ------------------------------------------------------------ registry --
+
+namespace {
+
+template <typename T, int BS, int UNR, bool F>
+hipError_t L_scalar(const void *p, dim3 g, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_spmv_scalar<T, BS, UNR, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
+    return hipGetLastError();
+}
+
+template <typename T, int BS, int G, int UNR, bool LDSRP, bool F>
+hipError_t L_vector(const void *p, dim3 g, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_spmv_vector<T, BS, G, UNR, LDSRP, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
+    return hipGetLastError();
+}
+
+template <typename T, int BS, int C, int UNR, bool F>
+hipError_t L_sell(const void *p, dim3 g, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_spmv_sell<T, BS, C, UNR, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
+    return hipGetLastError();
+}
+
+template <typename T, int BS, int TILE, bool F>
+hipError_t L_adaptive(const void *p, dim3 g, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_spmv_adaptive<T, BS, TILE, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
+    return hipGetLastError();
+}
+
+#define FN4(L, ...) {{L<float, __VA_ARGS__, false>, L<float, __VA_ARGS__, true>}, \
+                     {L<double, __VA_ARGS__, false>, L<double, __VA_ARGS__, true>}}
+
+// format, block, group, unroll, lds
+#define SCALAR(BS, U) {1, BS, 1, U, 0, FN4(L_scalar, BS, U)}
+#define VECTOR(BS, G, U) {2, BS, G, U, 0, FN4(L_vector, BS, G, U, false)}
+#define VECTOR_LDS(BS, G) {2, BS, G, 1, 1, FN4(L_vector, BS, G, 1, true)}
+#define SELL(C, U) {3, 256, C, U, 0, FN4(L_sell, 256, C, U)}
+#define ADAPT(BS, TILE) {4, BS, 1, 1, TILE, FN4(L_adaptive, BS, TILE)}
+
+#define VECTOR_U(BS, G) VECTOR(BS, G, 1), VECTOR(BS, G, 2), VECTOR(BS, G, 4)
+#define VECTOR_G(BS) VECTOR_U(BS, 2), VECTOR_U(BS, 4), VECTOR_U(BS, 8), VECTOR_U(BS, 16), \
+                     VECTOR_U(BS, 32), VECTOR_U(BS, 64)
+
+const SpmvEntry kSpmv[] = {
+    // plain variants first: thread per row, wavefront per row (256 threads)
+    SCALAR(256, 1), VECTOR(256, 64, 1),
+    SCALAR(64, 1), SCALAR(128, 1), SCALAR(512, 1),
+    SCALAR(64, 2), SCALAR(128, 2), SCALAR(256, 2), SCALAR(512, 2),
+    SCALAR(64, 4), SCALAR(128, 4), SCALAR(256, 4), SCALAR(512, 4),
+    VECTOR_U(128, 2), VECTOR_U(128, 4), VECTOR_U(128, 8), VECTOR_U(128, 16), VECTOR_U(128, 32), VECTOR_U(128, 64),
+    VECTOR_U(256, 2), VECTOR_U(256, 4), VECTOR_U(256, 8), VECTOR_U(256, 16), VECTOR_U(256, 32),
+    VECTOR(256, 64, 2), VECTOR(256, 64, 4),
+    VECTOR_G(512),
+    VECTOR_LDS(256, 2), VECTOR_LDS(256, 4), VECTOR_LDS(256, 8), VECTOR_LDS(256, 16),
+    SELL(32, 1), SELL(32, 2), SELL(32, 4),
+    SELL(64, 1), SELL(64, 2), SELL(64, 4),
+    SELL(128, 1), SELL(128, 2), SELL(128, 4),
+    SELL(256, 1), SELL(256, 2), SELL(256, 4),
+    ADAPT(128, 512), ADAPT(128, 1024), ADAPT(128, 2048), ADAPT(128, 4096),
+    ADAPT(256, 512), ADAPT(256, 1024), ADAPT(256, 2048), ADAPT(256, 4096),
+    ADAPT(512, 512), ADAPT(512, 1024), ADAPT(512, 2048), ADAPT(512, 4096),
+};
+
+}  // namespace
+
+const SpmvEntry *spmv_table(int *count)
+{
+    *count = (int)(sizeof(kSpmv) / sizeof(kSpmv[0]));
+    return kSpmv;
+}
+
+}  // namespace spk

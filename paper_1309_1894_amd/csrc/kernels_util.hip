@@ -1,0 +1,267 @@
+// kernels_util.hip -- support kernels: output validation for the tuner,
+// tolerance scales, cache eviction, STREAM probes, CSR checks and the
+// CSR -> sliced-ELL conversion.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace spk {
+
+namespace {
+
+constexpr int kBS = 256;
+
+inline unsigned grid_for(int64_t n, int per_thread = 1)
+{
+    int64_t g = (n + (int64_t)kBS * per_thread - 1) / ((int64_t)kBS * per_thread);
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (unsigned)g;
+}
+
+__device__ __forceinline__ int64_t ord_of(double v)
+{
+    const long long b = __double_as_longlong(v);
+    return b < 0 ? -(int64_t)(b & 0x7fffffffffffffffll) : (int64_t)b;
+}
+
+__device__ __forceinline__ int64_t ord_of(float v)
+{
+    const int b = __float_as_int(v);
+    return b < 0 ? -(int64_t)(b & 0x7fffffff) : (int64_t)b;
+}
+
+}  // namespace
+
+// mode 0: |out - ref| <= tau*scale (scale null -> exact match)
+// mode 1: out within one ulp of ref rounded to T
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_check(int mode, int64_t n, const T *out, const double *ref,
+                                              const double *scale, double tau, unsigned long long *bad)
+{
+    unsigned long long local = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) {
+        const double r = ref[i];
+        const T o = out[i];
+        bool ok;
+        if (__builtin_isnan(r)) {
+            ok = __builtin_isnan(o);
+        } else if (__builtin_isinf(r)) {
+            ok = ((double)o == r);
+        } else if (__builtin_isnan(o)) {
+            ok = false;
+        } else if (mode == 1) {
+            const int64_t d = ord_of(o) - ord_of((T)r);
+            ok = (d >= -1 && d <= 1);
+        } else {
+            const double lim = scale ? tau * scale[i] : 0.0;
+            ok = __builtin_fabs((double)o - r) <= lim;
+        }
+        local += ok ? 0ull : 1ull;
+    }
+    if (local) atomicAdd(bad, local);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_widen(int64_t n, const T *in, double *out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS)
+        out[i] = (double)in[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_row_absum(int32_t m, const int32_t *rp, const int32_t *ci, const T *val,
+                                                  const T *x, double *scale)
+{
+    const int r = blockIdx.x * kBS + threadIdx.x;
+    if (r >= m) return;
+    double s = 0.0;
+    for (int k = rp[r]; k < rp[r + 1]; ++k) s += __builtin_fabs((double)val[k] * (double)x[ci[k]]);
+    scale[r] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_dot_absum(int64_t n, const T *x, const T *y, double *out)
+{
+    __shared__ double red[kBS / kWave];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS)
+        s += __builtin_fabs((double)x[i] * (double)y[i]);
+    s = block_sum<kBS>(s, red);
+    if (threadIdx.x == 0) atomicAdd(out, s);
+}
+
+__global__ __launch_bounds__(kBS) void k_fill(uint4 *p, int64_t n16, uint32_t pattern)
+{
+    const uint4 v = make_uint4(pattern, pattern ^ 0x9E3779B9u, pattern + 1u, ~pattern);
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n16; i += (int64_t)gridDim.x * kBS)
+        p[i] = v;
+}
+
+// STREAM copy: 16-byte accesses, grid-stride.
+__global__ __launch_bounds__(kBS) void k_copy(int64_t n2, const double2 *a, double2 *b)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n2; i += (int64_t)gridDim.x * kBS)
+        b[i] = a[i];
+}
+
+__global__ __launch_bounds__(kBS) void k_copy_tail(int64_t lo, int64_t n, const double *a, double *b)
+{
+    const int64_t i = lo + (int64_t)blockIdx.x * kBS + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+__global__ __launch_bounds__(kBS) void k_triad(int64_t n2, const double2 *a, const double2 *b, double s,
+                                              double2 *c)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n2; i += (int64_t)gridDim.x * kBS) {
+        const double2 u = a[i], v = b[i];
+        c[i] = make_double2(__builtin_fma(s, v.x, u.x), __builtin_fma(s, v.y, u.y));
+    }
+}
+
+__global__ __launch_bounds__(kBS) void k_triad_tail(int64_t lo, int64_t n, const double *a, const double *b,
+                                                   double s, double *c)
+{
+    const int64_t i = lo + (int64_t)blockIdx.x * kBS + threadIdx.x;
+    if (i < n) c[i] = __builtin_fma(s, b[i], a[i]);
+}
+
+__global__ __launch_bounds__(kBS) void k_colcheck(int64_t nnz, const int32_t *ci, int64_t ncols,
+                                                 unsigned long long *bad)
+{
+    unsigned long long local = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * kBS) {
+        const int32_t c = ci[i];
+        local += (c < 0 || (int64_t)c >= ncols) ? 1ull : 0ull;
+    }
+    if (local) atomicAdd(bad, local);
+}
+
+// One lane per row: copy row r's entries, in order, into column k of its
+// slice (entry (r, k) at sell_ptr[slice] + k*C + r%C).  Padding slots keep
+// whatever the caller initialised them to; kernels never read them.
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_csr_to_sell(int32_t m, int32_t C, const int32_t *rp, const int32_t *ci,
+                                                    const T *val, const int64_t *sell_ptr, int32_t *sell_len,
+                                                    int32_t *sell_ci, T *sell_val)
+{
+    const int r = blockIdx.x * kBS + threadIdx.x;
+    if (r >= m) return;
+    const int s = rp[r], e = rp[r + 1];
+    const int slice = r / C;
+    const int64_t base = sell_ptr[slice] + (r - slice * C);
+    sell_len[r] = e - s;
+    for (int k = s; k < e; ++k) {
+        sell_ci[base + (int64_t)(k - s) * C] = ci[k];
+        sell_val[base + (int64_t)(k - s) * C] = val[k];
+    }
+}
+
+// ----------------------------------------------------------- launchers --
+
+hipError_t launch_check(int dtype, int mode, int64_t n, const void *out, const double *ref,
+                        const double *scale, double tau, unsigned long long *bad, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_check<double>, dim3(grid_for(n, 4)), dim3(kBS), 0, s, mode, n, (const double *)out,
+                           ref, scale, tau, bad);
+    else
+        hipLaunchKernelGGL(k_check<float>, dim3(grid_for(n, 4)), dim3(kBS), 0, s, mode, n, (const float *)out,
+                           ref, scale, tau, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_widen(int dtype, int64_t n, const void *in, double *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_widen<double>, dim3(grid_for(n, 4)), dim3(kBS), 0, s, n, (const double *)in, out);
+    else
+        hipLaunchKernelGGL(k_widen<float>, dim3(grid_for(n, 4)), dim3(kBS), 0, s, n, (const float *)in, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_absum(int dtype, int32_t m, const int32_t *rp, const int32_t *ci, const void *val,
+                            const void *x, double *scale, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    const dim3 g((unsigned)((m + kBS - 1) / kBS));
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_row_absum<double>, g, dim3(kBS), 0, s, m, rp, ci, (const double *)val,
+                           (const double *)x, scale);
+    else
+        hipLaunchKernelGGL(k_row_absum<float>, g, dim3(kBS), 0, s, m, rp, ci, (const float *)val,
+                           (const float *)x, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot_absum(int dtype, int64_t n, const void *x, const void *y, double *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_dot_absum<double>, dim3(grid_for(n, 8)), dim3(kBS), 0, s, n, (const double *)x,
+                           (const double *)y, out);
+    else
+        hipLaunchKernelGGL(k_dot_absum<float>, dim3(grid_for(n, 8)), dim3(kBS), 0, s, n, (const float *)x,
+                           (const float *)y, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(void *p, int64_t n, uint32_t pattern, hipStream_t s)
+{
+    const int64_t n16 = n / 16;
+    if (n16 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n16, 8)), dim3(kBS), 0, s, (uint4 *)p, n16, pattern);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(int64_t n, const double *a, double *b, hipStream_t s)
+{
+    const int64_t n2 = n / 2;
+    if (n2 > 0) {
+        hipLaunchKernelGGL(k_copy, dim3(grid_for(n2, 8)), dim3(kBS), 0, s, n2, (const double2 *)a, (double2 *)b);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n & 1) hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(kBS), 0, s, n - 1, n, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_triad(int64_t n, const double *a, const double *b, double s_, double *c, hipStream_t s)
+{
+    const int64_t n2 = n / 2;
+    if (n2 > 0) {
+        hipLaunchKernelGGL(k_triad, dim3(grid_for(n2, 8)), dim3(kBS), 0, s, n2, (const double2 *)a,
+                           (const double2 *)b, s_, (double2 *)c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n & 1) hipLaunchKernelGGL(k_triad_tail, dim3(1), dim3(kBS), 0, s, n - 1, n, a, b, s_, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_colcheck(int64_t nnz, const int32_t *ci, int64_t ncols, unsigned long long *bad,
+                               hipStream_t s)
+{
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_colcheck, dim3(grid_for(nnz, 8)), dim3(kBS), 0, s, nnz, ci, ncols, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_to_sell(int dtype, int32_t m, int32_t C, const int32_t *rp, const int32_t *ci,
+                              const void *val, const int64_t *sell_ptr, int32_t *sell_len, int32_t *sell_ci,
+                              void *sell_val, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    const dim3 g((unsigned)((m + kBS - 1) / kBS));
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_csr_to_sell<double>, g, dim3(kBS), 0, s, m, C, rp, ci, (const double *)val, sell_ptr,
+                           sell_len, sell_ci, (double *)sell_val);
+    else
+        hipLaunchKernelGGL(k_csr_to_sell<float>, g, dim3(kBS), 0, s, m, C, rp, ci, (const float *)val, sell_ptr,
+                           sell_len, sell_ci, (float *)sell_val);
+    return hipGetLastError();
+}
+
+}  // namespace spk

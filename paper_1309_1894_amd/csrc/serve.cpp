@@ -1,0 +1,708 @@
+// serve.cpp -- a continuous-batching request loop for the Krylov-style step
+// (y = A*x, w = alpha*y + x) over a pool of matrices.
+//
+// A scheduler thread owns the GPU side.  Each turn it
+//   1. retires finished launches (event query): copies results to the
+//      callers' buffers, stamps completion times, frees slots and bytes;
+//   2. admits queued requests in arrival order while a request slot is free
+//      and the HBM budget covers the request's vectors plus, if its matrix
+//      is not resident, the matrix (idle matrices are evicted least recently
+//      used first to make room; a matrix in use is never evicted);
+//   3. launches the admitted group as one batched tile kernel on the next of
+//      its streams, so groups admitted while others run overlap on the GPU.
+// The tile kernel is the batched one, with each matrix cut into tiles by the
+// kernel of its shape class, so a request's result does not depend on what
+// it was batched with.  Mode 1 is the baseline: one request at a time with
+// the plain unbatched kernels (SpMV, then WAXPY).
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <thread>
+#include <vector>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace spk {
+
+namespace {
+
+size_t round_pow2(size_t n)
+{
+    size_t p = 256;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// Recycles device or pinned host blocks by power-of-two size.
+struct Pool {
+    bool device;
+    std::multimap<size_t, void *> free_;
+    std::map<void *, size_t> size_of;
+    int64_t held = 0;
+    hipError_t get(size_t n, void **out)
+    {
+        const size_t sz = round_pow2(n);
+        auto it = free_.find(sz);
+        if (it != free_.end()) {
+            *out = it->second;
+            free_.erase(it);
+            return hipSuccess;
+        }
+        hipError_t e = device ? hipMalloc(out, sz) : hipHostMalloc(out, sz, hipHostMallocDefault);
+        if (e == hipSuccess) {
+            size_of[*out] = sz;
+            held += (int64_t)sz;
+        }
+        return e;
+    }
+    void put(void *p)
+    {
+        if (p) free_.emplace(size_of[p], p);
+    }
+    void release_all()
+    {
+        for (auto &kv : size_of) {
+            if (device) (void)hipFree(kv.first);
+            else (void)hipHostFree(kv.first);
+        }
+        free_.clear();
+        size_of.clear();
+        held = 0;
+    }
+};
+
+struct PoolMat {
+    int32_t dtype = SPK_F64;
+    int64_t m = 0, n = 0, nnz = 0;
+    int32_t *h_rp = nullptr, *h_ci = nullptr;
+    void *h_val = nullptr;
+    bool h_pinned = false;
+    int32_t *d_rp = nullptr, *d_ci = nullptr;
+    void *d_val = nullptr;
+    int64_t dev_bytes = 0;
+    bool resident = false;
+    int refs = 0;
+    double last_use = 0.0;
+    hipEvent_t uploaded = nullptr;
+    std::vector<BatchTile> tiles;   // tiles of this matrix (inst field 0)
+};
+
+struct Request {
+    int32_t mat = 0;
+    const void *x = nullptr;
+    void *y = nullptr;
+    void *w = nullptr;
+    double t_arrival = 0.0, t_done = -1.0;
+};
+
+struct Flight {
+    std::vector<std::pair<int64_t, Request>> reqs;
+    std::vector<int64_t> off;   // vector offset of each request
+    void *dev = nullptr, *pin = nullptr;
+    size_t y_off = 0, w_off = 0;
+    int64_t vec_bytes = 0;
+    hipEvent_t done = nullptr;
+    int dtype = SPK_F64;
+};
+
+}  // namespace
+
+}  // namespace spk
+
+struct spk_server_s {
+    spk_handle h = nullptr;
+    spk_serve_opts opts{};
+    const spk::BatchEntry *entry = nullptr;
+    std::vector<hipStream_t> streams;
+    hipStream_t upload = nullptr;
+    int next_stream = 0;
+    std::deque<spk::PoolMat> mats;          // guarded by mats_mu
+    std::mutex mats_mu;                     // held by the scheduler for a whole turn
+    std::atomic<int32_t> nmats{0};
+    std::vector<spk::Request> reqs;        // by id, guarded by mu (stats)
+    std::deque<std::pair<int64_t, spk::Request>> incoming;   // guarded by mu
+    std::deque<std::pair<int64_t, spk::Request>> pending;    // scheduler only
+    std::vector<spk::Flight> flights;
+    std::vector<hipEvent_t> spare_events;
+    spk::Pool dpool{true}, hpool{false};
+    int64_t used_mat = 0, used_vec = 0, peak = 0;
+    int64_t inflight = 0;
+    int64_t completed = 0, rejected = 0, batches = 0, uploads = 0, evictions = 0;
+    double first_arrival = -1.0, last_done = 0.0, bytes_moved = 0.0;
+    std::vector<int64_t> done_ids;
+    std::mutex mu;
+    std::condition_variable cv_in, cv_done;
+    bool stop = false;
+    spk_status error = SPK_OK;
+    char error_msg[512] = {0};
+    std::thread thr;
+};
+
+namespace spk {
+
+namespace {
+
+using Server = spk_server_s;
+
+hipEvent_t take_event(Server *S)
+{
+    if (!S->spare_events.empty()) {
+        hipEvent_t e = S->spare_events.back();
+        S->spare_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    return e;
+}
+
+int64_t vec_bytes_of(const PoolMat &M) { return (M.n + 2 * M.m) * (int64_t)dtype_size(M.dtype); }
+
+spk_status make_resident(Server *S, PoolMat &M)
+{
+    const size_t vs = dtype_size(M.dtype);
+    SPK_HIP(hipMalloc(&M.d_rp, sizeof(int32_t) * (M.m + 1)));
+    SPK_HIP(hipMalloc(&M.d_ci, sizeof(int32_t) * std::max<int64_t>(1, M.nnz)));
+    SPK_HIP(hipMalloc(&M.d_val, vs * std::max<int64_t>(1, M.nnz)));
+    SPK_HIP(hipMemcpyAsync(M.d_rp, M.h_rp, sizeof(int32_t) * (M.m + 1), hipMemcpyHostToDevice, S->upload));
+    if (M.nnz) {
+        SPK_HIP(hipMemcpyAsync(M.d_ci, M.h_ci, sizeof(int32_t) * M.nnz, hipMemcpyHostToDevice, S->upload));
+        SPK_HIP(hipMemcpyAsync(M.d_val, M.h_val, vs * M.nnz, hipMemcpyHostToDevice, S->upload));
+    }
+    if (!M.uploaded) SPK_HIP(hipEventCreateWithFlags(&M.uploaded, hipEventDisableTiming));
+    SPK_HIP(hipEventRecord(M.uploaded, S->upload));
+    M.resident = true;
+    S->used_mat += M.dev_bytes;
+    ++S->uploads;
+    return SPK_OK;
+}
+
+void evict(Server *S, PoolMat &M)
+{
+    // idle: no launch references it (refs == 0 and its last launch retired)
+    (void)hipEventSynchronize(M.uploaded);
+    (void)hipFree(M.d_rp);
+    (void)hipFree(M.d_ci);
+    (void)hipFree(M.d_val);
+    M.d_rp = M.d_ci = nullptr;
+    M.d_val = nullptr;
+    M.resident = false;
+    S->used_mat -= M.dev_bytes;
+    ++S->evictions;
+}
+
+// Frees room for `need` bytes by evicting idle matrices (LRU), never those
+// listed in `keep`.  Returns whether the budget now covers `need`.
+bool make_room(Server *S, int64_t need, const std::vector<int32_t> &keep)
+{
+    const int64_t budget = S->opts.hbm_budget;
+    while (S->used_mat + S->used_vec + need > budget) {
+        int32_t victim = -1;
+        double oldest = 1e300;
+        for (size_t i = 0; i < S->mats.size(); ++i) {
+            const PoolMat &M = S->mats[i];
+            if (!M.resident || M.refs > 0) continue;
+            if (std::find(keep.begin(), keep.end(), (int32_t)i) != keep.end()) continue;
+            if (M.last_use < oldest) {
+                oldest = M.last_use;
+                victim = (int32_t)i;
+            }
+        }
+        if (victim < 0) return false;
+        evict(S, S->mats[victim]);
+    }
+    return true;
+}
+
+void set_error(Server *S, spk_status st)
+{
+    if (S->error == SPK_OK) {
+        S->error = st;
+        snprintf(S->error_msg, sizeof S->error_msg, "%s", spk_last_error());
+    }
+}
+
+// Launches a group of admitted requests (all of one dtype).
+spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &group)
+{
+    const int dtype = S->mats[group[0].second.mat].dtype;
+    const size_t vs = dtype_size(dtype);
+    Flight F;
+    F.dtype = dtype;
+    F.reqs = group;
+    std::vector<BatchInst> inst;
+    std::vector<BatchTile> tiles;
+    int64_t total = 0;
+    for (size_t k = 0; k < group.size(); ++k) {
+        const PoolMat &M = S->mats[group[k].second.mat];
+        F.off.push_back(total);
+        inst.push_back(BatchInst{M.d_rp, M.d_ci, M.d_val, total, (int32_t)M.m, 0});
+        for (BatchTile t : M.tiles) {
+            t.inst = (int32_t)k;
+            tiles.push_back(t);
+        }
+        total += M.m;
+    }
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t inst_b = al(sizeof(BatchInst) * inst.size());
+    const size_t tile_b = al(sizeof(BatchTile) * std::max<size_t>(1, tiles.size()));
+    const size_t vec_b = al(vs * (size_t)std::max<int64_t>(1, total));
+    const size_t in_b = inst_b + tile_b + vec_b;
+    F.y_off = in_b;
+    F.w_off = in_b + vec_b;
+    const size_t all_b = in_b + 2 * vec_b;
+    SPK_HIP(S->dpool.get(all_b, &F.dev));
+    SPK_HIP(S->hpool.get(all_b, &F.pin));
+    char *pin = (char *)F.pin;
+    memcpy(pin, inst.data(), sizeof(BatchInst) * inst.size());
+    memcpy(pin + inst_b, tiles.data(), sizeof(BatchTile) * tiles.size());
+    for (size_t k = 0; k < group.size(); ++k) {
+        const Request &R = group[k].second;
+        const PoolMat &M = S->mats[R.mat];
+        memcpy(pin + inst_b + tile_b + vs * F.off[k], R.x, vs * M.n);
+    }
+    hipStream_t s = S->streams[S->next_stream];
+    S->next_stream = (S->next_stream + 1) % (int)S->streams.size();
+    for (const auto &g : group) SPK_HIP(hipStreamWaitEvent(s, S->mats[g.second.mat].uploaded, 0));
+    char *dev = (char *)F.dev;
+    SPK_HIP(hipMemcpyAsync(dev, pin, in_b, hipMemcpyHostToDevice, s));
+    const void *x = dev + inst_b + tile_b;
+    void *y = dev + F.y_off;
+    void *w = dev + F.w_off;
+    if (S->opts.mode == 1) {
+        // baseline: the plain unbatched kernels, SpMV then WAXPY
+        const PoolMat &M = S->mats[group[0].second.mat];
+        spk_csr view{M.m, M.n, M.nnz, M.dtype, M.d_rp, M.d_ci, M.d_val};
+        SpmvProblem q;
+        q.csr = &view;
+        q.x = x;
+        q.y = y;
+        const spk_variant pv = plain_variant(SPK_OP_SPMV, M.nnz > 8 * M.m ? 1 : 0);
+        SPK_TRY(run_spmv(S->h, q, pv, s));
+        SPK_TRY(run_waxpy(S->h, M.dtype, M.m, S->opts.alpha, y, x, w, plain_variant(SPK_OP_WAXPY, 0), s));
+    } else {
+        SPK_TRY(launch_tiles(S->entry, dtype, (const BatchInst *)dev, (const BatchTile *)(dev + inst_b),
+                             (int64_t)tiles.size(), S->opts.alpha, x, y, w, nullptr, 0, s));
+    }
+    SPK_HIP(hipMemcpyAsync(pin + F.y_off, y, 2 * vec_b, hipMemcpyDeviceToHost, s));
+    F.done = take_event(S);
+    SPK_HIP(hipEventRecord(F.done, s));
+    F.vec_bytes = 0;
+    for (const auto &g : group) F.vec_bytes += vec_bytes_of(S->mats[g.second.mat]);
+    ++S->batches;
+    S->flights.push_back(std::move(F));
+    return SPK_OK;
+}
+
+bool retire(Server *S)
+{
+    bool any = false;
+    for (size_t i = 0; i < S->flights.size();) {
+        Flight &F = S->flights[i];
+        if (hipEventQuery(F.done) != hipSuccess) {
+            ++i;
+            continue;
+        }
+        const size_t vs = dtype_size(F.dtype);
+        const double t = now_seconds();
+        const char *pin = (const char *)F.pin;
+        std::vector<std::pair<int64_t, double>> ids;
+        for (size_t k = 0; k < F.reqs.size(); ++k) {
+            const Request &R = F.reqs[k].second;
+            PoolMat &M = S->mats[R.mat];
+            memcpy(R.y, pin + F.y_off + vs * F.off[k], vs * M.m);
+            if (R.w) memcpy(R.w, pin + F.w_off + vs * F.off[k], vs * M.m);
+            M.refs--;
+            M.last_use = t;
+            S->bytes_moved += (double)spmv_bytes(M.m, M.n, M.nnz, M.dtype, true);
+            ids.emplace_back(F.reqs[k].first, now_seconds());
+        }
+        S->dpool.put(F.dev);
+        S->hpool.put(F.pin);
+        S->spare_events.push_back(F.done);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->used_vec -= F.vec_bytes;
+            S->inflight -= (int64_t)F.reqs.size();
+            S->completed += (int64_t)F.reqs.size();
+            S->last_done = t;
+            for (const auto &d : ids) {
+                S->reqs[d.first].t_done = d.second;
+                S->done_ids.push_back(d.first);
+            }
+        }
+        S->cv_done.notify_all();
+        S->flights.erase(S->flights.begin() + (long)i);
+        any = true;
+    }
+    return any;
+}
+
+bool admit(Server *S)
+{
+    if (S->opts.mode == 1 && !S->flights.empty()) return false;
+    std::vector<std::pair<int64_t, Request>> group;
+    std::vector<int32_t> keep;
+    int group_dtype = -1;
+    int64_t group_vec = 0;
+    const int64_t max_group = S->opts.mode == 1 ? 1 : S->opts.max_batch;
+    while (!S->pending.empty() && (int64_t)group.size() < max_group &&
+           S->inflight + (int64_t)group.size() < S->opts.max_inflight) {
+        const Request &R = S->pending.front().second;
+        PoolMat &M = S->mats[R.mat];
+        if (group_dtype >= 0 && M.dtype != group_dtype) break;
+        const int64_t need = group_vec + vec_bytes_of(M) + (M.resident ? 0 : M.dev_bytes);
+        keep.push_back(R.mat);
+        if (!make_room(S, need, keep)) {
+            keep.pop_back();
+            break;  // head of the queue waits for memory (no overtaking)
+        }
+        if (!M.resident) {
+            spk_status st = make_resident(S, M);
+            if (st != SPK_OK) {
+                set_error(S, st);
+                break;
+            }
+        }
+        M.refs++;
+        M.last_use = now_seconds();
+        group_dtype = M.dtype;
+        group_vec += vec_bytes_of(M);
+        group.push_back(S->pending.front());
+        S->pending.pop_front();
+    }
+    if (group.empty()) return false;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->inflight += (int64_t)group.size();
+        S->used_vec += group_vec;
+        S->peak = std::max(S->peak, S->used_mat + S->used_vec);
+    }
+    spk_status st = launch_group(S, group);
+    if (st != SPK_OK) set_error(S, st);
+    return true;
+}
+
+void scheduler(Server *S)
+{
+    (void)hipSetDevice(S->h->device);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->incoming.empty() && S->pending.empty() && S->flights.empty()) {
+                if (S->stop) break;
+                S->cv_in.wait_for(lk, std::chrono::milliseconds(2));
+            }
+            while (!S->incoming.empty()) {
+                S->pending.push_back(S->incoming.front());
+                S->incoming.pop_front();
+            }
+            if (S->stop && S->error != SPK_OK) {
+                // drop what cannot run
+                S->pending.clear();
+            }
+        }
+        bool progress;
+        {
+            std::lock_guard<std::mutex> mk(S->mats_mu);
+            progress = retire(S);
+            if (S->error == SPK_OK) progress = admit(S) || progress;
+        }
+        if (!progress && !S->flights.empty()) std::this_thread::yield();
+        if (S->error != SPK_OK) {
+            // unblock waiters: count dropped requests as rejected
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->rejected += (int64_t)S->pending.size();
+            S->completed += (int64_t)S->pending.size();
+            S->pending.clear();
+            S->cv_done.notify_all();
+        }
+    }
+}
+
+double percentile(std::vector<double> v, double q)
+{
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    const double pos = q * (double)(v.size() - 1);
+    const size_t i = (size_t)pos;
+    const double f = pos - (double)i;
+    return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
+}
+
+}  // namespace
+
+}  // namespace spk
+
+using namespace spk;
+
+extern "C" {
+
+spk_status spk_serve_create(spk_handle h, const spk_serve_opts *opts, spk_server *out)
+{
+    if (!h || !out) return fail(SPK_ERR_NULL, "handle/out is NULL");
+    *out = nullptr;
+    spk_serve_opts o{};
+    if (opts) o = *opts;
+    if (o.streams <= 0) o.streams = 4;
+    if (o.max_inflight <= 0) o.max_inflight = 256;
+    if (o.max_batch <= 0) o.max_batch = 64;
+    if (o.hbm_budget <= 0) o.hbm_budget = 200ll * 1000 * 1000 * 1000;
+    if (o.mode != 0 && o.mode != 1) return fail(SPK_ERR_ARG, "mode must be 0 or 1");
+    if (o.streams > 16) return fail(SPK_ERR_ARG, "at most 16 streams");
+    DeviceGuard g(h);
+    Server *S = new Server();
+    S->h = h;
+    S->opts = o;
+    S->entry = batch_entry(256, 2048);
+    for (int i = 0; i < (o.mode == 1 ? 1 : o.streams); ++i) {
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            spk_serve_destroy(S);
+            return fail(SPK_ERR_HIP, "stream creation failed");
+        }
+        S->streams.push_back(s);
+    }
+    if (hipStreamCreateWithFlags(&S->upload, hipStreamNonBlocking) != hipSuccess) {
+        spk_serve_destroy(S);
+        return fail(SPK_ERR_HIP, "stream creation failed");
+    }
+    S->thr = std::thread(scheduler, S);
+    *out = S;
+    return SPK_OK;
+}
+
+spk_status spk_serve_add_matrix(spk_server S, const spk_csr *A, int32_t *id)
+{
+    if (!S || !A || !id) return fail(SPK_ERR_NULL, "NULL argument");
+    if (!dtype_ok(A->dtype)) return fail(SPK_ERR_DTYPE, "bad dtype %d", A->dtype);
+    if (A->nrows < 0 || A->nnz < 0 || A->nrows != A->ncols) return fail(SPK_ERR_SHAPE, "the step needs a square matrix");
+    if (A->nnz >= (1ll << 31) || A->nrows >= (1ll << 30)) return fail(SPK_ERR_SHAPE, "matrix too large");
+    if (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val))) return fail(SPK_ERR_NULL, "CSR arrays are NULL");
+    const int32_t *rp = A->row_ptr;
+    if (rp[0] != 0 || rp[A->nrows] != A->nnz) return fail(SPK_ERR_CSR, "row_ptr does not span [0, nnz]");
+    for (int64_t i = 0; i < A->nrows; ++i)
+        if (rp[i + 1] < rp[i]) return fail(SPK_ERR_CSR, "row_ptr decreases at row %lld", (long long)i);
+    for (int64_t k = 0; k < A->nnz; ++k)
+        if (A->col_idx[k] < 0 || A->col_idx[k] >= A->ncols) return fail(SPK_ERR_CSR, "column index out of range");
+    PoolMat M;
+    M.dtype = A->dtype;
+    M.m = A->nrows;
+    M.n = A->ncols;
+    M.nnz = A->nnz;
+    const size_t vs = dtype_size(A->dtype);
+    DeviceGuard g(S->h);
+    const size_t brp = sizeof(int32_t) * (M.m + 1), bci = sizeof(int32_t) * std::max<int64_t>(1, M.nnz),
+                 bv = vs * std::max<int64_t>(1, M.nnz);
+    M.h_pinned = hipHostMalloc((void **)&M.h_rp, brp, hipHostMallocDefault) == hipSuccess &&
+                 hipHostMalloc((void **)&M.h_ci, bci, hipHostMallocDefault) == hipSuccess &&
+                 hipHostMalloc(&M.h_val, bv, hipHostMallocDefault) == hipSuccess;
+    if (!M.h_pinned) {
+        if (M.h_rp) (void)hipHostFree(M.h_rp);
+        if (M.h_ci) (void)hipHostFree(M.h_ci);
+        if (M.h_val) (void)hipHostFree(M.h_val);
+        M.h_rp = (int32_t *)malloc(brp);
+        M.h_ci = (int32_t *)malloc(bci);
+        M.h_val = malloc(bv);
+        if (!M.h_rp || !M.h_ci || !M.h_val) return fail(SPK_ERR_OOM, "host copy of the matrix");
+    }
+    memcpy(M.h_rp, A->row_ptr, brp);
+    if (M.nnz) {
+        memcpy(M.h_ci, A->col_idx, sizeof(int32_t) * M.nnz);
+        memcpy(M.h_val, A->val, vs * M.nnz);
+    }
+    M.dev_bytes = (int64_t)(brp + bci + bv);
+    // tiles by the plan of the matrix's shape class
+    const int cls = batch_class(M.m, M.nnz);
+    int mode = batch_default_mode(cls, S->entry->tile);
+    spk_variant v{};
+    if (spk_plan_get(S->h, batch_key(M.dtype, cls).c_str(), &v) == SPK_OK) mode = v.group;
+    cut_rows(M.h_rp, M.m, mode, S->entry->block, S->entry->tile, 2048, 0, M.tiles);
+    std::lock_guard<std::mutex> lk(S->mats_mu);
+    if (M.dev_bytes + vec_bytes_of(M) > S->opts.hbm_budget) {
+        if (M.h_pinned) {
+            (void)hipHostFree(M.h_rp);
+            (void)hipHostFree(M.h_ci);
+            (void)hipHostFree(M.h_val);
+        } else {
+            free(M.h_rp);
+            free(M.h_ci);
+            free(M.h_val);
+        }
+        return fail(SPK_ERR_BUDGET, "matrix needs %lld bytes, budget is %lld", (long long)(M.dev_bytes + vec_bytes_of(M)),
+                    (long long)S->opts.hbm_budget);
+    }
+    *id = (int32_t)S->mats.size();
+    S->mats.push_back(std::move(M));
+    S->nmats.store((int32_t)S->mats.size());
+    return SPK_OK;
+}
+
+static spk_status submit_at(spk_server S, int32_t mat_id, const void *x, void *y, void *w, double t_arrival,
+                            int64_t *req)
+{
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->error != SPK_OK) return fail(S->error, "server failed: %s", S->error_msg);
+    if (mat_id < 0 || mat_id >= S->nmats.load()) return fail(SPK_ERR_NOT_FOUND, "unknown matrix %d", mat_id);
+    if (!x || !y) return fail(SPK_ERR_NULL, "x/y are NULL");
+    Request R;
+    R.mat = mat_id;
+    R.x = x;
+    R.y = y;
+    R.w = w;
+    R.t_arrival = t_arrival;
+    const int64_t id = (int64_t)S->reqs.size();
+    S->reqs.push_back(R);
+    if (S->first_arrival < 0 || t_arrival < S->first_arrival) S->first_arrival = t_arrival;
+    S->incoming.emplace_back(id, R);
+    if (req) *req = id;
+    S->cv_in.notify_one();
+    return SPK_OK;
+}
+
+spk_status spk_serve_submit(spk_server S, int32_t mat_id, const void *x, void *y, void *w, int64_t *req)
+{
+    if (!S) return fail(SPK_ERR_NULL, "server is NULL");
+    return submit_at(S, mat_id, x, y, w, now_seconds(), req);
+}
+
+spk_status spk_serve_poll(spk_server S, int64_t *ids, int32_t cap, int32_t *n)
+{
+    if (!S || !n || (cap > 0 && !ids)) return fail(SPK_ERR_NULL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    const int32_t k = (int32_t)std::min<size_t>((size_t)std::max(cap, 0), S->done_ids.size());
+    for (int32_t i = 0; i < k; ++i) ids[i] = S->done_ids[i];
+    S->done_ids.erase(S->done_ids.begin(), S->done_ids.begin() + k);
+    *n = k;
+    return SPK_OK;
+}
+
+spk_status spk_serve_drain(spk_server S)
+{
+    if (!S) return fail(SPK_ERR_NULL, "server is NULL");
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->completed >= (int64_t)S->reqs.size(); });
+    if (S->error != SPK_OK) return fail(S->error, "server failed: %s", S->error_msg);
+    return SPK_OK;
+}
+
+spk_status spk_serve_replay(spk_server S, int64_t n, const double *arrival_s, const int32_t *mat_ids,
+                            const void *const *x, void *const *y, void *const *w)
+{
+    if (!S || (n > 0 && (!arrival_s || !mat_ids || !x || !y))) return fail(SPK_ERR_NULL, "NULL argument");
+    for (int64_t i = 0; i < n; ++i) {
+        if (mat_ids[i] < 0 || mat_ids[i] >= S->nmats.load())
+            return fail(SPK_ERR_NOT_FOUND, "request %lld: unknown matrix %d", (long long)i, mat_ids[i]);
+        if (i > 0 && arrival_s[i] < arrival_s[i - 1]) return fail(SPK_ERR_ARG, "arrival times must not decrease");
+    }
+    const double t0 = now_seconds();
+    for (int64_t i = 0; i < n; ++i) {
+        const double target = t0 + arrival_s[i];
+        for (;;) {
+            const double dt = target - now_seconds();
+            if (dt <= 0) break;
+            if (dt > 200e-6) std::this_thread::sleep_for(std::chrono::microseconds((int64_t)((dt - 100e-6) * 1e6)));
+            else std::this_thread::yield();
+        }
+        // latency counts from the scheduled arrival, so a late submission is
+        // charged to the server
+        SPK_TRY(submit_at(S, mat_ids[i], x[i], y[i], w ? w[i] : nullptr, target, nullptr));
+    }
+    return spk_serve_drain(S);
+}
+
+spk_status spk_serve_stats_get(spk_server S, spk_serve_stats *out)
+{
+    if (!S || !out) return fail(SPK_ERR_NULL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    memset(out, 0, sizeof *out);
+    std::vector<double> lat;
+    double mx = 0.0, sum = 0.0;
+    for (const Request &R : S->reqs) {
+        if (R.t_done < 0) continue;
+        const double us = (R.t_done - R.t_arrival) * 1e6;
+        lat.push_back(us);
+        mx = std::max(mx, us);
+        sum += us;
+    }
+    out->submitted = (int64_t)S->reqs.size();
+    out->completed = S->completed;
+    out->rejected = S->rejected;
+    out->batches = S->batches;
+    out->uploads = S->uploads;
+    out->evictions = S->evictions;
+    out->resident_bytes = S->used_mat;
+    out->peak_bytes = S->peak;
+    out->p50_us = percentile(lat, 0.50);
+    out->p99_us = percentile(lat, 0.99);
+    out->mean_us = lat.empty() ? 0.0 : sum / (double)lat.size();
+    out->max_us = mx;
+    out->wall_s = S->first_arrival >= 0 ? S->last_done - S->first_arrival : 0.0;
+    out->bytes_moved = S->bytes_moved;
+    return SPK_OK;
+}
+
+spk_status spk_serve_latencies(spk_server S, double *out_us, int64_t cap, int64_t *n)
+{
+    if (!S || !n || (cap > 0 && !out_us)) return fail(SPK_ERR_NULL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    const int64_t k = std::min<int64_t>(cap, (int64_t)S->reqs.size());
+    for (int64_t i = 0; i < k; ++i) {
+        const Request &R = S->reqs[i];
+        out_us[i] = R.t_done < 0 ? -1.0 : (R.t_done - R.t_arrival) * 1e6;
+    }
+    *n = k;
+    return SPK_OK;
+}
+
+spk_status spk_serve_destroy(spk_server S)
+{
+    if (!S) return fail(SPK_ERR_NULL, "server is NULL");
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_in.notify_all();
+    if (S->thr.joinable()) S->thr.join();
+    DeviceGuard g(S->h);
+    for (hipStream_t s : S->streams) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    if (S->upload) {
+        (void)hipStreamSynchronize(S->upload);
+        (void)hipStreamDestroy(S->upload);
+    }
+    for (PoolMat &M : S->mats) {
+        if (M.resident) {
+            (void)hipFree(M.d_rp);
+            (void)hipFree(M.d_ci);
+            (void)hipFree(M.d_val);
+        }
+        if (M.uploaded) (void)hipEventDestroy(M.uploaded);
+        if (M.h_pinned) {
+            (void)hipHostFree(M.h_rp);
+            (void)hipHostFree(M.h_ci);
+            (void)hipHostFree(M.h_val);
+        } else {
+            free(M.h_rp);
+            free(M.h_ci);
+            free(M.h_val);
+        }
+    }
+    for (Flight &F : S->flights) hipEventDestroy(F.done);
+    for (hipEvent_t e : S->spare_events) hipEventDestroy(e);
+    S->dpool.release_all();
+    S->hpool.release_all();
+    delete S;
+    return SPK_OK;
+}
+
+}  // extern "C"

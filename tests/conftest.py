@@ -16,3 +16,23 @@ def pytest_configure(config):
 def orc():
     import oracle
     return oracle
+
+
+@pytest.fixture(scope="session")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    torch.cuda.set_device(0)
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="session")
+def spk(dev):
+    from paper_1309_1894_amd import spk as _spk
+    return _spk
+
+
+def say(*a):
+    """Names the case on stdout before a GPU step (flushed)."""
+    print(*a, flush=True)

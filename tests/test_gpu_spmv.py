@@ -1,0 +1,210 @@
+"""GPU parity of CSR SpMV (y = A*x) and the fused step (w = alpha*y + x)
+against the oracle, for every compiled variant (scalar, G lanes per row,
+sliced ELL, LDS row blocks), FP64 and FP32, on structural edge cases and on
+the workload matrices."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from conftest import say
+from paper_1309_1894_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+NP = {0: np.float32, 1: np.float64}
+
+
+def csr_from_entries(m, n, entries, dtype=np.float64):
+    entries = sorted(entries, key=lambda e: e[0])
+    rp = np.zeros(m + 1, np.int64)
+    for r, _, _ in entries:
+        rp[r + 1] += 1
+    rp = np.cumsum(rp).astype(np.int32)
+    return I.CSR(m, n, rp, np.array([c for _, c, _ in entries], np.int32),
+                 np.array([v for _, _, v in entries], dtype))
+
+
+def edge_cases():
+    rng = np.random.default_rng(11)
+    out = {
+        "1x1": csr_from_entries(1, 1, [(0, 0, 2.5)]),
+        "empty_rows": csr_from_entries(7, 5, [(1, 0, 1.25), (1, 4, -3.0), (5, 2, 0.5)]),
+        "all_empty": csr_from_entries(300, 300, []),
+        "rect_wide": csr_from_entries(5, 900, [(r, int(c), float(rng.uniform(-1, 1)))
+                                               for r in range(5) for c in rng.choice(900, 300, replace=False)]),
+        "rect_tall": csr_from_entries(700, 3, [(r, r % 3, float(rng.uniform(-1, 1))) for r in range(700)]),
+        "duplicates_unsorted": csr_from_entries(4, 6, [(0, 5, 1.0), (0, 0, -0.75), (0, 5, 0.1), (1, 4, 3.0),
+                                                       (3, 1, -0.3), (3, 1, 0.3), (3, 0, 0.0)]),
+        "lap2d_33": I.lap2d(33),
+        "banded_b7": I.banded(5000, 7, 0.6, stream=1),
+        "zipf_6000": I.zipf(6000, seed_struct=8, seed_val=9),     # rows up to 4096 entries
+    }
+    # one dense row longer than every LDS tile, among short rows
+    ents = [(r, r, 1.0 + r) for r in range(50)] + [(25, c, float(rng.uniform(-1, 1))) for c in range(50, 9050)]
+    out["long_row"] = csr_from_entries(50, 9050, ents)
+    return out
+
+
+CASES = edge_cases()
+
+
+def _check(A, x, y_gpu, w_gpu=None, alpha=None, dt=1):
+    ref, absum = O.spmv(A, x)
+    yg = y_gpu.cpu().numpy()
+    bad, worst, at = O.check_rows(yg.astype(np.float64), ref, absum, O.tau_for(NP[dt]))
+    assert bad == 0, f"{bad} rows outside tolerance (worst {worst:g} at row {at})"
+    empty = np.diff(A.row_ptr) == 0
+    assert np.all(yg[empty] == 0)
+    if w_gpu is not None:
+        # the step's w from the GPU's own y: one fused rounding
+        wr = O.waxpy(alpha, yg, x[:A.nrows])
+        d, at = O.max_ulp(w_gpu.cpu().numpy(), wr)
+        assert d <= (0 if dt == 1 else 1), (d, at)
+
+
+@pytest.mark.parametrize("dt", [1, 0])
+@pytest.mark.parametrize("name", list(CASES))
+def test_every_variant(spk, dev, name, dt):
+    A = CASES[name].astype(NP[dt])
+    M = spk.Matrix(A)
+    x = I.uniform(31, 0, A.ncols, NP[dt])
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(A.nrows, dtype=M.torch_dtype, device=dev)
+    vs = spk.variants(spk.SPK_OP_SPMV, dt)
+    say(f"spmv {name} dtype={dt}: {len(vs)} variants, m={A.nrows} nnz={A.nnz}")
+    try:
+        for v in vs:
+            for streams in ((1, 2) if v.format != spk.SPK_FMT_SELL else (1,)):
+                v.streams = streams
+                y.fill_(float("nan"))
+                spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), v)
+                try:
+                    _check(A, x, y, dt=dt)
+                except AssertionError as e:
+                    raise AssertionError(f"{v}: {e}")
+    finally:
+        M.release()
+
+
+@pytest.mark.parametrize("dt", [1, 0])
+@pytest.mark.parametrize("name", ["lap2d_33", "banded_b7", "zipf_6000", "empty_rows", "long_row"])
+def test_fused_step_every_variant(spk, dev, name, dt):
+    A = CASES[name].astype(NP[dt])
+    if A.nrows != A.ncols:
+        A = I.CSR(A.nrows, A.nrows, A.row_ptr, np.minimum(A.col_idx, A.nrows - 1).astype(np.int32), A.val)
+    M = spk.Matrix(A)
+    x = I.uniform(32, 0, A.ncols, NP[dt])
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(A.nrows, dtype=M.torch_dtype, device=dev)
+    w = torch.empty_like(y)
+    say(f"spmv_waxpy {name} dtype={dt}")
+    try:
+        for v in spk.variants(spk.SPK_OP_SPMV_WAXPY, dt):
+            y.fill_(float("nan"))
+            w.fill_(float("nan"))
+            spk.spk_run(spk.problem(spk.SPK_OP_SPMV_WAXPY, A=M, x=xd, y=y, w=w, alpha=0.5), v)
+            try:
+                _check(A, x, y, w, 0.5, dt)
+            except AssertionError as e:
+                raise AssertionError(f"{v}: {e}")
+    finally:
+        M.release()
+
+
+def test_bit_exact_cases(spk, dev):
+    """Identity, diagonal and the Laplacian on polynomials are exact in FP64
+    for every variant (integer values, or one rounding)."""
+    n = 4099
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    d = I.uniform(2, 0, n)
+    x = I.uniform(1, 0, n)
+    cases = [(I.CSR(n, n, rp, ci, np.ones(n)), x, x),
+             (I.CSR(n, n, rp, ci, d), x, d * x)]
+    N = 45
+    L = I.lap2d(N)
+    ii, jj = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    ii, jj = ii.ravel().astype(np.float64), jj.ravel().astype(np.float64)
+    p = lambda a, b: a * a + b * b
+    yexp = np.full(N * N, -4.0)
+    for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+        a, b = ii + di, jj + dj
+        out = (a < 0) | (a >= N) | (b < 0) | (b >= N)
+        yexp += np.where(out, p(a, b), 0.0)
+    cases.append((L, p(ii, jj), yexp))
+    for A, xv, yv in cases:
+        M = spk.Matrix(A)
+        xd = torch.from_numpy(xv).to(dev)
+        y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+        try:
+            for v in spk.variants(spk.SPK_OP_SPMV, 1):
+                spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), v)
+                assert np.array_equal(y.cpu().numpy(), yv), v
+        finally:
+            M.release()
+
+
+def test_nan_inf_positions(spk, dev):
+    A = I.banded(3000, 4, 0.8, stream=2)
+    x = I.uniform(3, 0, 3000)
+    x[[10, 500, 2999]] = [np.nan, np.inf, -np.inf]
+    M = spk.Matrix(A)
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(3000, dtype=torch.float64, device=dev)
+    try:
+        for v in spk.variants(spk.SPK_OP_SPMV, 1):
+            spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), v)
+            _check(A, x, y)
+    finally:
+        M.release()
+
+
+def test_borrowed_csr_and_default_dispatch(spk, dev):
+    A = I.zipf(20000, seed_struct=4, seed_val=5)
+    x = I.uniform(6, 0, A.ncols)
+    rp, ci, val = spk.to_device_csr(A, dev)
+    xd = torch.from_numpy(x).to(dev)
+    y = spk.spk_spmv_csr(rp, ci, val, xd)
+    _check(A, x, y)
+    M = spk.Matrix(A)
+    try:
+        y2 = spk.spk_spmv_mat(M, xd)
+        _check(A, x, y2)
+        y3, w3 = spk.spk_spmv_waxpy(M, 0.5, xd)
+        _check(A, x, y3, w3, 0.5)
+        # the same variant gives the same bits every time
+        y4 = spk.spk_spmv_mat(M, xd)
+        assert torch.equal(y2, y4)
+    finally:
+        M.release()
+
+
+def test_register_validation(spk, dev):
+    A = I.lap2d(8)
+    bad = I.CSR(A.nrows, A.ncols, A.row_ptr.copy(), A.col_idx.copy(), A.val)
+    bad.col_idx[5] = 64
+    with pytest.raises(spk.SpkError) as e:
+        spk.Matrix(bad)
+    assert e.value.name == "SPK_ERR_CSR"
+    bad2 = I.CSR(A.nrows, A.ncols, A.row_ptr.copy(), A.col_idx, A.val)
+    bad2.row_ptr[3] = bad2.row_ptr[4] + 1
+    with pytest.raises(spk.SpkError):
+        spk.Matrix(bad2)
+
+
+@pytest.mark.parametrize("which", ["lap3d_128", "zipf_1M"])
+def test_full_size_workloads(spk, dev, which):
+    """Workload matrices at full size, with the default and the plain kernels."""
+    A = I.lap3d(128) if which == "lap3d_128" else I.zipf(1000000)
+    say(f"full-size {which}: m={A.nrows} nnz={A.nnz}")
+    x = I.uniform(31 if which == "lap3d_128" else 34, 0, A.ncols)
+    M = spk.Matrix(A)
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+    try:
+        for v in [None, spk.spk_plain_variant(spk.SPK_OP_SPMV, 0), spk.spk_plain_variant(spk.SPK_OP_SPMV, 1)]:
+            spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), v)
+            _check(A, x, y)
+    finally:
+        M.release()
