@@ -1,0 +1,409 @@
+#!/usr/bin/env python3
+"""Benchmark of the autotuned SpMV + WAXPY hot path on one MI355X.
+
+Headline (``value``): achieved HBM GB/s of one Krylov-style step
+(y = A_i x_i, w_i = 0.5 y_i + x_i) over 4096 independent random banded FP64
+CSR instances (row counts log-uniform in [64, 16384), half-bandwidth 1..32,
+60% fill inside the band), all instances in one persistent, hipGraph-replayed
+launch whose tile kernel is autotuned per shape class.  Bytes are the
+algorithmic ones: every array once (values, column indices, row pointers, x,
+y, w), no re-reads, no padding.
+
+Also reported on the same JSON line: the plain (untuned, unbatched) kernels on
+the same batch, the vector sweep (WAXPY/AXPY/dot at n = 2^27, FP64 and FP32,
+tuned vs plain), the large single SpMVs (3-D Laplacian 128^3 and a 1M-row
+Zipf matrix, tuned vs the better plain kernel, cold cache), the 2-D Laplacian
+step, a short open-loop serving run (p50/p99), the STREAM copy bandwidth, the
+roofline of the dominant kernel and the oracle timed on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-extras", action="store_true", help="headline only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--instances", type=int, default=4096)
+    ap.add_argument("--serve-requests", type=int, default=3000)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+    lib = os.path.join(ROOT, "paper_1309_1894_amd", "libspk.so")
+    if not os.path.exists(lib):
+        import __graft_entry__
+        __graft_entry__.build()
+
+    import numpy as np
+    import torch
+
+    from paper_1309_1894_amd import inputs as I
+    from paper_1309_1894_amd import spk
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    h = spk.default_handle(0)
+    ncu, name = h.info()
+    log(f"device: {name}, {ncu} CUs")
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    # ------------------------------------------------ the batched workload
+    t0 = time.time()
+    B = I.batch_banded(args.instances, fill=0.6, seed_struct=41, seed_val=42)
+    x = I.batch_vector(B, seed=43)
+    log(f"batch: {B.count} instances, {int(B.m.sum())} rows, {int(B.nnz.sum())} nnz "
+        f"(generated in {time.time() - t0:.1f}s)")
+    d_rp = torch.from_numpy(B.row_ptr).to(dev)
+    d_ci = torch.from_numpy(B.col_idx).to(dev)
+    d_val = torch.from_numpy(B.val).to(dev)
+    d_x = torch.from_numpy(x).to(dev)
+    nv = int(B.m.sum())
+    d_y = torch.empty(nv, dtype=torch.float64, device=dev)
+    d_w = torch.empty(nv, dtype=torch.float64, device=dev)
+    batch = spk.Batch(B, (d_rp, d_ci, d_val), persistent=True, use_graph=True)
+    info = batch.info()
+    step_bytes = info["bytes"]
+    alpha = 0.5
+
+    # tuning (Section 2's search, per shape class), not timed
+    t0 = time.time()
+    rep = batch.tune(alpha, d_x, d_y, d_w, reps=5, warmup=1)
+    info = batch.info()
+    log(f"batch tune: {rep.tried} candidates timed, {rep.rejected} rejected, {info['classes']} classes, "
+        f"{info['tiles']} tiles ({time.time() - t0:.1f}s)")
+
+    # timed region: exactly K steps, synchronised on both sides
+    for _ in range(args.warmup):
+        batch.run(alpha, d_x, d_y, d_w)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        batch.run(alpha, d_x, d_y, d_w)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    per_launch_ms = [a.elapsed_time(b) for a, b in ev]
+    kern_ms = float(np.mean(per_launch_ms))
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+    achieved = step_bytes / (kern_ms * 1e-3) / 1e9
+    log(f"batched tuned: {ms_per_step:.3f} ms/step, {value:.1f} GB/s (kernel {kern_ms:.3f} ms, {achieved:.1f} GB/s)")
+
+    # plain baseline on the same batch: per-instance plain kernels, unfused
+    plain = plain_batch(spk, B, d_x, d_y, d_w, alpha, stream, torch)
+    plain["gbs_of_tuned_bytes"] = round(step_bytes / (plain["ms"] * 1e-3) / 1e9, 1)
+    log(f"batched plain: {plain}")
+    out["batched"] = {"tuned_gbs": round(value, 1), "tuned_ms": round(ms_per_step, 4),
+                      "plain": plain, "speedup_vs_plain": round(plain["ms"] / ms_per_step, 2),
+                      "instances": B.count, "rows": nv, "nnz": int(B.nnz.sum()), "bytes_per_step": step_bytes,
+                      "tiles": info["tiles"], "classes": info["classes"]}
+
+    # STREAM copy: measured bandwidth ceiling (and counter calibration)
+    out["stream_copy_gbs"] = stream_copy(spk, torch, dev, stream)
+
+    if not args.no_extras:
+        del d_y, d_w
+        out["vector_sweep"] = vector_sweep(spk, torch, I, dev)
+        out["spmv_large"] = spmv_large(spk, torch, I, dev)
+        out["krylov_step_lap2d"] = lap2d_step(spk, torch, I, dev)
+        out["serving"] = serving(spk, I, args.serve_requests)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(B, x, alpha, step_bytes)
+
+    traffic = load_traffic("k_batch_persistent", step_bytes)
+    result = {
+        "metric": "achieved HBM GB/s (% of roofline) SpMV+WAXPY, autotuned vs plain; serving p50/p99",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded SplitMix64 generators)",
+        "config": {"workload": f"batched SpMV+WAXPY step: {B.count} random banded FP64 CSR instances, "
+                               f"rows log-uniform [64,16384), half-band 1..32, fill 0.6, alpha 0.5; "
+                               f"one persistent hipGraph launch, tiles tuned per size class",
+                   "instances": B.count, "rows": nv, "nnz": int(B.nnz.sum()), "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "kernel": "k_batch_persistent<double,256,2048>", "bytes_per_launch": step_bytes,
+                     "kernel_ms": round(kern_ms, 4)},
+        "cpu_baseline": cpu,
+        "extras": out,
+    }
+    print(json.dumps(result), flush=True)
+
+
+def plain_batch(spk, B, d_x, d_y, d_w, alpha, stream, torch):
+    """Every instance with the fixed plain kernels, one launch each: SpMV
+    (lane per row, or wavefront per row, 256 threads) then WAXPY (one element
+    per thread).  Reports the better of the two SpMV kernels."""
+    import ctypes as C
+    h = spk.default_handle()
+    L = spk.lib
+    s = stream.cuda_stream
+    mats = [spk.Matrix(B.instance(i), validate=False) for i in range(B.count)]
+    wv = spk.spk_plain_variant(spk.SPK_OP_WAXPY, 0)
+    nbytes = 0
+    for i in range(B.count):
+        m, nz = int(B.m[i]), int(B.nnz[i])
+        nbytes += nz * 12 + 4 * (m + 1) + 16 * m + 24 * m   # SpMV, then WAXPY re-reads y and x
+    best = None
+    try:
+        for which in (0, 1):
+            v = spk.spk_plain_variant(spk.SPK_OP_SPMV, which)
+            probs = []
+            for i, M in enumerate(mats):
+                o, m = int(B.vec_off[i]), int(B.m[i])
+                ps = spk.spk_problem(spk.SPK_OP_SPMV, 1, 0, 0.0, M.ptr, d_x.data_ptr() + 8 * o,
+                                     d_y.data_ptr() + 8 * o, None, None)
+                pw = spk.spk_problem(spk.SPK_OP_WAXPY, 1, m, alpha, None, d_y.data_ptr() + 8 * o,
+                                     d_x.data_ptr() + 8 * o, d_w.data_ptr() + 8 * o, None)
+                probs.append((ps, pw))
+
+            def step():
+                for ps, pw in probs:
+                    st = L.spk_run(h.ptr, C.byref(ps), C.byref(v), s)
+                    if st:
+                        raise spk.SpkError(st, "plain spmv")
+                    st = L.spk_run(h.ptr, C.byref(pw), C.byref(wv), s)
+                    if st:
+                        raise spk.SpkError(st, "plain waxpy")
+
+            step()
+            torch.cuda.synchronize()
+            reps = 3
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                step()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            rec = {"spmv_kernel": "lane-per-row" if which == 0 else "wavefront-per-row", "ms": round(ms, 3),
+                   "launches_per_step": 2 * B.count, "gbs_of_tuned_bytes": None,
+                   "gbs_own_bytes": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+            if best is None or ms < best["ms"]:
+                best = rec
+    finally:
+        for M in mats:
+            M.release()
+    return best
+
+
+def stream_copy(spk, torch, dev, stream):
+    n = 1 << 28  # 2 GiB per array
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    c = torch.empty_like(a)
+    for _ in range(3):
+        spk.spk_stream_probe(0, a, a, c)
+    torch.cuda.synchronize()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        spk.spk_stream_probe(0, a, a, c)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, c
+    return round(2 * 8 * n / (ms * 1e-3) / 1e9, 1)
+
+
+def vector_sweep(spk, torch, I, dev):
+    """WAXPY/AXPY/dot at n = 2^27, FP64 and FP32: tuned vs plain (HBM-sized)."""
+    res = {}
+    n = 1 << 27
+    for dt, tdt, ndt in ((1, torch.float64, "f64"), (0, torch.float32, "f32")):
+        npdt = __import__("numpy").float64 if dt == 1 else __import__("numpy").float32
+        x = torch.from_numpy(I.uniform(21, 0, n, npdt)).to(dev)
+        y = torch.from_numpy(I.uniform(22, 0, n, npdt)).to(dev)
+        w = torch.empty_like(x)
+        d = torch.empty(1, dtype=torch.float64, device=dev)
+        s = x.element_size()
+        for op, nm, nbytes in ((spk.SPK_OP_WAXPY, "waxpy", 3 * n * s), (spk.SPK_OP_AXPY, "axpy", 3 * n * s),
+                               (spk.SPK_OP_DOT, "dot", 2 * n * s)):
+            p = spk.problem(op, x=x, y=y, w=w if op == spk.SPK_OP_WAXPY else None,
+                            d_result=d if op == spk.SPK_OP_DOT else None, alpha=1.5)
+            rep = spk.spk_tune(p, reps=5, warmup=1, record=True)
+            res[f"{nm}_{ndt}"] = {"tuned_gbs": round(nbytes / (rep.best_us * 1e-6) / 1e9, 1),
+                                  "plain_gbs": round(nbytes / (rep.plain_us * 1e-6) / 1e9, 1),
+                                  "tuned_us": round(rep.best_us, 2), "plain_us": round(rep.plain_us, 2),
+                                  "best": rep.best.as_dict(), "variants_timed": rep.tried,
+                                  "rejected": rep.rejected}
+            log(f"sweep {nm} {ndt}: {res[f'{nm}_{ndt}']}")
+        del x, y, w
+    torch.cuda.empty_cache()
+    return res
+
+
+def spmv_large(spk, torch, I, dev):
+    """Single large SpMVs, cold last-level cache: tuned vs the better plain kernel.
+    Each candidate is validated against the plain kernel's output (the
+    library's own reference run) before it is timed."""
+    import numpy as np
+    res = {}
+    for name, A, seed in (("lap3d_128", I.lap3d(128), 31), ("zipf_1M", I.zipf(1000000), 34)):
+        M = spk.Matrix(A)
+        x = I.uniform(seed, 0, A.ncols)
+        xd = torch.from_numpy(x).to(dev)
+        y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+        rep = spk.spk_tune(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), reps=10, warmup=2, flush=True,
+                           record=True)
+        nbytes = A.nnz * 12 + 4 * (A.nrows + 1) + 8 * A.ncols + 8 * A.nrows
+        res[name] = {"tuned_gbs": round(nbytes / (rep.best_us * 1e-6) / 1e9, 1),
+                     "plain_gbs": round(nbytes / (rep.plain_us * 1e-6) / 1e9, 1),
+                     "tuned_us": round(rep.best_us, 2), "plain_us": round(rep.plain_us, 2),
+                     "best": rep.best.as_dict(), "variants_timed": rep.tried, "pruned": rep.pruned,
+                     "rejected": rep.rejected, "bytes": nbytes}
+        log(f"spmv {name}: {res[name]}")
+        M.release()
+    return res
+
+
+def lap2d_step(spk, torch, I, dev):
+    """2-D Laplacian 256^2 Krylov-style step (cache-resident, launch-bound)."""
+    A = I.lap2d(256)
+    M = spk.Matrix(A)
+    x = I.uniform(11, 0, A.nrows)
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+    w = torch.empty_like(y)
+    rep = spk.spk_tune(spk.problem(spk.SPK_OP_SPMV_WAXPY, A=M, x=xd, y=y, w=w, alpha=0.5), reps=20, warmup=3)
+    M.release()
+    return {"tuned_us": round(rep.best_us, 2), "plain_us": round(rep.plain_us, 2), "best": rep.best.as_dict(),
+            "variants_timed": rep.tried, "rejected": rep.rejected}
+
+
+def serving(spk, I, nreq):
+    """Open-loop Poisson serving of SpMV+WAXPY requests over a pool of banded
+    and Zipf matrices (1e3..1e5 rows here, 70% FP64 / 30% FP32): continuous
+    batching vs a FIFO server that runs one request at a time with the plain
+    unbatched kernels, both at the same offered load (70% of the FIFO
+    server's closed-loop saturation rate)."""
+    import numpy as np
+    npool = 48
+    sizes = I.log_uniform_int(1e3, 1e5, 51, 0, npool)
+    kinds = I.u64(51, 1, 0, npool) % np.uint64(2)
+    fp64 = I.unit_from_u64(I.u64(51, 2, 0, npool)) < 0.7
+    pool = []
+    for i in range(npool):
+        m = int(sizes[i])
+        dt = np.float64 if fp64[i] else np.float32
+        if kinds[i] == 0:
+            b = 1 + int(I.u64(51, 3, i, 1)[0] % np.uint64(32))
+            pool.append(I.banded(m, b, 0.6, seed_struct=53, seed_val=54, stream=i, dtype=dt))
+        else:
+            pool.append(I.zipf(m, kmax=min(4096, m), seed_struct=55 + i, seed_val=56, dtype=dt))
+    mats = (I.u64(52, 0, 0, nreq) % np.uint64(npool)).astype(np.int64)
+    xs = [I.uniform(52, 1 + i, pool[mats[i]].ncols, pool[mats[i]].val.dtype) for i in range(nreq)]
+
+    def make(mode):
+        srv = spk.Server(streams=4, max_inflight=256, max_batch=64, mode=mode, alpha=0.5)
+        ids = [srv.add_matrix(A) for A in pool]
+        for i, A in enumerate(pool):   # one request per matrix makes it resident
+            srv.submit(ids[i], np.zeros(A.ncols, A.val.dtype), np.empty(A.nrows, A.val.dtype),
+                       np.empty(A.nrows, A.val.dtype))
+        srv.drain()
+        return srv, ids
+
+    res = {"requests": nreq, "pool": npool}
+    srv, ids = make(1)
+    k = min(nreq, 400)
+    t0 = time.perf_counter()
+    for i in range(k):
+        srv.submit(ids[mats[i]], xs[i], np.empty(pool[mats[i]].nrows, pool[mats[i]].val.dtype))
+    srv.drain()
+    sat = k / (time.perf_counter() - t0)
+    srv.close()
+    rate = 0.7 * sat
+    res["fifo_saturation_per_s"] = round(sat, 1)
+    res["offered_rate_per_s"] = round(rate, 1)
+    arr = I.poisson_arrivals(nreq, rate, seed=51)
+    for mode, label in ((1, "fifo_plain"), (0, "continuous_batching")):
+        srv, ids = make(mode)
+        ys = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
+        ws = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
+        srv.replay(arr, [ids[m] for m in mats], xs, ys, ws)
+        st = srv.stats()
+        lat = srv.latencies()[npool:]
+        res[label] = {"p50_us": round(float(np.percentile(lat, 50)), 1),
+                      "p99_us": round(float(np.percentile(lat, 99)), 1),
+                      "mean_us": round(float(lat.mean()), 1), "launches": st["batches"],
+                      "gbs": round(st["bytes_moved"] / max(st["wall_s"], 1e-9) / 1e9, 2)}
+        log(f"serving {label}: {res[label]}")
+        srv.close()
+    return res
+
+
+def cpu_baseline(B, x, alpha, step_bytes):
+    """The oracle as it stands, on the host cores, over the same batch."""
+    import numpy as np
+
+    import oracle as O
+    threads = O.num_threads()
+    t = []
+    t_total = 0.0
+    while len(t) < 3 and t_total < 30.0:
+        t0 = time.perf_counter()
+        O.batch_spmv_waxpy(B, x, alpha)
+        dt = time.perf_counter() - t0
+        t.append(dt)
+        t_total += dt
+    sec = float(np.median(t))
+    return {"value": round(step_bytes / sec / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"the whole batched step ({B.count} instances), median of {len(t)} runs, "
+                      f"{sec * 1e3:.1f} ms per step"}
+
+
+def load_traffic(kernel, bytes_per_launch):
+    """HBM bytes per launch from the committed counter summary, if it matches this build."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        from paper_1309_1894_amd import build as _b
+        if t.get("build_id") != _b.build_id():
+            return None
+        return t.get(kernel)
+    except (OSError, ValueError):
+        return None
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+"""Batched execution: one (persistent, graph-replayed) launch over many CSR
+instances matches the oracle per instance, and gives every instance the same
+bits as running it alone."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from conftest import say
+from paper_1309_1894_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev_batch(B, dev):
+    return (torch.from_numpy(B.row_ptr).to(dev), torch.from_numpy(B.col_idx).to(dev),
+            torch.from_numpy(B.val).to(dev))
+
+
+def _check_batch(B, x, y, w, alpha, dt=np.float64):
+    yg, wg = y.cpu().numpy(), w.cpu().numpy() if w is not None else None
+    for i in range(B.count):
+        A = B.instance(i)
+        o = int(B.vec_off[i])
+        xi = x[o:o + A.nrows]
+        ref, absum = O.spmv(A, xi)
+        bad, worst, at = O.check_rows(yg[o:o + A.nrows].astype(np.float64), ref, absum, O.tau_for(dt))
+        assert bad == 0, f"instance {i}: {bad} rows (worst {worst:g} at {at})"
+        if wg is not None:
+            d, at = O.max_ulp(wg[o:o + A.nrows], O.waxpy(alpha, yg[o:o + A.nrows], xi))
+            assert d <= (0 if dt == np.float64 else 1), (i, d, at)
+
+
+def mixed_batch(dt=np.float64):
+    """Instances of every shape class, including empty rows and one long row."""
+    insts = []
+    m, b = I.batch_sizes(40, seed=7, mmin=64, ratio=64.0, bmax=32)
+    for i in range(40):
+        insts.append(I.banded(int(m[i]), int(b[i]), 0.6, seed_struct=7, seed_val=8, stream=i, dtype=dt))
+    insts.append(I.zipf(3000, n=3000, kmax=3000, seed_struct=9, seed_val=10, dtype=dt))   # rows up to 3000 > LDS tile
+    insts.append(I.banded(500, 3, 0.1, seed_struct=11, seed_val=12, dtype=dt))             # many empty rows
+    insts.append(I.lap2d(40, dtype=dt))
+    return I.batch_from_instances(insts)
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("persistent,graph", [(1, 1), (1, 0), (0, 0), (0, 1)])
+def test_batch_matches_oracle(spk, dev, dt, persistent, graph):
+    B = mixed_batch(dt)
+    x = I.batch_vector(B, seed=13, dtype=dt)
+    say(f"batch dtype={dt.__name__} persistent={persistent} graph={graph}: {B.count} instances")
+    arrs = _dev_batch(B, dev)
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.full((x.size,), float("nan"), dtype=xd.dtype, device=dev)
+    w = torch.full_like(y, float("nan"))
+    b = spk.Batch(B, arrs, persistent=persistent, use_graph=graph)
+    try:
+        b.run(0.5, xd, y, w)
+        torch.cuda.synchronize()
+        _check_batch(B, x, y, w, 0.5, dt)
+        # replays with eager work in between give the same bits every time
+        first = (y.clone(), w.clone())
+        for k in range(4):
+            y.fill_(float("nan"))
+            w.fill_(0.0)
+            torch.cuda.synchronize()
+            b.run(0.5, xd, y, w)
+            torch.cuda.synchronize()
+            assert torch.equal(y, first[0]) and torch.equal(w, first[1]), f"replay {k}"
+    finally:
+        b.free()
+
+
+def test_instance_alone_equals_in_batch(spk, dev):
+    B = mixed_batch()
+    x = I.batch_vector(B, seed=14)
+    arrs = _dev_batch(B, dev)
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(x.size, dtype=torch.float64, device=dev)
+    w = torch.empty_like(y)
+    b = spk.Batch(B, arrs)
+    b.run(0.5, xd, y, w)
+    torch.cuda.synchronize()
+    yb, wb = y.cpu().numpy(), w.cpu().numpy()
+    b.free()
+    for i in (0, 7, 40, 41, 42):
+        single = I.batch_from_instances([B.instance(i)])
+        o, m = int(B.vec_off[i]), int(B.m[i])
+        xs = x[o:o + m].copy()
+        b1 = spk.Batch(single, _dev_batch(single, dev))
+        ys = torch.empty(m, dtype=torch.float64, device=dev)
+        ws = torch.empty_like(ys)
+        b1.run(0.5, torch.from_numpy(xs).to(dev), ys, ws)
+        torch.cuda.synchronize()
+        assert np.array_equal(ys.cpu().numpy(), yb[o:o + m]), i
+        assert np.array_equal(ws.cpu().numpy(), wb[o:o + m]), i
+        b1.free()
+
+
+def test_batch_tune_per_class(spk, dev):
+    B = mixed_batch()
+    x = I.batch_vector(B, seed=15)
+    arrs = _dev_batch(B, dev)
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(x.size, dtype=torch.float64, device=dev)
+    w = torch.empty_like(y)
+    h = spk.Handle(0)
+    b = spk.Batch(B, arrs, handle=h)
+    try:
+        rep = b.tune(0.5, xd, y, w, reps=3, warmup=1)
+        assert rep.tried > 0 and rep.rejected == 0
+        info = b.info()
+        assert info["classes"] >= 3 and info["tiles"] > B.count
+        y.fill_(float("nan"))
+        b.run(0.5, xd, y, w)
+        torch.cuda.synchronize()
+        _check_batch(B, x, y, w, 0.5)
+        # winners are filed per class in the plan DB
+        assert any(spk.spk_plan_get(f"batch:f64:c{c}", handle=h) is not None for c in range(8))
+    finally:
+        b.free()
+        h.close()
+
+
+def test_batch_spmv_only_and_empty(spk, dev):
+    B = mixed_batch()
+    x = I.batch_vector(B, seed=16)
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(x.size, dtype=torch.float64, device=dev)
+    b = spk.Batch(B, _dev_batch(B, dev))
+    b.run(0.5, xd, y, None)
+    torch.cuda.synchronize()
+    _check_batch(B, x, y, None, 0.5)
+    b.free()
+    E = I.batch_from_instances([])
+    e = spk.Batch(E, (torch.zeros(1, dtype=torch.int32, device=dev), torch.zeros(1, dtype=torch.int32, device=dev),
+                      torch.zeros(1, dtype=torch.float64, device=dev)))
+    assert e.info()["tiles"] == 0
+    e.free()
+
+
+def test_full_batched_workload_sampled(spk, dev):
+    """The full 4096-instance batch: sampled instances against the oracle."""
+    B = I.batch_banded(4096)
+    x = I.batch_vector(B, seed=43)
+    say(f"full batch: {int(B.m.sum())} rows, {int(B.nnz.sum())} nnz")
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(x.size, dtype=torch.float64, device=dev)
+    w = torch.empty_like(y)
+    b = spk.Batch(B, _dev_batch(B, dev))
+    try:
+        b.run(0.5, xd, y, w)
+        torch.cuda.synchronize()
+        yg, wg = y.cpu().numpy(), w.cpu().numpy()
+        idx = sorted(set(np.random.default_rng(1).integers(0, 4096, 24).tolist()) | {0, 4095})
+        for i in idx:
+            A = B.instance(i)
+            o = int(B.vec_off[i])
+            yr, wr, absum = O.spmv_waxpy(A, x[o:o + A.nrows], 0.5)
+            assert O.check_rows(yg[o:o + A.nrows], yr, absum, O.TAU_F64)[0] == 0, i
+            assert O.max_ulp(wg[o:o + A.nrows], O.waxpy(0.5, yg[o:o + A.nrows], x[o:o + A.nrows]))[0] == 0
+    finally:
+        b.free()

@@ -1,0 +1,102 @@
+"""Serving: continuous batching of SpMV+WAXPY requests gives each request the
+same bits alone and in the mix, stays within its HBM budget (evicting idle
+matrices), and matches the oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import say
+from paper_1309_1894_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def pool_mats():
+    out = []
+    for i in range(10):
+        dt = np.float64 if i % 3 else np.float32
+        m = [1000, 3000, 20000, 5000, 1500][i % 5]
+        if i % 2:
+            out.append(I.banded(m, 1 + 3 * i, 0.6, seed_struct=60, seed_val=61, stream=i, dtype=dt))
+        else:
+            out.append(I.zipf(m, kmax=min(4096, m), seed_struct=62 + i, seed_val=63, dtype=dt))
+    return out
+
+
+def _check(A, x, y, w):
+    ref, absum = O.spmv(A, x)
+    dt = A.val.dtype
+    assert O.check_rows(y.astype(np.float64), ref, absum, O.tau_for(dt))[0] == 0
+    assert O.max_ulp(w, O.waxpy(0.5, y, x))[0] <= (0 if dt == np.float64 else 1)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_serve_matches_oracle_and_alone(spk, dev, mode):
+    pool = pool_mats()
+    nreq = 200
+    mats = (I.u64(70, 0, 0, nreq) % np.uint64(len(pool))).astype(int)
+    xs = [I.uniform(71, i, pool[m].ncols, pool[m].val.dtype) for i, m in enumerate(mats)]
+    ys = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
+    ws = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
+    say(f"serve mode={mode}: {nreq} requests over {len(pool)} matrices")
+    srv = spk.Server(streams=4, max_inflight=64, max_batch=16, mode=mode, alpha=0.5)
+    try:
+        ids = [srv.add_matrix(A) for A in pool]
+        arr = I.poisson_arrivals(nreq, 20000.0, seed=72)
+        srv.replay(arr, [ids[m] for m in mats], xs, ys, ws)
+        st = srv.stats()
+        assert st["completed"] == nreq and st["rejected"] == 0
+        lat = srv.latencies()
+        assert np.all(lat > 0)
+        if mode == 0:
+            assert st["batches"] < nreq   # requests were batched together
+    finally:
+        srv.close()
+    for i in range(nreq):
+        _check(pool[mats[i]], xs[i], ys[i], ws[i])
+    # each request alone gives the same bits as in the mix
+    solo = spk.Server(streams=1, max_inflight=1, max_batch=1, mode=mode, alpha=0.5)
+    try:
+        ids = [solo.add_matrix(A) for A in pool]
+        for i in range(0, nreq, 17):
+            y1 = np.empty_like(ys[i])
+            w1 = np.empty_like(ws[i])
+            solo.submit(ids[mats[i]], xs[i], y1, w1)
+            solo.drain()
+            assert np.array_equal(y1, ys[i]) and np.array_equal(w1, ws[i]), i
+    finally:
+        solo.close()
+
+
+def test_serve_budget_evicts_idle_matrices(spk, dev):
+    pool = [I.banded(20000, 16, 0.6, stream=i) for i in range(6)]
+    one = 4 * 20001 + 12 * pool[0].nnz
+    budget = int(2.5 * one)   # room for two matrices and their vectors
+    srv = spk.Server(streams=2, max_inflight=8, max_batch=4, mode=0, hbm_budget=budget, alpha=0.5)
+    try:
+        ids = [srv.add_matrix(A) for A in pool]
+        order = [0, 1, 2, 3, 0, 4, 5, 1, 2, 3] * 3
+        xs = [I.uniform(80, k, 20000) for k in range(len(order))]
+        ys = [np.empty(20000) for _ in order]
+        ws = [np.empty(20000) for _ in order]
+        for k, m in enumerate(order):
+            srv.submit(ids[m], xs[k], ys[k], ws[k])
+        srv.drain()
+        st = srv.stats()
+        say(f"budget run: {st}")
+        assert st["completed"] == len(order)
+        assert st["evictions"] > 0 and st["peak_bytes"] <= budget
+        for k, m in enumerate(order):
+            _check(pool[m], xs[k], ys[k], ws[k])
+    finally:
+        srv.close()
+
+
+def test_serve_rejects_oversized_matrix(spk, dev):
+    srv = spk.Server(hbm_budget=1 << 20)
+    try:
+        with pytest.raises(spk.SpkError) as e:
+            srv.add_matrix(I.banded(100000, 8, 0.6))
+        assert e.value.name == "SPK_ERR_BUDGET"
+    finally:
+        srv.close()

@@ -1,0 +1,108 @@
+"""The tuner: validate-then-time over the compiled variant space, rejection of
+variants whose output disagrees with the reference, plan DB round trip."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from conftest import say
+from paper_1309_1894_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tune_waxpy_and_dot(spk, dev, tmp_path):
+    db = str(tmp_path / "plans.spkdb")
+    h = spk.Handle(0, db)
+    try:
+        n = 1 << 20
+        x = I.uniform(21, 0, n)
+        y = I.uniform(22, 0, n)
+        xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+        w = torch.empty_like(xd)
+        rep = spk.spk_tune(spk.problem(spk.SPK_OP_WAXPY, x=xd, y=yd, w=w, alpha=1.5), reps=3, warmup=1, handle=h)
+        say(f"waxpy tune: {rep.best} {rep.best_us:.2f} us vs plain {rep.plain_us:.2f} us")
+        assert rep.tried > 100 and rep.rejected == 0 and rep.best_us <= rep.plain_us
+        assert O.max_ulp(w.cpu().numpy(), O.waxpy(1.5, x, y))[0] == 0
+        key = rep.class_key.decode()
+        assert key == "waxpy:f64:n20"
+        d = torch.empty(1, dtype=torch.float64, device=dev)
+        rep2 = spk.spk_tune(spk.problem(spk.SPK_OP_DOT, x=xd, y=yd, d_result=d), reps=3, handle=h)
+        assert rep2.rejected == 0
+        assert abs(d.item() - O.dot(x, y)) <= 1e-12 * O.dot_absum(x, y)
+        # AXPY (in place) restores y between runs
+        y2 = yd.clone()
+        rep3 = spk.spk_tune(spk.problem(spk.SPK_OP_AXPY, x=xd, y=y2, alpha=-0.5), reps=3, handle=h)
+        assert rep3.rejected == 0
+        assert O.max_ulp(y2.cpu().numpy(), O.axpy(-0.5, x, y))[0] == 0
+    finally:
+        h.close()
+    # a new handle loads the recorded winners
+    h2 = spk.Handle(0, db)
+    try:
+        v = spk.spk_plan_get(key, handle=h2)
+        assert v is not None and v.as_dict() == rep.best.as_dict()
+        w2 = spk.spk_waxpy(1.5, xd, yd, handle=h2)
+        assert O.max_ulp(w2.cpu().numpy(), O.waxpy(1.5, x, y))[0] == 0
+    finally:
+        h2.close()
+    assert os.path.getsize(db) > 0
+
+
+def test_planted_wrong_reference_rejects_everything(spk, dev):
+    """A reference that is wrong (perturbed on the host) must make every variant
+    fail validation; nothing is timed or recorded."""
+    n = 4096
+    x = I.uniform(1, 0, n)
+    y = I.uniform(2, 0, n)
+    ref = O.waxpy(1.5, x, y)
+    ref[100] = np.nextafter(np.nextafter(ref[100], 9), 9)   # two ulps off
+    h = spk.Handle(0)
+    try:
+        xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+        w = torch.empty_like(xd)
+        with pytest.raises(spk.SpkError) as e:
+            spk.spk_tune(spk.problem(spk.SPK_OP_WAXPY, x=xd, y=yd, w=w, alpha=1.5), ref=ref, reps=2, handle=h)
+        assert e.value.name == "SPK_ERR_VALIDATION"
+        assert spk.spk_plan_get("waxpy:f64:n12", handle=h) is None
+        # the correct reference passes
+        rep = spk.spk_tune(spk.problem(spk.SPK_OP_WAXPY, x=xd, y=yd, w=w, alpha=1.5), ref=O.waxpy(1.5, x, y),
+                           reps=2, handle=h)
+        assert rep.rejected == 0
+    finally:
+        h.close()
+
+
+@pytest.mark.parametrize("which", ["zipf", "lap2d", "banded"])
+def test_tune_spmv(spk, dev, which):
+    A = {"zipf": lambda: I.zipf(50000, seed_struct=2, seed_val=3),
+         "lap2d": lambda: I.lap2d(200),
+         "banded": lambda: I.banded(40000, 12, 0.6, stream=5)}[which]()
+    x = I.uniform(4, 0, A.ncols)
+    ref, absum = O.spmv(A, x)
+    h = spk.Handle(0)
+    M = spk.Matrix(A, handle=h)
+    try:
+        xd = torch.from_numpy(x).to(dev)
+        y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+        rep = spk.spk_tune(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), ref=ref, ref_scale=absum, reps=3,
+                           handle=h)
+        say(f"spmv tune {which}: {rep.best} {rep.best_us:.2f} us (plain {rep.plain_us:.2f}), pruned {rep.pruned}")
+        assert rep.rejected == 0 and rep.tried > 20
+        if which == "zipf":
+            assert rep.pruned > 0   # sliced ELL is pruned by the padding model
+        assert O.check_rows(y.cpu().numpy(), ref, absum, O.TAU_F64)[0] == 0
+        # dispatch now uses the recorded winner
+        y.fill_(float("nan"))
+        spk.spk_spmv_mat(M, xd, y)
+        assert O.check_rows(y.cpu().numpy(), ref, absum, O.TAU_F64)[0] == 0
+        # the fused step, validated against the plain run
+        w = torch.empty_like(y)
+        rep2 = spk.spk_tune(spk.problem(spk.SPK_OP_SPMV_WAXPY, A=M, x=xd, y=y, w=w, alpha=0.5), reps=3, handle=h)
+        assert rep2.rejected == 0
+        assert O.max_ulp(w.cpu().numpy(), O.waxpy(0.5, y.cpu().numpy(), x))[0] == 0
+    finally:
+        M.release()
+        h.close()
