@@ -349,6 +349,7 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
             fill_args<std::remove_const_t<T>>(a, p, rp, ci, val);
             if (v.format == SPK_FMT_ADAPTIVE) {
                 a.blocks = bd->blk;
+                a.block_k = bd->bk;
                 a.blk0 = (int32_t)lo;
                 a.nblk = (int32_t)(hi - lo);
                 grid = dim3((unsigned)(hi - lo));
@@ -438,16 +439,19 @@ spk_status get_sell(spk_handle h, spk_mat *A, int C, SellData **out)
 // Row blocks for the LDS-staged kernel: runs of short rows whose entries
 // fit `tile` (at most 2*block rows), up to block/64 medium rows handled one
 // wavefront each, and single long rows handled by a whole workgroup.
-static void make_blocks(const std::vector<int32_t> &rp, int64_t m, int block, int tile, std::vector<uint32_t> &out)
+static void make_blocks(const std::vector<int32_t> &rp, int64_t m, int block, int tile, std::vector<uint32_t> &out,
+                        std::vector<int32_t> &out_k)
 {
     const int64_t kShort = std::min<int64_t>(96, tile);
     const int64_t kLong = (int64_t)block * 8;
-    const int64_t row_cap = 2 * (int64_t)block;
+    const int64_t row_cap = (int64_t)kStreamRowsPerThread * block;
     const int64_t waves = block / 64;
     out.clear();
+    out_k.clear();
     int64_t r = 0;
     while (r < m) {
         const int64_t len = rp[r + 1] - rp[r];
+        out_k.push_back(rp[r]);
         if (len > kLong) {
             out.push_back((uint32_t)r | (kBlkBlock << 30));
             ++r;
@@ -473,6 +477,7 @@ static void make_blocks(const std::vector<int32_t> &rp, int64_t m, int block, in
         }
     }
     out.push_back((uint32_t)m);
+    out_k.push_back(rp[m]);
 }
 
 spk_status get_blocks(spk_handle h, spk_mat *A, int block, int tile, BlockData **out)
@@ -485,12 +490,15 @@ spk_status get_blocks(spk_handle h, spk_mat *A, int block, int tile, BlockData *
         return SPK_OK;
     }
     BlockData d;
-    make_blocks(A->rp_host, A->nrows, block, tile, d.host);
+    make_blocks(A->rp_host, A->nrows, block, tile, d.host, d.host_k);
     d.nblk = (int32_t)d.host.size() - 1;
     SPK_HIP(hipMalloc(&d.blk, sizeof(uint32_t) * d.host.size()));
+    SPK_HIP(hipMalloc(&d.bk, sizeof(int32_t) * d.host_k.size()));
     SPK_HIP(hipMemcpyAsync(d.blk, d.host.data(), sizeof(uint32_t) * d.host.size(), hipMemcpyHostToDevice, h->work));
+    SPK_HIP(hipMemcpyAsync(d.bk, d.host_k.data(), sizeof(int32_t) * d.host_k.size(), hipMemcpyHostToDevice,
+                           h->work));
     SPK_HIP(hipStreamSynchronize(h->work));
-    d.bytes = (int64_t)(sizeof(uint32_t) * d.host.size());
+    d.bytes = (int64_t)(sizeof(uint32_t) * d.host.size() + sizeof(int32_t) * d.host_k.size());
     A->bytes += d.bytes;
     auto res = A->blocks.emplace(key, std::move(d));
     *out = &res.first->second;

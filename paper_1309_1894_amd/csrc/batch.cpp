@@ -29,7 +29,6 @@ struct spk_batch_s {
     std::vector<int> cls;                 // class per instance
     std::map<int, int> mode;              // class -> tile mode
     std::vector<spk::BatchTile> tiles;
-    spk::BatchInst *d_inst = nullptr;
     spk::BatchTile *d_tiles = nullptr;
     int64_t d_tiles_cap = 0;
     uint32_t *d_ctr = nullptr;            // [0] queue head, [1] done count
@@ -76,17 +75,21 @@ const BatchEntry *batch_entry(int block, int tile)
     return nullptr;
 }
 
-void cut_rows(const int32_t *rp, int64_t m, int mode, int block, int tile, int64_t target, int32_t inst,
+void cut_rows(const int32_t *rp, int64_t m, int mode, int block, int tile, int64_t target,
               std::vector<BatchTile> &out)
 {
     int64_t r = 0;
     while (r < m) {
-        BatchTile t{inst, (int32_t)r, 0, mode};
+        BatchTile t{};
+        t.r0 = (int32_t)r;
+        t.mode = mode;
         if (mode == 0) {
             if (rp[r + 1] - rp[r] > tile) {
                 // a row that does not fit the LDS tile gets one wavefront
                 t.mode = 64;
                 t.r1 = (int32_t)(r + 1);
+                t.k0 = rp[t.r0];
+                t.k1 = rp[t.r1];
                 out.push_back(t);
                 ++r;
                 continue;
@@ -111,13 +114,14 @@ void cut_rows(const int32_t *rp, int64_t m, int mode, int block, int tile, int64
             t.r1 = (int32_t)r1;
             r = r1;
         }
+        t.k0 = rp[t.r0];
+        t.k1 = rp[t.r1];
         out.push_back(t);
     }
 }
 
-spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchInst *d_inst, const BatchTile *d_tiles,
-                        int64_t ntiles, double alpha, const void *x, void *y, void *w, uint32_t *next,
-                        int64_t persistent_grid, hipStream_t s)
+spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchTile *d_tiles, int64_t ntiles, double alpha,
+                        const void *x, void *y, void *w, uint32_t *next, int64_t persistent_grid, hipStream_t s)
 {
     if (ntiles == 0) return SPK_OK;
     union {
@@ -128,7 +132,6 @@ spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchInst *d_inst,
     auto fill = [&](auto &q) {
         using Q = std::remove_reference_t<decltype(q)>;
         using T = std::remove_const_t<std::remove_pointer_t<decltype(Q::x)>>;
-        q.inst = d_inst;
         q.tiles = d_tiles;
         q.ntiles = (int32_t)ntiles;
         q.x = (const T *)x;
@@ -158,8 +161,16 @@ void invalidate_graph(spk_batch b)
 // Tiles of instance i under `mode`.
 void cut_instance(const spk_batch b, int64_t i, int mode, std::vector<BatchTile> &out)
 {
+    const size_t first = out.size();
     cut_rows(b->rp_host.data() + b->rp_off[i], b->m[i], mode, b->entry->block, b->entry->tile, b->opts.tile_nnz,
-             (int32_t)i, out);
+             out);
+    const size_t vs = dtype_size(b->dtype);
+    for (size_t k = first; k < out.size(); ++k) {
+        out[k].rp = b->rp + b->rp_off[i];
+        out[k].ci = b->ci + b->nz_off[i];
+        out[k].val = (const char *)b->val + vs * b->nz_off[i];
+        out[k].vec_off = b->vec_off[i];
+    }
 }
 
 spk_status upload_tiles(spk_batch b, const std::vector<BatchTile> &tiles)
@@ -191,7 +202,7 @@ spk_status replan(spk_batch b)
 // Launches the tile kernel over `ntiles` tiles already on the device.
 spk_status launch(spk_batch b, int64_t ntiles, double alpha, const void *x, void *y, void *w, hipStream_t s)
 {
-    return launch_tiles(b->entry, b->dtype, b->d_inst, b->d_tiles, ntiles, alpha, x, y, w,
+    return launch_tiles(b->entry, b->dtype, b->d_tiles, ntiles, alpha, x, y, w,
                         b->opts.persistent ? b->d_ctr : nullptr, b->grid_persistent, s);
 }
 
@@ -285,14 +296,7 @@ spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *d, const spk_batch
                 b->mode[c] = batch_default_mode(c, e->tile);
         }
     }
-    std::vector<BatchInst> inst((size_t)b->count);
-    const size_t vs = dtype_size(b->dtype);
-    for (int64_t i = 0; i < b->count; ++i)
-        inst[i] = BatchInst{b->rp + b->rp_off[i], b->ci + b->nz_off[i], (const char *)b->val + vs * b->nz_off[i],
-                            b->vec_off[i], (int32_t)b->m[i], 0};
-    hipError_t he = hipMalloc(&b->d_inst, sizeof(BatchInst) * std::max<int64_t>(1, b->count));
-    if (he == hipSuccess && b->count)
-        he = hipMemcpyAsync(b->d_inst, inst.data(), sizeof(BatchInst) * b->count, hipMemcpyHostToDevice, h->work);
+    hipError_t he = hipSuccess;
     if (he == hipSuccess) he = hipMalloc(&b->d_ctr, 256);
     if (he == hipSuccess) he = hipMemsetAsync(b->d_ctr, 0, 256, h->work);
     if (he == hipSuccess) he = hipStreamSynchronize(h->work);
@@ -416,6 +420,73 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
 
     int tried = 0, rejected = 0;
     double total_best = 0.0, total_plain = 0.0;
+
+    // times `ntiles` tiles already uploaded; rejects (returns -1) when the
+    // output disagrees with the reference
+    auto validate_and_time = [&](int64_t ntiles, double *med) -> spk_status {
+        *med = -1.0;
+        SPK_HIP(hipMemsetAsync(bad, 0, 8, s));
+        SPK_TRY(launch(b, ntiles, alpha, x, y, w, s));
+        SPK_HIP(launch_check(b->dtype, 0, nvec, y, ref_y, scale, tau, bad, s));
+        if (w) SPK_HIP(launch_check(b->dtype, 0, nvec, w, ref_w, scale_w, tau, bad, s));
+        SPK_HIP(hipMemcpyAsync(hbad, bad, 8, hipMemcpyDeviceToHost, s));
+        SPK_HIP(hipStreamSynchronize(s));
+        if (*hbad) {
+            ++rejected;
+            return SPK_OK;
+        }
+        for (int r = 0; r < warmup; ++r) SPK_TRY(launch(b, ntiles, alpha, x, y, w, s));
+        for (int r = 0; r < reps; ++r) {
+            if (o.flush) SPK_TRY(spk_flush_cache(h, (spk_stream)s));
+            SPK_HIP(hipEventRecord(ev[2 * r], s));
+            SPK_TRY(launch(b, ntiles, alpha, x, y, w, s));
+            SPK_HIP(hipEventRecord(ev[2 * r + 1], s));
+        }
+        SPK_HIP(hipStreamSynchronize(s));
+        std::vector<double> t;
+        for (int r = 0; r < reps; ++r) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]);
+            t.push_back(ms * 1e3);
+        }
+        std::sort(t.begin(), t.end());
+        *med = t[t.size() / 2];
+        ++tried;
+        return SPK_OK;
+    };
+
+    // launch configuration: workgroup size / LDS tile and persistence,
+    // timed on the whole batch with the current per-class kernels
+    {
+        int n = 0;
+        const BatchEntry *tab = batch_table(&n);
+        const BatchEntry *best_e = b->entry;
+        int best_p = b->opts.persistent;
+        double best_t = 1e300;
+        for (int i = 0; i < n; ++i) {
+            for (int pers : {1, 0}) {
+                b->entry = &tab[i];
+                b->opts.persistent = pers;
+                SPK_TRY(occupancy(b));
+                SPK_TRY(replan(b));
+                double med = 0;
+                SPK_TRY(validate_and_time((int64_t)b->tiles.size(), &med));
+                if (o.verbose)
+                    fprintf(stderr, "spk_batch_tune: block %d tile %d persistent %d: %.2f us\n", tab[i].block,
+                            tab[i].tile, pers, med);
+                if (med > 0 && med < best_t) {
+                    best_t = med;
+                    best_e = &tab[i];
+                    best_p = pers;
+                }
+            }
+        }
+        b->entry = best_e;
+        b->opts.persistent = best_p;
+        SPK_TRY(occupancy(b));
+        SPK_TRY(replan(b));
+    }
+
     std::map<int, std::vector<int64_t>> by_class;
     for (int64_t i = 0; i < b->count; ++i) by_class[b->cls[i]].push_back(i);
     for (auto &kv : by_class) {
@@ -427,34 +498,10 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
             std::vector<BatchTile> tl;
             for (int64_t i : kv.second) cut_instance(b, i, mode, tl);
             SPK_TRY(upload_tiles(b, tl));
-            // validate: only this class's rows are rewritten
-            SPK_HIP(hipMemsetAsync(bad, 0, 8, s));
-            SPK_TRY(launch(b, (int64_t)tl.size(), alpha, x, y, w, s));
-            SPK_HIP(launch_check(b->dtype, 0, nvec, y, ref_y, scale, tau, bad, s));
-            if (w) SPK_HIP(launch_check(b->dtype, 0, nvec, w, ref_w, scale_w, tau, bad, s));
-            SPK_HIP(hipMemcpyAsync(hbad, bad, 8, hipMemcpyDeviceToHost, s));
-            SPK_HIP(hipStreamSynchronize(s));
-            if (*hbad) {
-                ++rejected;
-                continue;
-            }
-            for (int r = 0; r < warmup; ++r) SPK_TRY(launch(b, (int64_t)tl.size(), alpha, x, y, w, s));
-            for (int r = 0; r < reps; ++r) {
-                if (o.flush) SPK_TRY(spk_flush_cache(h, (spk_stream)s));
-                SPK_HIP(hipEventRecord(ev[2 * r], s));
-                SPK_TRY(launch(b, (int64_t)tl.size(), alpha, x, y, w, s));
-                SPK_HIP(hipEventRecord(ev[2 * r + 1], s));
-            }
-            SPK_HIP(hipStreamSynchronize(s));
-            std::vector<double> t;
-            for (int r = 0; r < reps; ++r) {
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]);
-                t.push_back(ms * 1e3);
-            }
-            std::sort(t.begin(), t.end());
-            const double med = t[t.size() / 2];
-            ++tried;
+            // only this class's rows are rewritten by the trial launches
+            double med = 0;
+            SPK_TRY(validate_and_time((int64_t)tl.size(), &med));
+            if (med < 0) continue;
             if (o.verbose) fprintf(stderr, "spk_batch_tune: class %d mode %d: %.2f us\n", c, mode, med);
             if (mode == batch_default_mode(c, b->entry->tile)) plain_time = med;
             if (med < best) {
@@ -499,7 +546,6 @@ spk_status spk_batch_free(spk_handle h, spk_batch b)
     DeviceGuard g(h);
     (void)hipDeviceSynchronize();
     invalidate_graph(b);
-    if (b->d_inst) (void)hipFree(b->d_inst);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->d_ctr) (void)hipFree(b->d_ctr);
     delete b;

@@ -6,20 +6,20 @@
 
 namespace spk {
 
-// One instance: its own CSR arrays, and the offset of its vectors inside
-// the launch's x / y / w.
-struct BatchInst {
+// A tile is rows [r0, r1) (entries [k0, k1)) of one CSR matrix, processed
+// with kernel `mode`: 0 = LDS-staged row stream, G in {2..64} = G lanes per
+// row.  The tile carries its matrix's arrays and the offset of the matrix's
+// vectors inside the launch's x / y / w, so a workgroup needs one 64-byte
+// descriptor load before it can start streaming.
+struct BatchTile {
     const int32_t *rp;
     const int32_t *ci;
     const void *val;
     int64_t vec_off;
-    int32_t m, pad;
+    int32_t r0, r1, k0, k1;
+    int32_t mode, pad0, pad1, pad2;
 };
 
-// A tile is rows [r0, r1) of one instance processed with kernel `mode`:
-// 0 = LDS-staged row stream, G in {2..64} = G lanes per row.
-struct BatchTile {
-    int32_t inst, r0, r1, mode;
-};
+static_assert(sizeof(BatchTile) == 64, "tile descriptor is one 64-byte line");
 
 }  // namespace spk

@@ -125,13 +125,16 @@ struct SpmvArgs {
     const int32_t *sell_len;   // stored entries per row
     const int32_t *sell_ci;
     const T *sell_val;
-    // row blocks (LDS-staged kernel): start row | mode << 30, nblk + 1 entries
+    // row blocks (LDS-staged kernel): start row | mode << 30 and first entry,
+    // nblk + 1 entries each
     const uint32_t *blocks;
+    const int32_t *block_k;
     int32_t blk0, nblk;
 };
 
 constexpr uint32_t kBlkRowMask = 0x3FFFFFFFu;
 constexpr uint32_t kBlkStream = 0u;     // short rows, products staged in LDS
+constexpr int kStreamRowsPerThread = 2; // a row stream holds at most 2*BS rows
 constexpr uint32_t kBlkWave = 1u;       // one wavefront per row
 constexpr uint32_t kBlkBlock = 2u;      // one workgroup for a single long row
 
@@ -139,7 +142,6 @@ constexpr uint32_t kBlkBlock = 2u;      // one workgroup for a single long row
 
 template <typename T>
 struct BatchArgs {
-    const BatchInst *inst;
     const BatchTile *tiles;
     int32_t ntiles;
     const T *x;

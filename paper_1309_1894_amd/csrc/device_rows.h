@@ -7,27 +7,54 @@
 
 namespace spk {
 
-// Row-stream of a run of short rows: stage values and gathered x of the
-// run's entries in LDS with coalesced loads, then each lane sums one row in
-// storage order.  Used by the row-block kernel and the batched kernel.
+// Row stream of a run of short rows [r0, r1) whose entries [k0, k1) fit
+// the LDS tile (k1 - k0 <= TILE, r1 - r0 <= 2*BS):
+//   1. every lane issues its TILE/BS value and column loads at once
+//      (coalesced: lane t takes entries k0 + t + j*BS), then the x gathers,
+//      and stores the products in LDS; the run's row offsets go to LDS too;
+//   2. each lane sums one row's products from LDS (two interleaved partial
+//      sums) and writes y (and w = alpha*y + x).
+// Products are rounded once (FP32 operands: exactly) and summed in FP64.
 template <typename T, int BS, int TILE>
 __device__ __forceinline__ void stream_rows(const int32_t *rp, const int32_t *ci, const T *val, const T *x,
-                                            T *y, T *w, T alpha, int r0, int r1, T *sv, T *sx)
+                                            T *y, T *w, T alpha, int r0, int r1, int k0, int k1, double *sp,
+                                            int *srp)
 {
+    constexpr int ITEMS = TILE / BS;
+    static_assert(ITEMS * BS == TILE, "TILE must be a multiple of BS");
     const int t = threadIdx.x;
-    const int k0 = rp[r0], k1 = rp[r1];
-    for (int k = k0 + t; k < k1; k += BS) {
-        sv[k - k0] = val[k];
-        sx[k - k0] = x[ci[k]];
+    const int nr = r1 - r0;
+    const int nk = k1 - k0;
+    for (int i = t; i <= nr; i += BS) srp[i] = rp[r0 + i] - k0;
+    T v[ITEMS];
+    int c[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int k = t + j * BS;
+        v[j] = k < nk ? val[k0 + k] : T(0);
+        c[j] = k < nk ? ci[k0 + k] : -1;
+    }
+    T xv[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) xv[j] = c[j] >= 0 ? x[c[j]] : T(0);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int k = t + j * BS;
+        if (k < nk) sp[k] = (double)v[j] * (double)xv[j];
     }
     __syncthreads();
-    for (int r = r0 + t; r < r1; r += BS) {
-        const int s = rp[r] - k0, e = rp[r + 1] - k0;
-        double acc = 0.0;
-        for (int k = s; k < e; ++k) acc = fma_t((double)sv[k], (double)sx[k], acc);
-        const T yt = (T)acc;
-        y[r] = yt;
-        if (w) w[r] = fma_t(alpha, yt, x[r]);
+    for (int i = t; i < nr; i += BS) {
+        const int s = srp[i], e = srp[i + 1];
+        double a0 = 0.0, a1 = 0.0;
+        int k = s;
+        for (; k + 1 < e; k += 2) {
+            a0 += sp[k];
+            a1 += sp[k + 1];
+        }
+        if (k < e) a0 += sp[k];
+        const T yt = (T)(a0 + a1);
+        y[r0 + i] = yt;
+        if (w) w[r0 + i] = fma_t(alpha, yt, x[r0 + i]);
     }
     __syncthreads();
 }

@@ -65,8 +65,10 @@ struct SellData {
 
 struct BlockData {
     uint32_t *blk = nullptr;    // nblk + 1 entries (start row | mode << 30)
+    int32_t *bk = nullptr;      // nblk + 1 entries (first entry of each block)
     int32_t nblk = 0;
     std::vector<uint32_t> host;
+    std::vector<int32_t> host_k;
     int64_t bytes = 0;
 };
 
@@ -189,13 +191,13 @@ const BatchEntry *batch_entry(int block, int tile);
 
 // Cuts rows [0, m) of one CSR (host row_ptr) into tiles for `mode`
 // (0 = LDS stream of at most `tile` entries and 2*block rows; G = G lanes
-// per row, about `target` entries per tile).
-void cut_rows(const int32_t *rp, int64_t m, int mode, int block, int tile, int64_t target, int32_t inst,
+// per row, about `target` entries per tile).  Fills r0, r1, k0, k1 and
+// mode; the caller sets the matrix pointers and vector offset.
+void cut_rows(const int32_t *rp, int64_t m, int mode, int block, int tile, int64_t target,
               std::vector<BatchTile> &out);
 
 // One launch of the tile kernel (persistent when `next` is non-null).
-spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchInst *d_inst, const BatchTile *d_tiles,
-                        int64_t ntiles, double alpha, const void *x, void *y, void *w, uint32_t *next,
-                        int64_t persistent_grid, hipStream_t s);
+spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchTile *d_tiles, int64_t ntiles, double alpha,
+                        const void *x, void *y, void *w, uint32_t *next, int64_t persistent_grid, hipStream_t s);
 
 }  // namespace spk

@@ -19,19 +19,18 @@
 namespace spk {
 
 template <typename T, int BS, int TILE>
-__device__ __forceinline__ void run_tile(const BatchArgs<T> &a, int tile, T *sv, T *sx)
+__device__ __forceinline__ void run_tile(const BatchArgs<T> &a, int tile, double *sp, int *srp)
 {
     const BatchTile td = a.tiles[tile];
-    const BatchInst in = a.inst[td.inst];
-    const int32_t *rp = in.rp;
-    const int32_t *ci = in.ci;
-    const T *val = (const T *)in.val;
-    const T *x = a.x + in.vec_off;
-    T *y = a.y + in.vec_off;
-    T *w = a.w ? a.w + in.vec_off : nullptr;
+    const int32_t *rp = td.rp;
+    const int32_t *ci = td.ci;
+    const T *val = (const T *)td.val;
+    const T *x = a.x + td.vec_off;
+    T *y = a.y + td.vec_off;
+    T *w = a.w ? a.w + td.vec_off : nullptr;
     switch (td.mode) {
     case 0:  // entries of the tile fit the LDS tile (guaranteed by the planner)
-        stream_rows<T, BS, TILE>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1, sv, sx);
+        stream_rows<T, BS, TILE>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1, td.k0, td.k1, sp, srp);
         break;
     case 2: group_rows<T, BS, 2>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
     case 4: group_rows<T, BS, 4>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
@@ -45,25 +44,32 @@ __device__ __forceinline__ void run_tile(const BatchArgs<T> &a, int tile, T *sv,
 template <typename T, int BS, int TILE>
 __global__ __launch_bounds__(BS) void k_batch_grid(BatchArgs<T> a)
 {
-    __shared__ T sv[TILE];
-    __shared__ T sx[TILE];
-    run_tile<T, BS, TILE>(a, (int)blockIdx.x, sv, sx);
+    __shared__ double sp[TILE];
+    __shared__ int srp[kStreamRowsPerThread * BS + 1];
+    run_tile<T, BS, TILE>(a, (int)blockIdx.x, sp, srp);
 }
 
 template <typename T, int BS, int TILE>
 __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs<T> a)
 {
-    __shared__ T sv[TILE];
-    __shared__ T sx[TILE];
+    __shared__ double sp[TILE];
+    __shared__ int srp[kStreamRowsPerThread * BS + 1];
     __shared__ int s_tile;
     const int t = threadIdx.x;
-    for (;;) {
-        if (t == 0) s_tile = (int)atomicAdd(a.next, 1u);
+    if (t == 0) s_tile = (int)atomicAdd(a.next, 1u);
+    __syncthreads();
+    int tile = s_tile;
+    __syncthreads();
+    while (tile < a.ntiles) {
+        // the next index is claimed now and read after this tile, so the
+        // atomic's latency hides behind the tile's own loads
+        int claimed = 0;
+        if (t == 0) claimed = (int)atomicAdd(a.next, 1u);
+        run_tile<T, BS, TILE>(a, tile, sp, srp);
+        if (t == 0) s_tile = claimed;
         __syncthreads();
-        const int tile = s_tile;
+        tile = s_tile;
         __syncthreads();
-        if (tile >= a.ntiles) break;
-        run_tile<T, BS, TILE>(a, tile, sv, sx);
     }
     // Every workgroup has drawn past the end of the queue before it counts
     // itself done, so the last one may reset both counters.

@@ -129,8 +129,8 @@ __global__ __launch_bounds__(BS) void k_spmv_sell(SpmvArgs<T> a)
 template <typename T, int BS, int TILE, bool FUSED>
 __global__ __launch_bounds__(BS) void k_spmv_adaptive(SpmvArgs<T> a)
 {
-    __shared__ T sv[TILE];
-    __shared__ T sx[TILE];
+    __shared__ double sp[TILE];
+    __shared__ int srp[kStreamRowsPerThread * BS + 1];
     __shared__ double red[BS / kWave];
     const int b = a.blk0 + (int)blockIdx.x;
     const uint32_t e0 = a.blocks[b], e1 = a.blocks[b + 1];
@@ -138,7 +138,8 @@ __global__ __launch_bounds__(BS) void k_spmv_adaptive(SpmvArgs<T> a)
     const uint32_t mode = e0 >> 30;
     T *w = FUSED ? a.w : nullptr;
     if (mode == kBlkStream) {
-        stream_rows<T, BS, TILE>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, r1, sv, sx);
+        stream_rows<T, BS, TILE>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, r1, a.block_k[b], a.block_k[b + 1],
+                                 sp, srp);
     } else if (mode == kBlkWave) {
         group_rows<T, BS, kWave>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, r1);
     } else {

@@ -97,11 +97,23 @@ __global__ __launch_bounds__(kBS) void k_fill(uint4 *p, int64_t n16, uint32_t pa
         p[i] = v;
 }
 
-// STREAM copy: 16-byte accesses, grid-stride.
+// STREAM copy: 16-byte accesses, four in flight per lane, one pass.
+constexpr int kCopyUnroll = 4;
+
 __global__ __launch_bounds__(kBS) void k_copy(int64_t n2, const double2 *a, double2 *b)
 {
-    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n2; i += (int64_t)gridDim.x * kBS)
-        b[i] = a[i];
+    const int64_t base = (int64_t)blockIdx.x * kBS * kCopyUnroll + threadIdx.x;
+    double2 v[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const int64_t i = base + (int64_t)u * kBS;
+        if (i < n2) v[u] = a[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const int64_t i = base + (int64_t)u * kBS;
+        if (i < n2) b[i] = v[u];
+    }
 }
 
 __global__ __launch_bounds__(kBS) void k_copy_tail(int64_t lo, int64_t n, const double *a, double *b)
@@ -220,7 +232,9 @@ hipError_t launch_copy(int64_t n, const double *a, double *b, hipStream_t s)
 {
     const int64_t n2 = n / 2;
     if (n2 > 0) {
-        hipLaunchKernelGGL(k_copy, dim3(grid_for(n2, 8)), dim3(kBS), 0, s, n2, (const double2 *)a, (double2 *)b);
+        const int64_t per = (int64_t)kBS * kCopyUnroll;
+        hipLaunchKernelGGL(k_copy, dim3((unsigned)((n2 + per - 1) / per)), dim3(kBS), 0, s, n2, (const double2 *)a,
+                           (double2 *)b);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

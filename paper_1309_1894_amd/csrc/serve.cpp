@@ -91,7 +91,7 @@ struct PoolMat {
     int refs = 0;
     double last_use = 0.0;
     hipEvent_t uploaded = nullptr;
-    std::vector<BatchTile> tiles;   // tiles of this matrix (inst field 0)
+    std::vector<BatchTile> tiles;   // row ranges of this matrix (pointers set at launch)
 };
 
 struct Request {
@@ -237,43 +237,43 @@ spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &gro
     Flight F;
     F.dtype = dtype;
     F.reqs = group;
-    std::vector<BatchInst> inst;
     std::vector<BatchTile> tiles;
     int64_t total = 0;
     for (size_t k = 0; k < group.size(); ++k) {
         const PoolMat &M = S->mats[group[k].second.mat];
         F.off.push_back(total);
-        inst.push_back(BatchInst{M.d_rp, M.d_ci, M.d_val, total, (int32_t)M.m, 0});
         for (BatchTile t : M.tiles) {
-            t.inst = (int32_t)k;
+            t.rp = M.d_rp;
+            t.ci = M.d_ci;
+            t.val = M.d_val;
+            t.vec_off = total;
             tiles.push_back(t);
         }
         total += M.m;
     }
+    // one staging block: [tiles | x | y | w], 256-byte aligned parts
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    const size_t inst_b = al(sizeof(BatchInst) * inst.size());
     const size_t tile_b = al(sizeof(BatchTile) * std::max<size_t>(1, tiles.size()));
     const size_t vec_b = al(vs * (size_t)std::max<int64_t>(1, total));
-    const size_t in_b = inst_b + tile_b + vec_b;
+    const size_t in_b = tile_b + vec_b;
     F.y_off = in_b;
     F.w_off = in_b + vec_b;
     const size_t all_b = in_b + 2 * vec_b;
     SPK_HIP(S->dpool.get(all_b, &F.dev));
     SPK_HIP(S->hpool.get(all_b, &F.pin));
     char *pin = (char *)F.pin;
-    memcpy(pin, inst.data(), sizeof(BatchInst) * inst.size());
-    memcpy(pin + inst_b, tiles.data(), sizeof(BatchTile) * tiles.size());
+    memcpy(pin, tiles.data(), sizeof(BatchTile) * tiles.size());
     for (size_t k = 0; k < group.size(); ++k) {
         const Request &R = group[k].second;
         const PoolMat &M = S->mats[R.mat];
-        memcpy(pin + inst_b + tile_b + vs * F.off[k], R.x, vs * M.n);
+        memcpy(pin + tile_b + vs * F.off[k], R.x, vs * M.n);
     }
     hipStream_t s = S->streams[S->next_stream];
     S->next_stream = (S->next_stream + 1) % (int)S->streams.size();
     for (const auto &g : group) SPK_HIP(hipStreamWaitEvent(s, S->mats[g.second.mat].uploaded, 0));
     char *dev = (char *)F.dev;
     SPK_HIP(hipMemcpyAsync(dev, pin, in_b, hipMemcpyHostToDevice, s));
-    const void *x = dev + inst_b + tile_b;
+    const void *x = dev + tile_b;
     void *y = dev + F.y_off;
     void *w = dev + F.w_off;
     if (S->opts.mode == 1) {
@@ -288,8 +288,8 @@ spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &gro
         SPK_TRY(run_spmv(S->h, q, pv, s));
         SPK_TRY(run_waxpy(S->h, M.dtype, M.m, S->opts.alpha, y, x, w, plain_variant(SPK_OP_WAXPY, 0), s));
     } else {
-        SPK_TRY(launch_tiles(S->entry, dtype, (const BatchInst *)dev, (const BatchTile *)(dev + inst_b),
-                             (int64_t)tiles.size(), S->opts.alpha, x, y, w, nullptr, 0, s));
+        SPK_TRY(launch_tiles(S->entry, dtype, (const BatchTile *)dev, (int64_t)tiles.size(),
+                             S->opts.alpha, x, y, w, nullptr, 0, s));
     }
     SPK_HIP(hipMemcpyAsync(pin + F.y_off, y, 2 * vec_b, hipMemcpyDeviceToHost, s));
     F.done = take_event(S);
@@ -524,7 +524,7 @@ spk_status spk_serve_add_matrix(spk_server S, const spk_csr *A, int32_t *id)
     int mode = batch_default_mode(cls, S->entry->tile);
     spk_variant v{};
     if (spk_plan_get(S->h, batch_key(M.dtype, cls).c_str(), &v) == SPK_OK) mode = v.group;
-    cut_rows(M.h_rp, M.m, mode, S->entry->block, S->entry->tile, 2048, 0, M.tiles);
+    cut_rows(M.h_rp, M.m, mode, S->entry->block, S->entry->tile, 2048, M.tiles);
     std::lock_guard<std::mutex> lk(S->mats_mu);
     if (M.dev_bytes + vec_bytes_of(M) > S->opts.hbm_budget) {
         if (M.h_pinned) {
