@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain per-instance baseline")
+    ap.add_argument("--verbose", action="store_true", help="print every tuning candidate")
     ap.add_argument("--instances", type=int, default=4096)
     ap.add_argument("--serve-requests", type=int, default=3000)
     return ap.parse_args()
@@ -93,7 +95,7 @@ def main():
 
     # tuning (Section 2's search, per shape class), not timed
     t0 = time.time()
-    rep = batch.tune(alpha, d_x, d_y, d_w, reps=5, warmup=1)
+    rep = batch.tune(alpha, d_x, d_y, d_w, reps=5, warmup=1, verbose=args.verbose)
     info = batch.info()
     log(f"batch tune: {rep.tried} candidates timed, {rep.rejected} rejected, {info['classes']} classes, "
         f"{info['tiles']} tiles ({time.time() - t0:.1f}s)")
@@ -119,11 +121,17 @@ def main():
     log(f"batched tuned: {ms_per_step:.3f} ms/step, {value:.1f} GB/s (kernel {kern_ms:.3f} ms, {achieved:.1f} GB/s)")
 
     # plain baseline on the same batch: per-instance plain kernels, unfused
-    plain = plain_batch(spk, B, d_x, d_y, d_w, alpha, stream, torch)
-    plain["gbs_of_tuned_bytes"] = round(step_bytes / (plain["ms"] * 1e-3) / 1e9, 1)
+    cfg = batch.config()
+    kname = (f"k_batch_{'persistent' if cfg['persistent'] else 'grid'}<double,{cfg['block']},{cfg['tile_nnz']}>")
+    if args.no_plain:
+        plain = {"ms": None, "skipped": True}
+    else:
+        plain = plain_batch(spk, B, d_x, d_y, d_w, alpha, stream, torch)
+        plain["gbs_of_tuned_bytes"] = round(step_bytes / (plain["ms"] * 1e-3) / 1e9, 1)
     log(f"batched plain: {plain}")
-    out["batched"] = {"tuned_gbs": round(value, 1), "tuned_ms": round(ms_per_step, 4),
-                      "plain": plain, "speedup_vs_plain": round(plain["ms"] / ms_per_step, 2),
+    out["batched"] = {"tuned_gbs": round(value, 1), "tuned_ms": round(ms_per_step, 4), "launch": cfg,
+                      "plain": plain,
+                      "speedup_vs_plain": round(plain["ms"] / ms_per_step, 2) if plain["ms"] else None,
                       "instances": B.count, "rows": nv, "nnz": int(B.nnz.sum()), "bytes_per_step": step_bytes,
                       "tiles": info["tiles"], "classes": info["classes"]}
 
@@ -141,7 +149,7 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(B, x, alpha, step_bytes)
 
-    traffic = load_traffic("k_batch_persistent", step_bytes)
+    traffic = load_traffic(kname, step_bytes)
     result = {
         "metric": "achieved HBM GB/s (% of roofline) SpMV+WAXPY, autotuned vs plain; serving p50/p99",
         "value": round(value, 1),
@@ -161,7 +169,7 @@ def main():
                    "instances": B.count, "rows": nv, "nnz": int(B.nnz.sum()), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "kernel": "k_batch_persistent<double,256,2048>", "bytes_per_launch": step_bytes,
+                     "kernel": kname, "bytes_per_launch": step_bytes,
                      "kernel_ms": round(kern_ms, 4)},
         "cpu_baseline": cpu,
         "extras": out,

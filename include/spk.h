@@ -299,8 +299,10 @@ typedef struct {
 } spk_batch_desc;
 
 typedef struct {
-    int32_t persistent;      /* 1 (default): one persistent launch with a tile
-                              * queue; 0: one workgroup per tile */
+    int32_t persistent;      /* launch kind: 1 (default) one persistent launch
+                              * pulling tiles from per-XCD queues; 0 one
+                              * workgroup per tile; 2 one workgroup per run of
+                              * 4 tiles, software-pipelined */
     int32_t use_graph;       /* 1 (default): replay a captured hipGraph */
     int32_t block;           /* threads per workgroup (0 -> 256) */
     int32_t tile_nnz;        /* target entries per tile (0 -> 2048) */
@@ -329,6 +331,10 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
 /* Number of tiles and classes and the algorithmic bytes of one step. */
 spk_status spk_batch_info(spk_handle h, spk_batch b, int64_t *tiles, int32_t *classes,
                           int64_t *bytes);
+
+/* The launch configuration the batch currently uses (after planning or
+ * tuning): persistence, graph use, workgroup size and LDS tile. */
+spk_status spk_batch_config(spk_handle h, spk_batch b, spk_batch_opts *out);
 
 spk_status spk_batch_free(spk_handle h, spk_batch b);
 

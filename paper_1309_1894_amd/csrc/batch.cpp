@@ -31,7 +31,7 @@ struct spk_batch_s {
     std::vector<spk::BatchTile> tiles;
     spk::BatchTile *d_tiles = nullptr;
     int64_t d_tiles_cap = 0;
-    uint32_t *d_ctr = nullptr;            // [0] queue head, [1] done count
+    uint32_t *d_ctr = nullptr;            // 8 per-XCD queue heads (256 B apart), then the done count
     int64_t grid_persistent = 0;
     // captured launch
     hipGraph_t graph = nullptr;
@@ -43,6 +43,8 @@ struct spk_batch_s {
 
 namespace spk {
 
+constexpr size_t kCounterBytes = 9 * 256;
+
 int batch_class(int64_t m, int64_t nnz)
 {
     const double mean = m > 0 ? (double)nnz / (double)m : 0.0;
@@ -51,12 +53,12 @@ int batch_class(int64_t m, int64_t nnz)
     return c;
 }
 
-int batch_default_mode(int cls, int tile)
+int batch_default_mode(int cls, int entries)
 {
     // mean row length <= 2^cls: short rows go through the LDS stream
     const int mean = 1 << cls;
-    if (mean <= 32 && mean * 4 <= tile) return 0;
-    return std::min(64, std::max(8, mean / 2));
+    if (mean <= 64 && mean * 4 <= entries) return 0;
+    return std::min(64, std::max(8, mean / 4));
 }
 
 std::string batch_key(int dtype, int cls)
@@ -75,17 +77,18 @@ const BatchEntry *batch_entry(int block, int tile)
     return nullptr;
 }
 
-void cut_rows(const int32_t *rp, int64_t m, int mode, int block, int tile, int64_t target,
-              std::vector<BatchTile> &out)
+bool is_stream_mode(int mode) { return mode == 0; }
+
+void cut_rows(const int32_t *rp, int64_t m, int mode, int entries, int64_t target, std::vector<BatchTile> &out)
 {
     int64_t r = 0;
     while (r < m) {
         BatchTile t{};
         t.r0 = (int32_t)r;
         t.mode = mode;
-        if (mode == 0) {
-            if (rp[r + 1] - rp[r] > tile) {
-                // a row that does not fit the LDS tile gets one wavefront
+        if (is_stream_mode(mode)) {
+            if (rp[r + 1] - rp[r] > entries) {
+                // a row that does not fit the wavefront's LDS slice gets one wavefront
                 t.mode = 64;
                 t.r1 = (int32_t)(r + 1);
                 t.k0 = rp[t.r0];
@@ -95,16 +98,17 @@ void cut_rows(const int32_t *rp, int64_t m, int mode, int block, int tile, int64
                 continue;
             }
             int64_t nz = 0, c = 0;
-            while (r < m && c < 2 * (int64_t)block) {
+            while (r < m && c < 2 * 64) {
                 const int64_t l = rp[r + 1] - rp[r];
-                if (nz + l > tile) break;
+                if (nz + l > entries) break;
                 nz += l;
                 ++r;
                 ++c;
             }
             t.r1 = (int32_t)r;
         } else {
-            const int64_t rows_per_pass = block / mode;
+            // G lanes per row: passes of 64/G rows until about `target` entries
+            const int64_t rows_per_pass = 64 / mode;
             int64_t r1 = r, nz = 0;
             while (r1 < m && nz < target) {
                 const int64_t r2 = std::min<int64_t>(m, r1 + rows_per_pass);
@@ -121,7 +125,8 @@ void cut_rows(const int32_t *rp, int64_t m, int mode, int block, int tile, int64
 }
 
 spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchTile *d_tiles, int64_t ntiles, double alpha,
-                        const void *x, void *y, void *w, uint32_t *next, int64_t persistent_grid, hipStream_t s)
+                        const void *x, void *y, void *w, int kind, uint32_t *ctr, int64_t persistent_grid,
+                        hipStream_t s)
 {
     if (ntiles == 0) return SPK_OK;
     union {
@@ -138,13 +143,14 @@ spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchTile *d_tiles
         q.y = (T *)y;
         q.w = (T *)w;
         q.alpha = (T)alpha;
-        q.next = next;
-        q.done = next ? next + 1 : nullptr;
+        q.next = ctr;                              // 8 queue heads, 256 bytes apart
+        q.done = ctr ? ctr + 8 * 64 : nullptr;     // then the completion count
     };
     if (dtype == SPK_F64) fill(a.d); else fill(a.f);
-    const bool pers = next != nullptr;
-    const dim3 grid((unsigned)(pers ? std::min<int64_t>(persistent_grid, ntiles) : ntiles));
-    SPK_HIP(e->fn[dtype][pers ? 1 : 0](dtype == SPK_F64 ? (const void *)&a.d : (const void *)&a.f, grid, s));
+    const int64_t nw = e->block / 64;
+    int64_t g = (ntiles + nw - 1) / nw;   // tile groups, one per workgroup
+    if (kind == kBatchPersistent) g = std::min<int64_t>(persistent_grid, g);
+    SPK_HIP(e->fn[dtype][kind](dtype == SPK_F64 ? (const void *)&a.d : (const void *)&a.f, dim3((unsigned)g), s));
     return SPK_OK;
 }
 
@@ -162,7 +168,7 @@ void invalidate_graph(spk_batch b)
 void cut_instance(const spk_batch b, int64_t i, int mode, std::vector<BatchTile> &out)
 {
     const size_t first = out.size();
-    cut_rows(b->rp_host.data() + b->rp_off[i], b->m[i], mode, b->entry->block, b->entry->tile, b->opts.tile_nnz,
+    cut_rows(b->rp_host.data() + b->rp_off[i], b->m[i], mode, batch_wave_entries(*b->entry), b->opts.tile_nnz,
              out);
     const size_t vs = dtype_size(b->dtype);
     for (size_t k = first; k < out.size(); ++k) {
@@ -202,8 +208,8 @@ spk_status replan(spk_batch b)
 // Launches the tile kernel over `ntiles` tiles already on the device.
 spk_status launch(spk_batch b, int64_t ntiles, double alpha, const void *x, void *y, void *w, hipStream_t s)
 {
-    return launch_tiles(b->entry, b->dtype, b->d_tiles, ntiles, alpha, x, y, w,
-                        b->opts.persistent ? b->d_ctr : nullptr, b->grid_persistent, s);
+    return launch_tiles(b->entry, b->dtype, b->d_tiles, ntiles, alpha, x, y, w, b->opts.persistent, b->d_ctr,
+                        b->grid_persistent, s);
 }
 
 spk_status occupancy(spk_batch b)
@@ -238,10 +244,8 @@ spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *d, const spk_batch
         o = *opts;
     }
     if (o.block == 0) o.block = 256;
-    if (o.tile_nnz == 0) o.tile_nnz = 2048;
-    const int lds_tile = o.tile_nnz <= 1024 ? 1024 : o.tile_nnz <= 2048 ? 2048 : 4096;
-    const BatchEntry *e = batch_entry(o.block, lds_tile);
-    if (!e) e = batch_entry(o.block, 2048);
+    if (o.tile_nnz == 0) o.tile_nnz = 1024;
+    const BatchEntry *e = batch_entry(o.block, 2048);
     if (!e) return fail(SPK_ERR_ARG, "no batched kernel with block %d", o.block);
 
     int64_t rp_total = 0;
@@ -293,12 +297,12 @@ spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *d, const spk_batch
             if (spk_plan_get(h, batch_key(b->dtype, c).c_str(), &v) == SPK_OK && (v.group == 0 || v.group >= 2))
                 b->mode[c] = v.group;
             else
-                b->mode[c] = batch_default_mode(c, e->tile);
+                b->mode[c] = batch_default_mode(c, batch_wave_entries(*e));
         }
     }
     hipError_t he = hipSuccess;
-    if (he == hipSuccess) he = hipMalloc(&b->d_ctr, 256);
-    if (he == hipSuccess) he = hipMemsetAsync(b->d_ctr, 0, 256, h->work);
+    if (he == hipSuccess) he = hipMalloc(&b->d_ctr, kCounterBytes);
+    if (he == hipSuccess) he = hipMemsetAsync(b->d_ctr, 0, kCounterBytes, h->work);
     if (he == hipSuccess) he = hipStreamSynchronize(h->work);
     if (he != hipSuccess) return bail(hip_fail(he, "batch descriptors"));
     spk_status st = occupancy(b);
@@ -380,7 +384,7 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
         void *hp = nullptr;
         ~Free()
         {
-            for (void *p : d) hipFree(p);
+            for (void *p : d) (void)hipFree(p);
             if (hp) (void)hipHostFree(hp);
         }
     } fr;
@@ -415,7 +419,7 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
     for (auto &e : ev) SPK_HIP(hipEventCreate(&e));
     struct EvFree {
         std::vector<hipEvent_t> &e;
-        ~EvFree() { for (auto x : e) hipEventDestroy(x); }
+        ~EvFree() { for (auto x : e) (void)hipEventDestroy(x); }
     } ef{ev};
 
     int tried = 0, rejected = 0;
@@ -464,7 +468,7 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
         int best_p = b->opts.persistent;
         double best_t = 1e300;
         for (int i = 0; i < n; ++i) {
-            for (int pers : {1, 0}) {
+            for (int pers : {kBatchGrid, kBatchPersistent}) {
                 b->entry = &tab[i];
                 b->opts.persistent = pers;
                 SPK_TRY(occupancy(b));
@@ -503,7 +507,7 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
             SPK_TRY(validate_and_time((int64_t)tl.size(), &med));
             if (med < 0) continue;
             if (o.verbose) fprintf(stderr, "spk_batch_tune: class %d mode %d: %.2f us\n", c, mode, med);
-            if (mode == batch_default_mode(c, b->entry->tile)) plain_time = med;
+            if (mode == batch_default_mode(c, batch_wave_entries(*b->entry))) plain_time = med;
             if (med < best) {
                 best = med;
                 best_mode = mode;
@@ -514,7 +518,7 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
         total_plain += plain_time > 0 ? plain_time : best;
         if (o.record) {
             spk_variant v{};
-            v.format = best_mode == 0 ? SPK_FMT_ADAPTIVE : SPK_FMT_VECTOR;
+            v.format = is_stream_mode(best_mode) ? SPK_FMT_ADAPTIVE : SPK_FMT_VECTOR;
             v.block = b->entry->block;
             v.group = best_mode;
             v.lds = b->entry->tile;
@@ -537,6 +541,16 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
     snprintf(report->class_key, sizeof report->class_key, "batch:%s:%d-classes", dtype_name(b->dtype),
              (int)by_class.size());
     if (tried == 0) return fail(SPK_ERR_VALIDATION, "no tile kernel reproduced the reference");
+    return SPK_OK;
+}
+
+spk_status spk_batch_config(spk_handle h, spk_batch b, spk_batch_opts *out)
+{
+    if (!h || !b || !out) return fail(SPK_ERR_NULL, "NULL argument");
+    *out = b->opts;
+    out->block = b->entry->block;
+    out->tile_nnz = b->entry->tile;
+    out->waves_per_cu = (int32_t)(b->grid_persistent / std::max(1, b->h->num_cu)) * (b->entry->block / 64);
     return SPK_OK;
 }
 

@@ -185,19 +185,21 @@ double now_seconds();
 // ------------------------------------------------------- batched tiles
 
 int batch_class(int64_t m, int64_t nnz);
-int batch_default_mode(int cls, int tile);
+bool is_stream_mode(int mode);
+int batch_default_mode(int cls, int entries);
 std::string batch_key(int dtype, int cls);
 const BatchEntry *batch_entry(int block, int tile);
 
-// Cuts rows [0, m) of one CSR (host row_ptr) into tiles for `mode`
-// (0 = LDS stream of at most `tile` entries and 2*block rows; G = G lanes
-// per row, about `target` entries per tile).  Fills r0, r1, k0, k1 and
-// mode; the caller sets the matrix pointers and vector offset.
-void cut_rows(const int32_t *rp, int64_t m, int mode, int block, int tile, int64_t target,
-              std::vector<BatchTile> &out);
+// Cuts rows [0, m) of one CSR (host row_ptr) into wavefront tiles for
+// `mode` (0 = LDS row stream of at most `entries` entries and 128 rows;
+// G = G lanes per row, about `target` entries per tile).  Fills r0, r1, k0,
+// k1 and mode; the caller sets the matrix pointers and vector offset.
+void cut_rows(const int32_t *rp, int64_t m, int mode, int entries, int64_t target, std::vector<BatchTile> &out);
 
-// One launch of the tile kernel (persistent when `next` is non-null).
+// One launch of the tile kernel of launch kind `kind` (kBatchGrid,
+// kBatchPersistent with queue counters `ctr`, or kBatchPipe).
 spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchTile *d_tiles, int64_t ntiles, double alpha,
-                        const void *x, void *y, void *w, uint32_t *next, int64_t persistent_grid, hipStream_t s);
+                        const void *x, void *y, void *w, int kind, uint32_t *ctr, int64_t persistent_grid,
+                        hipStream_t s);
 
 }  // namespace spk

@@ -54,13 +54,21 @@ const SpmvEntry *spmv_table(int *count);
 
 using BatchFn = hipError_t (*)(const void *args, dim3 grid, hipStream_t);
 
+// Launch kinds of the batched kernel.  Tiles are wavefront-sized: a
+// workgroup of BS threads runs BS/64 consecutive tiles, one per wavefront.
+constexpr int kBatchGrid = 0;        // one workgroup per group of BS/64 tiles
+constexpr int kBatchPersistent = 1;  // persistent grid pulling tile groups from per-XCD queues
+
 struct BatchEntry {
-    int block, tile;     // threads per workgroup, LDS tile (entries)
-    BatchFn fn[2][2];    // [dtype][persistent]
+    int block, tile;     // threads per workgroup, LDS products per workgroup
+    BatchFn fn[2][2];    // [dtype][launch kind]
     int (*occupancy[2])();  // [dtype] resident workgroups per CU (persistent kernel)
 };
 
 const BatchEntry *batch_table(int *count);
+
+// Row-stream capacity (entries) of one wavefront's tile.
+inline int batch_wave_entries(const BatchEntry &e) { return e.tile / (e.block / 64); }
 
 // ------------------------------------------------------------- utilities
 

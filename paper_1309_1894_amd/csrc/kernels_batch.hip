@@ -18,8 +18,19 @@
 
 namespace spk {
 
+// Tiles are wavefront-sized: every wavefront of a workgroup runs its own
+// tile, with its own slice of the workgroup's LDS (TILE/(BS/64) products and
+// 129 row offsets), and no workgroup barrier.
 template <typename T, int BS, int TILE>
-__device__ __forceinline__ void run_tile(const BatchArgs<T> &a, int tile, double *sp, int *srp)
+struct WaveTiles {
+    static constexpr int NW = BS / kWave;        // wavefronts per workgroup
+    static constexpr int ENTRIES = TILE / NW;    // row-stream capacity of one wavefront
+    static constexpr int ITEMS = ENTRIES / kWave;
+    static_assert(ITEMS * kWave * NW == TILE, "tile must split evenly over the wavefronts");
+};
+
+template <typename T, int BS, int TILE>
+__device__ __forceinline__ void run_wave_tile(const BatchArgs<T> &a, int tile, double *sp, int *srp)
 {
     const BatchTile td = a.tiles[tile];
     const int32_t *rp = td.rp;
@@ -29,55 +40,87 @@ __device__ __forceinline__ void run_tile(const BatchArgs<T> &a, int tile, double
     T *y = a.y + td.vec_off;
     T *w = a.w ? a.w + td.vec_off : nullptr;
     switch (td.mode) {
-    case 0:  // entries of the tile fit the LDS tile (guaranteed by the planner)
-        stream_rows<T, BS, TILE>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1, td.k0, td.k1, sp, srp);
+    case 0:  // entries and rows fit the wavefront's LDS slice (guaranteed by the planner)
+        wave_stream<T, WaveTiles<T, BS, TILE>::ITEMS>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1, td.k0, td.k1,
+                                                      sp, srp);
         break;
-    case 2: group_rows<T, BS, 2>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
-    case 4: group_rows<T, BS, 4>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
-    case 8: group_rows<T, BS, 8>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
-    case 16: group_rows<T, BS, 16>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
-    case 32: group_rows<T, BS, 32>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
-    default: group_rows<T, BS, 64>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
+    case 2: wave_group_rows<T, 2>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
+    case 4: wave_group_rows<T, 4>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
+    case 8: wave_group_rows<T, 8>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
+    case 16: wave_group_rows<T, 16>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
+    case 32: wave_group_rows<T, 32>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
+    default: wave_group_rows<T, 64>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
     }
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
+// XCD b % 8), and each XCD has its own L2.  Workgroups are dealt tile
+// groups so that XCD k works through one contiguous eighth of the tile
+// list: neighbouring tiles of an instance (which share x entries near their
+// boundary) meet in one L2.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_first(int xcd, int n)
+{
+    const int per = n / kXcds, rem = n % kXcds;
+    return xcd * per + min(xcd, rem);
 }
 
 template <typename T, int BS, int TILE>
 __global__ __launch_bounds__(BS) void k_batch_grid(BatchArgs<T> a)
 {
+    using WT = WaveTiles<T, BS, TILE>;
     __shared__ double sp[TILE];
-    __shared__ int srp[kStreamRowsPerThread * BS + 1];
-    run_tile<T, BS, TILE>(a, (int)blockIdx.x, sp, srp);
+    __shared__ int srp[WT::NW * (kWaveTileRows + 1)];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int ngroups = (a.ntiles + WT::NW - 1) / WT::NW;
+    const int b = (int)blockIdx.x;
+    const int tile = (xcd_first(b % kXcds, ngroups) + b / kXcds) * WT::NW + wv;
+    if (tile < a.ntiles)
+        run_wave_tile<T, BS, TILE>(a, tile, sp + wv * WT::ENTRIES, srp + wv * (kWaveTileRows + 1));
 }
+
+// Persistent form: a grid sized to fill the GPU; the workgroups of XCD k
+// claim chunks of kChunk tile groups from XCD k's own eighth of the list
+// (one queue head per XCD, each in its own 256-byte line), and each
+// wavefront takes its tile of every claimed group.
+constexpr int kChunk = 2;
+constexpr int kCtrStride = 64;   // uint32 per counter line
 
 template <typename T, int BS, int TILE>
 __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs<T> a)
 {
+    using WT = WaveTiles<T, BS, TILE>;
     __shared__ double sp[TILE];
-    __shared__ int srp[kStreamRowsPerThread * BS + 1];
-    __shared__ int s_tile;
+    __shared__ int srp[WT::NW * (kWaveTileRows + 1)];
+    __shared__ int s_claim;
     const int t = threadIdx.x;
-    if (t == 0) s_tile = (int)atomicAdd(a.next, 1u);
-    __syncthreads();
-    int tile = s_tile;
-    __syncthreads();
-    while (tile < a.ntiles) {
-        // the next index is claimed now and read after this tile, so the
-        // atomic's latency hides behind the tile's own loads
-        int claimed = 0;
-        if (t == 0) claimed = (int)atomicAdd(a.next, 1u);
-        run_tile<T, BS, TILE>(a, tile, sp, srp);
-        if (t == 0) s_tile = claimed;
+    const int wv = __builtin_amdgcn_readfirstlane(t / kWave);
+    const int ngroups = (a.ntiles + WT::NW - 1) / WT::NW;
+    const int xcd = (int)blockIdx.x % kXcds;
+    const int lo = xcd_first(xcd, ngroups);
+    const int hi = xcd_first(xcd + 1, ngroups);
+    uint32_t *head = a.next + xcd * kCtrStride;
+    for (;;) {
+        if (t == 0) s_claim = lo + (int)atomicAdd(head, (uint32_t)kChunk);
         __syncthreads();
-        tile = s_tile;
+        const int c0 = s_claim;
         __syncthreads();
+        if (c0 >= hi) break;
+        const int c1 = min(c0 + kChunk, hi);
+        for (int g = c0; g < c1; ++g) {
+            const int tile = g * WT::NW + wv;
+            if (tile < a.ntiles)
+                run_wave_tile<T, BS, TILE>(a, tile, sp + wv * WT::ENTRIES, srp + wv * (kWaveTileRows + 1));
+        }
     }
-    // Every workgroup has drawn past the end of the queue before it counts
-    // itself done, so the last one may reset both counters.
+    // Every workgroup has drawn past the end of its queue before it counts
+    // itself done, so the last one may reset all counters.
     if (t == 0) {
         __threadfence();
         const uint32_t d = atomicAdd(a.done, 1u);
         if (d == gridDim.x - 1u) {
-            atomicExch(a.next, 0u);
+            for (int k = 0; k < kXcds; ++k) atomicExch(a.next + k * kCtrStride, 0u);
             atomicExch(a.done, 0u);
         }
     }
@@ -95,20 +138,24 @@ int occ_batch()
     return n > 0 ? n : 1;
 }
 
-template <typename T, int BS, int TILE, bool P>
+template <typename T, int BS, int TILE, int KIND>
 hipError_t L_batch(const void *p, dim3 g, hipStream_t s)
 {
-    if constexpr (P)
+    if constexpr (KIND == 1)
         hipLaunchKernelGGL((k_batch_persistent<T, BS, TILE>), g, dim3(BS), 0, s, *(const BatchArgs<T> *)p);
     else
         hipLaunchKernelGGL((k_batch_grid<T, BS, TILE>), g, dim3(BS), 0, s, *(const BatchArgs<T> *)p);
     return hipGetLastError();
 }
 
-#define BENTRY(BS, TILE) {BS, TILE, {{L_batch<float, BS, TILE, false>, L_batch<float, BS, TILE, true>}, \
-                                     {L_batch<double, BS, TILE, false>, L_batch<double, BS, TILE, true>}}, \
-                         {occ_batch<float, BS, TILE>, occ_batch<double, BS, TILE>}}
+#define BENTRY(BS, TILE)                                                                     \
+    {BS, TILE,                                                                               \
+     {{L_batch<float, BS, TILE, 0>, L_batch<float, BS, TILE, 1>},                            \
+      {L_batch<double, BS, TILE, 0>, L_batch<double, BS, TILE, 1>}},                         \
+     {occ_batch<float, BS, TILE>, occ_batch<double, BS, TILE>}}
 
+// (threads per workgroup, LDS products per workgroup): a wavefront's row
+// stream holds TILE/(BS/64) entries: 256, 512 or 1024
 const BatchEntry kBatch[] = {
     BENTRY(256, 2048), BENTRY(256, 1024), BENTRY(256, 4096),
     BENTRY(128, 1024), BENTRY(128, 2048),

@@ -288,8 +288,8 @@ spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &gro
         SPK_TRY(run_spmv(S->h, q, pv, s));
         SPK_TRY(run_waxpy(S->h, M.dtype, M.m, S->opts.alpha, y, x, w, plain_variant(SPK_OP_WAXPY, 0), s));
     } else {
-        SPK_TRY(launch_tiles(S->entry, dtype, (const BatchTile *)dev, (int64_t)tiles.size(),
-                             S->opts.alpha, x, y, w, nullptr, 0, s));
+        SPK_TRY(launch_tiles(S->entry, dtype, (const BatchTile *)dev, (int64_t)tiles.size(), S->opts.alpha, x, y,
+                             w, kBatchGrid, nullptr, 0, s));
     }
     SPK_HIP(hipMemcpyAsync(pin + F.y_off, y, 2 * vec_b, hipMemcpyDeviceToHost, s));
     F.done = take_event(S);
@@ -521,10 +521,10 @@ spk_status spk_serve_add_matrix(spk_server S, const spk_csr *A, int32_t *id)
     M.dev_bytes = (int64_t)(brp + bci + bv);
     // tiles by the plan of the matrix's shape class
     const int cls = batch_class(M.m, M.nnz);
-    int mode = batch_default_mode(cls, S->entry->tile);
+    int mode = batch_default_mode(cls, batch_wave_entries(*S->entry));
     spk_variant v{};
     if (spk_plan_get(S->h, batch_key(M.dtype, cls).c_str(), &v) == SPK_OK) mode = v.group;
-    cut_rows(M.h_rp, M.m, mode, S->entry->block, S->entry->tile, 2048, M.tiles);
+    cut_rows(M.h_rp, M.m, mode, batch_wave_entries(*S->entry), 1024, M.tiles);
     std::lock_guard<std::mutex> lk(S->mats_mu);
     if (M.dev_bytes + vec_bytes_of(M) > S->opts.hbm_budget) {
         if (M.h_pinned) {

@@ -123,6 +123,7 @@ _SIGS = {
     "spk_batch_run": (_S, [_P, _P, _D, _P, _P, _P, _P]),
     "spk_batch_tune": (_S, [_P, _P, _D, _P, _P, _P, C.POINTER(spk_tune_opts), C.POINTER(spk_tune_report)]),
     "spk_batch_info": (_S, [_P, _P, C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_I64)]),
+    "spk_batch_config": (_S, [_P, _P, C.POINTER(spk_batch_opts)]),
     "spk_batch_free": (_S, [_P, _P]),
     "spk_serve_create": (_S, [_P, C.POINTER(spk_serve_opts), C.POINTER(_P)]),
     "spk_serve_add_matrix": (_S, [_P, C.POINTER(spk_csr), C.POINTER(_I32)]),
@@ -481,6 +482,11 @@ class Batch:
         t, c, b = _I64(), _I32(), _I64()
         _ok(_lib.spk_batch_info(self.handle.ptr, self.ptr, C.byref(t), C.byref(c), C.byref(b)), "spk_batch_info")
         return {"tiles": int(t.value), "classes": int(c.value), "bytes": int(b.value)}
+
+    def config(self) -> dict:
+        o = spk_batch_opts()
+        _ok(_lib.spk_batch_config(self.handle.ptr, self.ptr, C.byref(o)), "spk_batch_config")
+        return {f: int(getattr(o, f)) for f, _ in o._fields_}
 
     def free(self):
         if self.ptr:
