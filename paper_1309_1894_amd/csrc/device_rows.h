@@ -167,11 +167,6 @@ __device__ __forceinline__ void wave_lds_sync()
 
 constexpr int kWaveTileRows = 2 * kWave;   // rows of one wavefront's row stream
 
-// One wavefront streams a run of short rows [r0, r1) with entries [k0, k1)
-// (k1 - k0 <= 64*ITEMS, r1 - r0 <= 128) through its private LDS slice:
-// all value/column/row-offset/own-x loads at once, then the x gather,
-// products to LDS, one lane per row sums from LDS.  No workgroup barrier:
-// every wavefront of a CU is an independent stream.
 // Products of a wavefront tile's entries, written to its LDS slice
 // (sp[k - k0] for entry k).  Lane l takes entries k0 + l + 64j: coalesced
 // 8-byte value and 4-byte column loads.
@@ -196,84 +191,6 @@ __device__ __forceinline__ void wave_products(const int32_t *ci, const T *val, c
     for (int j = 0; j < ITEMS; ++j) {
         const int k = l + j * kWave;
         if (k < nk) sp[k] = (double)v[j] * (double)xv[j];
-    }
-}
-
-// One wavefront streams a run of short rows [r0, r1) with entries [k0, k1)
-// (k1 - k0 <= 64*ITEMS, r1 - r0 <= 128) through its private LDS slice:
-// all value/column/row-offset/own-x loads at once, then the x gather,
-// products to LDS, one lane per row sums from LDS.  No workgroup barrier:
-// every wavefront of a CU is an independent stream.
-// Products of a wavefront tile's entries, written to its LDS slice
-// (sp[k - k0] for entry k).  Lane l takes entries k0 + l + 64j: coalesced
-// 8-byte value and 4-byte column loads.
-template <typename T, int ITEMS>
-__device__ __forceinline__ void wave_products(const int32_t *ci, const T *val, const T *x, int k0, int nk, double *sp)
-{
-    const int l = threadIdx.x & (kWave - 1);
-    T v[ITEMS];
-    int c[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int k = l + j * kWave;
-        // matrix entries are read exactly once: non-temporal, so the cache
-        // keeps the x entries that neighbouring rows share
-        v[j] = k < nk ? __builtin_nontemporal_load(val + k0 + k) : T(0);
-        c[j] = k < nk ? __builtin_nontemporal_load(ci + k0 + k) : -1;
-    }
-    T xv[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) xv[j] = c[j] >= 0 ? x[c[j]] : T(0);
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int k = l + j * kWave;
-        if (k < nk) sp[k] = (double)v[j] * (double)xv[j];
-    }
-}
-
-// FP64 form with paired accesses: lane l takes the entry pair starting at
-// kb + 2(l + 64j), where kb <= k0 makes val + kb 16-byte aligned (one
-// 16-byte value load and one 8-byte column load per pair).  Needs
-// nk <= 64*ITEMS - 1 and ci + kb 8-byte aligned.  A pair that straddles the
-// tile end is loaded element-wise, so nothing past entry k1 - 1 is read.
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-typedef int i32x2 __attribute__((ext_vector_type(2)));
-
-template <int ITEMS>
-__device__ __forceinline__ void wave_products_pairs(const int32_t *ci, const double *val, const double *x, int k0,
-                                                    int nk, int kb, double *sp)
-{
-    static_assert(ITEMS % 2 == 0, "pairs");
-    const int l = threadIdx.x & (kWave - 1);
-    const int k1 = k0 + nk;
-    f64x2 v[ITEMS / 2];
-    i32x2 c[ITEMS / 2];
-#pragma unroll
-    for (int j = 0; j < ITEMS / 2; ++j) {
-        const int e = kb + 2 * (l + j * kWave);
-        if (e + 1 < k1) {
-            v[j] = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(val + e));
-            c[j] = __builtin_nontemporal_load(reinterpret_cast<const i32x2 *>(ci + e));
-        } else if (e < k1) {
-            v[j] = f64x2{val[e], 0.0};
-            c[j] = i32x2{ci[e], -1};
-        } else {
-            v[j] = f64x2{0.0, 0.0};
-            c[j] = i32x2{-1, -1};
-        }
-        if (e < k0) c[j].x = -1;   // the aligned start may precede the tile
-    }
-    f64x2 xv[ITEMS / 2];
-#pragma unroll
-    for (int j = 0; j < ITEMS / 2; ++j) {
-        xv[j].x = c[j].x >= 0 ? x[c[j].x] : 0.0;
-        xv[j].y = c[j].y >= 0 ? x[c[j].y] : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < ITEMS / 2; ++j) {
-        const int e = kb + 2 * (l + j * kWave);
-        if (c[j].x >= 0) sp[e - k0] = v[j].x * xv[j].x;
-        if (c[j].y >= 0) sp[e + 1 - k0] = v[j].y * xv[j].y;
     }
 }
 
