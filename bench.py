@@ -399,16 +399,32 @@ def cpu_baseline(B, x, alpha, step_bytes):
                       f"{sec * 1e3:.1f} ms per step"}
 
 
+# Sources of the batched kernel: the committed counter figures apply only
+# while these are unchanged.
+TILE_KERNEL_SOURCES = ["kernels_batch.hip", "device_rows.h", "device_common.h", "batch_types.h", "kernels.h"]
+
+
+def tile_kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in TILE_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1309_1894_amd", "csrc", f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
 def load_traffic(kernel, bytes_per_launch):
-    """HBM bytes per launch from the committed counter summary, if it matches this build."""
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel calibration),
+    or None when the kernel's sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
-        from paper_1309_1894_amd import build as _b
-        if t.get("build_id") != _b.build_id():
+        if t.get("kernel_source_hash") != tile_kernel_hash():
             return None
-        return t.get(kernel)
+        return t.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
     except (OSError, ValueError):
         return None
 
