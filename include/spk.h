@@ -78,7 +78,7 @@ typedef enum {
     SPK_FMT_SCALAR = 1,     /* CSR, one lane per row */
     SPK_FMT_VECTOR = 2,     /* CSR, `group` lanes per row (64 = one wavefront) */
     SPK_FMT_SELL = 3,       /* sliced ELL, `group` rows per slice, column-major slices */
-    SPK_FMT_ADAPTIVE = 4    /* CSR row blocks staged through LDS (`lds` entries per block) */
+    SPK_FMT_ADAPTIVE = 4    /* CSR wavefront tiles staged through LDS (`lds` entries per wavefront) */
 } spk_format;
 
 typedef void *spk_stream;                 /* hipStream_t */
@@ -111,9 +111,9 @@ typedef struct {
  *   grid    vector ops: 0 = one pass, else workgroups per compute unit of a
  *           grid-stride launch
  *   streams SpMV: split rows over this many streams (1, 2 or 4)
- *   lds     SpMV VECTOR: 1 = stage row_ptr in LDS; ADAPTIVE: LDS tile in
- *           entries per workgroup (the "L1 size" knob; gfx950 has no L1/LDS
- *           split, so the staged tile size takes its place) */
+ *   lds     SpMV VECTOR: 1 = stage row_ptr in LDS; ADAPTIVE: LDS row-stream
+ *           capacity in entries per wavefront (the "L1 size" knob; gfx950
+ *           has no L1/LDS split, so the staged tile size takes its place) */
 typedef struct {
     int32_t format, block, group, unroll, vec, grid, streams, lds;
 } spk_variant;

@@ -150,7 +150,7 @@ spk_variant default_variant(spk_handle h, const spk_problem &p, const spk_csr *c
         v.format = SPK_FMT_ADAPTIVE;
         v.block = 256;
         v.group = 1;
-        v.lds = 2048;
+        v.lds = 512;
         return v;
     }
     const double mean = csr && csr->nrows > 0 ? (double)csr->nnz / (double)csr->nrows : 1.0;
@@ -322,7 +322,7 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
     SellData *sd = nullptr;
     BlockData *bd = nullptr;
     if (v.format == SPK_FMT_SELL) SPK_TRY(get_sell(h, p.mat, v.group, &sd));
-    if (v.format == SPK_FMT_ADAPTIVE) SPK_TRY(get_blocks(h, p.mat, v.block, v.lds, &bd));
+    if (v.format == SPK_FMT_ADAPTIVE) SPK_TRY(get_blocks(h, p.mat, v.lds, &bd));
 
     const int parts = std::max(1, v.streams);
     // launch pieces: rows [cut[i], cut[i+1]) or row blocks for ADAPTIVE
@@ -352,7 +352,8 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
                 a.block_k = bd->bk;
                 a.blk0 = (int32_t)lo;
                 a.nblk = (int32_t)(hi - lo);
-                grid = dim3((unsigned)(hi - lo));
+                const int64_t nw = v.block / 64;   // one wavefront tile per wavefront
+                grid = dim3((unsigned)((hi - lo + nw - 1) / nw));
             } else {
                 a.row0 = (int32_t)lo;
                 a.m = (int32_t)(hi - lo);
@@ -439,13 +440,16 @@ spk_status get_sell(spk_handle h, spk_mat *A, int C, SellData **out)
 // Row blocks for the LDS-staged kernel: runs of short rows whose entries
 // fit `tile` (at most 2*block rows), up to block/64 medium rows handled one
 // wavefront each, and single long rows handled by a whole workgroup.
-static void make_blocks(const std::vector<int32_t> &rp, int64_t m, int block, int tile, std::vector<uint32_t> &out,
+// Wavefront tiles for the LDS-staged kernel, E = row-stream capacity:
+// runs of short rows (at most 96 entries each) whose entries fit E and that
+// number at most 128; runs of medium rows, up to 4E entries in all, one
+// wavefront with 64 lanes per row; single long rows (over 8E entries).
+static void make_blocks(const std::vector<int32_t> &rp, int64_t m, int E, std::vector<uint32_t> &out,
                         std::vector<int32_t> &out_k)
 {
-    const int64_t kShort = std::min<int64_t>(96, tile);
-    const int64_t kLong = (int64_t)block * 8;
-    const int64_t row_cap = (int64_t)kStreamRowsPerThread * block;
-    const int64_t waves = block / 64;
+    const int64_t kShort = std::min<int64_t>(96, E);
+    const int64_t kLong = 8 * (int64_t)E;
+    const int64_t kRows = 2 * 64;
     out.clear();
     out_k.clear();
     int64_t r = 0;
@@ -453,23 +457,23 @@ static void make_blocks(const std::vector<int32_t> &rp, int64_t m, int block, in
         const int64_t len = rp[r + 1] - rp[r];
         out_k.push_back(rp[r]);
         if (len > kLong) {
-            out.push_back((uint32_t)r | (kBlkBlock << 30));
+            out.push_back((uint32_t)r | (kBlkLong << 30));
             ++r;
         } else if (len > kShort) {
             out.push_back((uint32_t)r | (kBlkWave << 30));
-            int64_t c = 0;
-            while (r < m && c < waves) {
+            int64_t nz = 0;
+            while (r < m) {
                 const int64_t l = rp[r + 1] - rp[r];
-                if (l <= kShort || l > kLong) break;
+                if (l <= kShort || l > kLong || (nz > 0 && nz + l > 4 * (int64_t)E)) break;
+                nz += l;
                 ++r;
-                ++c;
             }
         } else {
             out.push_back((uint32_t)r | (kBlkStream << 30));
             int64_t nz = 0, c = 0;
-            while (r < m && c < row_cap) {
+            while (r < m && c < kRows) {
                 const int64_t l = rp[r + 1] - rp[r];
-                if (l > kShort || nz + l > tile) break;
+                if (l > kShort || nz + l > E) break;
                 nz += l;
                 ++r;
                 ++c;
@@ -480,17 +484,17 @@ static void make_blocks(const std::vector<int32_t> &rp, int64_t m, int block, in
     out_k.push_back(rp[m]);
 }
 
-spk_status get_blocks(spk_handle h, spk_mat *A, int block, int tile, BlockData **out)
+spk_status get_blocks(spk_handle h, spk_mat *A, int entries, BlockData **out)
 {
     std::lock_guard<std::mutex> lk(h->mu);
-    const auto key = std::make_pair(block, tile);
+    const auto key = std::make_pair(0, entries);
     auto it = A->blocks.find(key);
     if (it != A->blocks.end()) {
         *out = &it->second;
         return SPK_OK;
     }
     BlockData d;
-    make_blocks(A->rp_host, A->nrows, block, tile, d.host, d.host_k);
+    make_blocks(A->rp_host, A->nrows, entries, d.host, d.host_k);
     d.nblk = (int32_t)d.host.size() - 1;
     SPK_HIP(hipMalloc(&d.blk, sizeof(uint32_t) * d.host.size()));
     SPK_HIP(hipMalloc(&d.bk, sizeof(int32_t) * d.host_k.size()));

@@ -106,6 +106,20 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
+// XCD b % 8), each XCD with its own L2.  Remapping workgroup b to item
+// xcd_first(b % 8, n) + b / 8 gives XCD k one contiguous eighth of the n
+// items, so neighbouring items (which share x entries) meet in one L2.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_first(int xcd, int n)
+{
+    const int per = n / kXcds, rem = n % kXcds;
+    return xcd * per + min(xcd, rem);
+}
+
+__device__ __forceinline__ int xcd_remap(int b, int n) { return xcd_first(b % kXcds, n) + b / kXcds; }
+
 // ------------------------------------------------------------ SpMV operands
 
 // One launch of a SpMV kernel over the row range [row0, row0 + m) (or, for
@@ -132,11 +146,12 @@ struct SpmvArgs {
     int32_t blk0, nblk;
 };
 
+// Row blocks of the LDS-staged kernel are wavefront tiles:
 constexpr uint32_t kBlkRowMask = 0x3FFFFFFFu;
-constexpr uint32_t kBlkStream = 0u;     // short rows, products staged in LDS
-constexpr int kStreamRowsPerThread = 2; // a row stream holds at most 2*BS rows
-constexpr uint32_t kBlkWave = 1u;       // one wavefront per row
-constexpr uint32_t kBlkBlock = 2u;      // one workgroup for a single long row
+constexpr uint32_t kBlkStream = 0u;     // short rows streamed through the wavefront's LDS slice
+constexpr int kStreamRowsPerThread = 2; // a workgroup row stream holds at most 2*BS rows
+constexpr uint32_t kBlkWave = 1u;       // medium rows, one after another, 64 lanes per row
+constexpr uint32_t kBlkLong = 2u;       // one long row, 64 lanes
 
 // ------------------------------------------------------------ batched tiles
 

@@ -1,157 +1,10 @@
-// device_rows.h -- per-row work shared by the single-matrix row-block
-// kernel and the batched tile kernel, so that a row gives the same bits in
-// either.
+// device_rows.h -- per-row work of wavefront tiles, shared by the
+// single-matrix row-block kernel and the batched tile kernel.
 #pragma once
 
 #include "device_common.h"
 
 namespace spk {
-
-// Row stream of a run of short rows [r0, r1) whose entries [k0, k1) fit
-// the LDS tile (k1 - k0 <= TILE, r1 - r0 <= 2*BS):
-//   1. every lane issues its TILE/BS value and column loads at once
-//      (coalesced: lane t takes entries k0 + t + j*BS), then the x gathers,
-//      and stores the products in LDS; the run's row offsets go to LDS too;
-//   2. each lane sums one row's products from LDS (two interleaved partial
-//      sums) and writes y (and w = alpha*y + x).
-// Products are rounded once (FP32 operands: exactly) and summed in FP64.
-template <typename T, int BS, int TILE, int RG = 1>
-__device__ __forceinline__ void stream_rows(const int32_t *rp, const int32_t *ci, const T *val, const T *x,
-                                            T *y, T *w, T alpha, int r0, int r1, int k0, int k1, double *sp,
-                                            int *srp)
-{
-    constexpr int ITEMS = TILE / BS;
-    constexpr int RPT = kStreamRowsPerThread;
-    static_assert(ITEMS * BS == TILE, "TILE must be a multiple of BS");
-    const int t = threadIdx.x;
-    const int nr = r1 - r0;
-    const int nk = k1 - k0;
-    // phase 1: every independent load of the run at once -- values,
-    // columns, row offsets (and, for one lane per row, the x entries the
-    // step adds to each row)
-    T v[ITEMS];
-    int c[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int k = t + j * BS;
-        v[j] = k < nk ? val[k0 + k] : T(0);
-        c[j] = k < nk ? ci[k0 + k] : -1;
-    }
-    int rpv[RPT + 1];
-#pragma unroll
-    for (int q = 0; q <= RPT; ++q) rpv[q] = (t + q * BS <= nr) ? rp[r0 + t + q * BS] - k0 : 0;
-    T xo[RPT];
-    if constexpr (RG == 1) {
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) xo[q] = (w && t + q * BS < nr) ? x[r0 + t + q * BS] : T(0);
-    }
-    // phase 2: the x gather, products to LDS
-    T xv[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) xv[j] = c[j] >= 0 ? x[c[j]] : T(0);
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int k = t + j * BS;
-        if (k < nk) sp[k] = (double)v[j] * (double)xv[j];
-    }
-#pragma unroll
-    for (int q = 0; q <= RPT; ++q)
-        if (t + q * BS <= nr) srp[t + q * BS] = rpv[q];
-    __syncthreads();
-    // phase 3: row sums from LDS
-    if constexpr (RG == 1) {
-        // one lane per row, two interleaved partial sums
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            const int i = t + q * BS;
-            if (i < nr) {
-                const int s = srp[i], e = srp[i + 1];
-                double a0 = 0.0, a1 = 0.0;
-                int k = s;
-                for (; k + 1 < e; k += 2) {
-                    a0 += sp[k];
-                    a1 += sp[k + 1];
-                }
-                if (k < e) a0 += sp[k];
-                const T yt = (T)(a0 + a1);
-                y[r0 + i] = yt;
-                if (w) w[r0 + i] = fma_t(alpha, yt, xo[q]);
-            }
-        }
-    } else {
-        // RG adjacent lanes per row: they read consecutive LDS words (no
-        // bank conflicts) and meet in a DPP group sum
-        const int lane = t & (RG - 1);
-        for (int rb = 0; rb < nr; rb += BS / RG) {
-            const int i = rb + t / RG;
-            double acc = 0.0;
-            if (i < nr) {
-                const int e = srp[i + 1];
-                for (int k = srp[i] + lane; k < e; k += RG) acc += sp[k];
-            }
-            acc = group_sum<RG>(acc);
-            if (lane == 0 && i < nr) {
-                const T yt = (T)acc;
-                y[r0 + i] = yt;
-                if (w) w[r0 + i] = fma_t(alpha, yt, x[r0 + i]);
-            }
-        }
-    }
-    __syncthreads();
-}
-
-// G lanes per row over rows [r0, r1) of one matrix (all lanes take part).
-template <typename T, int BS, int G>
-__device__ __forceinline__ void group_rows(const int32_t *rp, const int32_t *ci, const T *val, const T *x,
-                                           T *y, T *w, T alpha, int r0, int r1)
-{
-    constexpr int RPI = BS / G;
-    const int t = threadIdx.x;
-    const int lane = t & (G - 1);
-    for (int rb = r0; rb < r1; rb += RPI) {
-        const int row = rb + t / G;
-        int s = 0, e = 0;
-        if (row < r1) {
-            s = rp[row];
-            e = rp[row + 1];
-        }
-        double a0 = 0.0, a1 = 0.0;
-        int k = s + lane;
-        for (; k + G < e; k += 2 * G) {
-            a0 = fma_t((double)val[k], (double)x[ci[k]], a0);
-            a1 = fma_t((double)val[k + G], (double)x[ci[k + G]], a1);
-        }
-        if (k < e) a0 = fma_t((double)val[k], (double)x[ci[k]], a0);
-        double sum = group_sum<G>(a0 + a1);
-        if (lane == 0 && row < r1) {
-            const T yt = (T)sum;
-            y[row] = yt;
-            if (w) w[row] = fma_t(alpha, yt, x[row]);
-        }
-    }
-}
-
-// One long row with the whole workgroup.
-template <typename T, int BS>
-__device__ __forceinline__ void block_row(const int32_t *rp, const int32_t *ci, const T *val, const T *x,
-                                          T *y, T *w, T alpha, int row, double *red)
-{
-    const int t = threadIdx.x;
-    const int s = rp[row], e = rp[row + 1];
-    double a0 = 0.0, a1 = 0.0;
-    int k = s + t;
-    for (; k + BS < e; k += 2 * BS) {
-        a0 = fma_t((double)val[k], (double)x[ci[k]], a0);
-        a1 = fma_t((double)val[k + BS], (double)x[ci[k + BS]], a1);
-    }
-    if (k < e) a0 = fma_t((double)val[k], (double)x[ci[k]], a0);
-    const double sum = block_sum<BS>(a0 + a1, red);
-    if (t == 0) {
-        const T yt = (T)sum;
-        y[row] = yt;
-        if (w) w[row] = fma_t(alpha, yt, x[row]);
-    }
-}
 
 // ------------------------------------------------ wavefront-private tiles
 
@@ -261,6 +114,49 @@ __device__ __forceinline__ void wave_group_rows(const int32_t *rp, const int32_t
         if (k < e) a0 = fma_t((double)val[k], (double)x[ci[k]], a0);
         const double sum = group_sum<G>(a0 + a1);
         if (lane == 0 && row < r1) {
+            const T yt = (T)sum;
+            y[row] = yt;
+            if (w) w[row] = fma_t(alpha, yt, x[row]);
+        }
+    }
+}
+
+// Rows [r0, r1) one after another, each with all 64 lanes of one
+// wavefront: per pass every lane issues UNR value/column loads, then UNR x
+// gathers, before it accumulates, so a row keeps 64*UNR gathers in flight
+// (the gathers of random-column rows are latency-bound).  UNR partial sums
+// per lane, combined in a fixed order, then the wavefront sum.
+template <typename T, int UNR>
+__device__ __forceinline__ void wave_rows_mlp(const int32_t *rp, const int32_t *ci, const T *val, const T *x, T *y,
+                                              T *w, T alpha, int r0, int r1)
+{
+    const int l = threadIdx.x & (kWave - 1);
+    for (int row = r0; row < r1; ++row) {
+        const int s = rp[row], e = rp[row + 1];
+        double acc[UNR];
+#pragma unroll
+        for (int j = 0; j < UNR; ++j) acc[j] = 0.0;
+        for (int base = s; base < e; base += kWave * UNR) {
+            T v[UNR];
+            int c[UNR];
+#pragma unroll
+            for (int j = 0; j < UNR; ++j) {
+                const int k = base + l + j * kWave;
+                v[j] = k < e ? __builtin_nontemporal_load(val + k) : T(0);
+                c[j] = k < e ? __builtin_nontemporal_load(ci + k) : -1;
+            }
+            T xv[UNR];
+#pragma unroll
+            for (int j = 0; j < UNR; ++j) xv[j] = c[j] >= 0 ? x[c[j]] : T(0);
+#pragma unroll
+            for (int j = 0; j < UNR; ++j) acc[j] = fma_t((double)v[j], (double)xv[j], acc[j]);
+        }
+#pragma unroll
+        for (int d = 1; d < UNR; d *= 2)
+#pragma unroll
+            for (int j = 0; j + d < UNR; j += 2 * d) acc[j] += acc[j + d];
+        const double sum = group_sum<kWave>(acc[0]);
+        if (l == 0) {
             const T yt = (T)sum;
             y[row] = yt;
             if (w) w[row] = fma_t(alpha, yt, x[row]);

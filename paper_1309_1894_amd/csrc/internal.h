@@ -86,7 +86,7 @@ struct spk_mat {
     int64_t max_len = 0;
     int64_t bytes = 0;
     std::map<int, spk::SellData> sell;                       // by slice height
-    std::map<std::pair<int, int>, spk::BlockData> blocks;    // by (block, tile)
+    std::map<std::pair<int, int>, spk::BlockData> blocks;    // by (0, wavefront entries)
 };
 
 namespace spk {
@@ -170,7 +170,7 @@ std::string class_key(const spk_problem &p, const spk_csr *csr);
 
 // Derived formats of a registered matrix (built on first use; synchronous).
 spk_status get_sell(spk_handle h, spk_mat *A, int C, SellData **out);
-spk_status get_blocks(spk_handle h, spk_mat *A, int block, int tile, BlockData **out);
+spk_status get_blocks(spk_handle h, spk_mat *A, int entries, BlockData **out);
 int64_t sell_padded_entries(const spk_mat *A, int C);
 
 // Plan DB persistence.

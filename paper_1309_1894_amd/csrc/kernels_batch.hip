@@ -53,19 +53,6 @@ __device__ __forceinline__ void run_wave_tile(const BatchArgs<T> &a, int tile, d
     }
 }
 
-// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
-// XCD b % 8), and each XCD has its own L2.  Workgroups are dealt tile
-// groups so that XCD k works through one contiguous eighth of the tile
-// list: neighbouring tiles of an instance (which share x entries near their
-// boundary) meet in one L2.
-constexpr int kXcds = 8;
-
-__device__ __forceinline__ int xcd_first(int xcd, int n)
-{
-    const int per = n / kXcds, rem = n % kXcds;
-    return xcd * per + min(xcd, rem);
-}
-
 template <typename T, int BS, int TILE>
 __global__ __launch_bounds__(BS) void k_batch_grid(BatchArgs<T> a)
 {
@@ -75,7 +62,7 @@ __global__ __launch_bounds__(BS) void k_batch_grid(BatchArgs<T> a)
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int ngroups = (a.ntiles + WT::NW - 1) / WT::NW;
     const int b = (int)blockIdx.x;
-    const int tile = (xcd_first(b % kXcds, ngroups) + b / kXcds) * WT::NW + wv;
+    const int tile = xcd_remap(b, ngroups) * WT::NW + wv;   // XCD-contiguous tile groups
     if (tile < a.ntiles)
         run_wave_tile<T, BS, TILE>(a, tile, sp + wv * WT::ENTRIES, srp + wv * (kWaveTileRows + 1));
 }

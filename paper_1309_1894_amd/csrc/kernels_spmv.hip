@@ -10,10 +10,11 @@
 //   SELL     sliced ELL: slices of C rows stored column-major, one lane per
 //            row, fully coalesced, no reduction; rows keep their own length
 //            so padding is never read.
-//   ADAPTIVE precomputed row blocks: runs of short rows whose entries fit an
-//            LDS tile are streamed into LDS with coalesced loads and summed
-//            per row from LDS; rows of medium length get one wavefront,
-//            very long rows one whole workgroup.
+//   ADAPTIVE precomputed wavefront tiles: runs of short rows whose entries
+//            fit a wavefront's LDS slice are streamed into LDS with
+//            coalesced loads and summed per row from LDS; runs of medium
+//            rows, and single long rows, get a wavefront (64 lanes per row,
+//            eight loads and gathers in flight per lane).
 // Products are formed and accumulated in FP64 (FP32 operands are widened
 // first, so their products are exact) and each output is rounded once.
 #include "device_common.h"
@@ -126,24 +127,31 @@ __global__ __launch_bounds__(BS) void k_spmv_sell(SpmvArgs<T> a)
 
 // ------------------------------------------------------------- ADAPTIVE --
 
-template <typename T, int BS, int TILE, bool FUSED>
+// Row blocks are wavefront tiles (precomputed at registration for a
+// wavefront capacity of E entries): each wavefront of a workgroup runs its
+// own block with a private LDS slice, without workgroup barriers.
+template <typename T, int BS, int E, bool FUSED>
 __global__ __launch_bounds__(BS) void k_spmv_adaptive(SpmvArgs<T> a)
 {
-    __shared__ double sp[TILE];
-    __shared__ int srp[kStreamRowsPerThread * BS + 1];
-    __shared__ double red[BS / kWave];
-    const int b = a.blk0 + (int)blockIdx.x;
+    constexpr int NW = BS / kWave;
+    __shared__ double sp[NW * E];
+    __shared__ int srp[NW * (kWaveTileRows + 1)];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int ngroups = (a.nblk + NW - 1) / NW;
+    const int g = xcd_remap((int)blockIdx.x, ngroups);
+    const int bl = g * NW + wv;
+    if (bl >= a.nblk) return;
+    const int b = a.blk0 + bl;
     const uint32_t e0 = a.blocks[b], e1 = a.blocks[b + 1];
     const int r0 = (int)(e0 & kBlkRowMask), r1 = (int)(e1 & kBlkRowMask);
     const uint32_t mode = e0 >> 30;
     T *w = FUSED ? a.w : nullptr;
     if (mode == kBlkStream) {
-        stream_rows<T, BS, TILE>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, r1, a.block_k[b], a.block_k[b + 1],
-                                 sp, srp);
-    } else if (mode == kBlkWave) {
-        group_rows<T, BS, kWave>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, r1);
+        wave_stream<T, E / kWave>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, r1, a.block_k[b], a.block_k[b + 1],
+                                  sp + wv * E, srp + wv * (kWaveTileRows + 1));
     } else {
-        block_row<T, BS>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, red);
+        // medium rows (kBlkWave) and single long rows (kBlkLong)
+        wave_rows_mlp<T, 8>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, r1);
     }
 }
 
@@ -172,10 +180,10 @@ hipError_t L_sell(const void *p, dim3 g, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int BS, int TILE, bool F>
+template <typename T, int BS, int E, bool F>
 hipError_t L_adaptive(const void *p, dim3 g, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_spmv_adaptive<T, BS, TILE, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
+    hipLaunchKernelGGL((k_spmv_adaptive<T, BS, E, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
     return hipGetLastError();
 }
 
@@ -187,7 +195,8 @@ hipError_t L_adaptive(const void *p, dim3 g, hipStream_t s)
 #define VECTOR(BS, G, U) {2, BS, G, U, 0, FN4(L_vector, BS, G, U, false)}
 #define VECTOR_LDS(BS, G) {2, BS, G, 1, 1, FN4(L_vector, BS, G, 1, true)}
 #define SELL(C, U) {3, 256, C, U, 0, FN4(L_sell, 256, C, U)}
-#define ADAPT(BS, TILE) {4, BS, 1, 1, TILE, FN4(L_adaptive, BS, TILE)}
+// lds = row-stream entries per wavefront tile
+#define ADAPT(BS, E) {4, BS, 1, 1, E, FN4(L_adaptive, BS, E)}
 
 #define VECTOR_U(BS, G) VECTOR(BS, G, 1), VECTOR(BS, G, 2), VECTOR(BS, G, 4)
 #define VECTOR_G(BS) VECTOR_U(BS, 2), VECTOR_U(BS, 4), VECTOR_U(BS, 8), VECTOR_U(BS, 16), \
@@ -208,9 +217,9 @@ const SpmvEntry kSpmv[] = {
     SELL(64, 1), SELL(64, 2), SELL(64, 4),
     SELL(128, 1), SELL(128, 2), SELL(128, 4),
     SELL(256, 1), SELL(256, 2), SELL(256, 4),
-    ADAPT(128, 512), ADAPT(128, 1024), ADAPT(128, 2048), ADAPT(128, 4096),
-    ADAPT(256, 512), ADAPT(256, 1024), ADAPT(256, 2048), ADAPT(256, 4096),
-    ADAPT(512, 512), ADAPT(512, 1024), ADAPT(512, 2048), ADAPT(512, 4096),
+    ADAPT(128, 256), ADAPT(128, 512), ADAPT(128, 1024),
+    ADAPT(256, 256), ADAPT(256, 512), ADAPT(256, 1024),
+    ADAPT(512, 256), ADAPT(512, 512), ADAPT(512, 1024),
 };
 
 }  // namespace
