@@ -322,8 +322,9 @@ def serving(spk, I, nreq):
     """Open-loop Poisson serving of SpMV+WAXPY requests over a pool of banded
     and Zipf matrices (1e3..1e5 rows here, 70% FP64 / 30% FP32): continuous
     batching vs a FIFO server that runs one request at a time with the plain
-    unbatched kernels, both at the same offered load (70% of the FIFO
-    server's closed-loop saturation rate)."""
+    unbatched kernels, both on the same arrival traces at two offered loads
+    (70% of the FIFO server's and 70% of the batching server's closed-loop
+    saturation rate)."""
     import numpy as np
     npool = 48
     sizes = I.log_uniform_int(1e3, 1e5, 51, 0, npool)
@@ -351,31 +352,39 @@ def serving(spk, I, nreq):
         return srv, ids
 
     res = {"requests": nreq, "pool": npool}
-    srv, ids = make(1)
-    k = min(nreq, 400)
-    t0 = time.perf_counter()
-    for i in range(k):
-        srv.submit(ids[mats[i]], xs[i], np.empty(pool[mats[i]].nrows, pool[mats[i]].val.dtype))
-    srv.drain()
-    sat = k / (time.perf_counter() - t0)
-    srv.close()
-    rate = 0.7 * sat
-    res["fifo_saturation_per_s"] = round(sat, 1)
-    res["offered_rate_per_s"] = round(rate, 1)
-    arr = I.poisson_arrivals(nreq, rate, seed=51)
-    for mode, label in ((1, "fifo_plain"), (0, "continuous_batching")):
+
+    def saturation(mode):
         srv, ids = make(mode)
-        ys = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
-        ws = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
-        srv.replay(arr, [ids[m] for m in mats], xs, ys, ws)
-        st = srv.stats()
-        lat = srv.latencies()[npool:]
-        res[label] = {"p50_us": round(float(np.percentile(lat, 50)), 1),
-                      "p99_us": round(float(np.percentile(lat, 99)), 1),
-                      "mean_us": round(float(lat.mean()), 1), "launches": st["batches"],
-                      "gbs": round(st["bytes_moved"] / max(st["wall_s"], 1e-9) / 1e9, 2)}
-        log(f"serving {label}: {res[label]}")
+        k = min(nreq, 600)
+        t0 = time.perf_counter()
+        for i in range(k):
+            srv.submit(ids[mats[i]], xs[i], np.empty(pool[mats[i]].nrows, pool[mats[i]].val.dtype))
+        srv.drain()
+        rate = k / (time.perf_counter() - t0)
         srv.close()
+        return rate
+
+    sat = {1: saturation(1), 0: saturation(0)}
+    res["closed_loop_saturation_per_s"] = {"fifo_plain": round(sat[1], 1), "continuous_batching": round(sat[0], 1)}
+    # two offered loads: 70% of what each server sustains closed-loop
+    for load_name, rate in (("load_0.7x_fifo_saturation", 0.7 * sat[1]),
+                            ("load_0.7x_batching_saturation", 0.7 * sat[0])):
+        arr = I.poisson_arrivals(nreq, rate, seed=51)
+        point = {"offered_rate_per_s": round(rate, 1)}
+        for mode, label in ((1, "fifo_plain"), (0, "continuous_batching")):
+            srv, ids = make(mode)
+            ys = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
+            ws = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
+            srv.replay(arr, [ids[m] for m in mats], xs, ys, ws)
+            st = srv.stats()
+            lat = srv.latencies()[npool:]
+            point[label] = {"p50_us": round(float(np.percentile(lat, 50)), 1),
+                            "p99_us": round(float(np.percentile(lat, 99)), 1),
+                            "mean_us": round(float(lat.mean()), 1), "launches": st["batches"],
+                            "gbs": round(st["bytes_moved"] / max(st["wall_s"], 1e-9) / 1e9, 2)}
+            log(f"serving {load_name} {label}: {point[label]}")
+            srv.close()
+        res[load_name] = point
     return res
 
 

@@ -149,7 +149,10 @@ spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchTile *d_tiles
     if (dtype == SPK_F64) fill(a.d); else fill(a.f);
     const int64_t nw = e->block / 64;
     int64_t g = (ntiles + nw - 1) / nw;   // tile groups, one per workgroup
-    if (kind == kBatchPersistent) g = std::min<int64_t>(persistent_grid, g);
+    // persistent: every XCD queue that holds tiles needs a workgroup of its
+    // own (workgroup b serves queue b % 8), so at least min(8, ntiles)
+    if (kind == kBatchPersistent)
+        g = std::min<int64_t>(persistent_grid, std::max<int64_t>(g, std::min<int64_t>(8, ntiles)));
     SPK_HIP(e->fn[dtype][kind](dtype == SPK_F64 ? (const void *)&a.d : (const void *)&a.f, dim3((unsigned)g), s));
     return SPK_OK;
 }
@@ -214,9 +217,18 @@ spk_status launch(spk_batch b, int64_t ntiles, double alpha, const void *x, void
 
 spk_status occupancy(spk_batch b)
 {
-    int64_t per_cu = b->entry->occupancy[b->dtype]();
-    if (b->opts.waves_per_cu > 0) per_cu = std::max<int64_t>(1, b->opts.waves_per_cu / (b->entry->block / 64));
-    b->grid_persistent = per_cu * b->h->num_cu;
+    // resident workgroups per CU: the runtime's occupancy figure, raised to
+    // what the kernel's static LDS (products + row offsets per wavefront)
+    // and the 32 wavefront slots of a CU allow.  The persistent kernel never
+    // waits on another workgroup, so a workgroup that does not fit at once
+    // simply starts later.
+    const int nw = b->entry->block / 64;
+    const int64_t lds = (int64_t)b->entry->tile * 8 + (int64_t)nw * (2 * 64 + 1) * 4;
+    const int64_t by_lds = (160 * 1024) / std::max<int64_t>(1, lds);
+    const int64_t by_waves = 32 / nw;
+    int64_t per_cu = std::max<int64_t>(b->entry->occupancy[b->dtype](), std::min(by_lds, by_waves));
+    if (b->opts.waves_per_cu > 0) per_cu = std::max<int64_t>(1, b->opts.waves_per_cu / nw);
+    b->grid_persistent = std::max<int64_t>(1, per_cu) * b->h->num_cu;
     return SPK_OK;
 }
 

@@ -67,11 +67,11 @@ __global__ __launch_bounds__(BS) void k_batch_grid(BatchArgs<T> a)
         run_wave_tile<T, BS, TILE>(a, tile, sp + wv * WT::ENTRIES, srp + wv * (kWaveTileRows + 1));
 }
 
-// Persistent form: a grid sized to fill the GPU; the workgroups of XCD k
-// claim chunks of kChunk tile groups from XCD k's own eighth of the list
-// (one queue head per XCD, each in its own 256-byte line), and each
-// wavefront takes its tile of every claimed group.
-constexpr int kChunk = 2;
+// Persistent form: a grid sized to fill the GPU whose wavefronts pull tiles
+// themselves: a wavefront on XCD k claims chunks of kChunk tiles from XCD
+// k's own eighth of the tile list (one queue head per XCD, each in its own
+// 256-byte line) and streams them; no workgroup barrier anywhere.
+constexpr int kChunk = 4;
 constexpr int kCtrStride = 64;   // uint32 per counter line
 
 template <typename T, int BS, int TILE>
@@ -80,33 +80,31 @@ __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs<T> a)
     using WT = WaveTiles<T, BS, TILE>;
     __shared__ double sp[TILE];
     __shared__ int srp[WT::NW * (kWaveTileRows + 1)];
-    __shared__ int s_claim;
-    const int t = threadIdx.x;
-    const int wv = __builtin_amdgcn_readfirstlane(t / kWave);
-    const int ngroups = (a.ntiles + WT::NW - 1) / WT::NW;
+    const int l = threadIdx.x & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int xcd = (int)blockIdx.x % kXcds;
-    const int lo = xcd_first(xcd, ngroups);
-    const int hi = xcd_first(xcd + 1, ngroups);
+    const int lo = xcd_first(xcd, a.ntiles);
+    const int hi = xcd_first(xcd + 1, a.ntiles);
     uint32_t *head = a.next + xcd * kCtrStride;
+    double *my_sp = sp + wv * WT::ENTRIES;
+    int *my_srp = srp + wv * (kWaveTileRows + 1);
+    // the next claim is issued before the current chunk is streamed, so the
+    // atomic's round trip overlaps the chunk's loads
+    int claim = 0;
+    if (l == 0) claim = (int)atomicAdd(head, (uint32_t)kChunk);
     for (;;) {
-        if (t == 0) s_claim = lo + (int)atomicAdd(head, (uint32_t)kChunk);
-        __syncthreads();
-        const int c0 = s_claim;
-        __syncthreads();
+        const int c0 = lo + __builtin_amdgcn_readlane(claim, 0);
         if (c0 >= hi) break;
+        if (l == 0) claim = (int)atomicAdd(head, (uint32_t)kChunk);
         const int c1 = min(c0 + kChunk, hi);
-        for (int g = c0; g < c1; ++g) {
-            const int tile = g * WT::NW + wv;
-            if (tile < a.ntiles)
-                run_wave_tile<T, BS, TILE>(a, tile, sp + wv * WT::ENTRIES, srp + wv * (kWaveTileRows + 1));
-        }
+        for (int tile = c0; tile < c1; ++tile) run_wave_tile<T, BS, TILE>(a, tile, my_sp, my_srp);
     }
-    // Every workgroup has drawn past the end of its queue before it counts
+    // Every wavefront has drawn past the end of its queue before it counts
     // itself done, so the last one may reset all counters.
-    if (t == 0) {
+    if (l == 0) {
         __threadfence();
         const uint32_t d = atomicAdd(a.done, 1u);
-        if (d == gridDim.x - 1u) {
+        if (d == gridDim.x * (uint32_t)WT::NW - 1u) {
             for (int k = 0; k < kXcds; ++k) atomicExch(a.next + k * kCtrStride, 0u);
             atomicExch(a.done, 0u);
         }
