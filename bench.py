@@ -136,7 +136,7 @@ def main():
                       "tiles": info["tiles"], "classes": info["classes"]}
 
     # STREAM copy: measured bandwidth ceiling (and counter calibration)
-    out["stream_copy_gbs"] = stream_copy(spk, torch, dev, stream)
+    out["stream"] = stream_copy(spk, torch, dev, stream)
 
     if not args.no_extras:
         del d_y, d_w
@@ -235,22 +235,26 @@ def plain_batch(spk, B, d_x, d_y, d_w, alpha, stream, torch):
 
 
 def stream_copy(spk, torch, dev, stream):
+    """STREAM copy (c = a) and triad (c = a + 3b) on 2^28 doubles per array."""
     n = 1 << 28  # 2 GiB per array
     a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.ones(n, dtype=torch.float64, device=dev)
     c = torch.empty_like(a)
-    for _ in range(3):
-        spk.spk_stream_probe(0, a, a, c)
-    torch.cuda.synchronize()
-    reps = 20
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        spk.spk_stream_probe(0, a, a, c)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del a, c
-    return round(2 * 8 * n / (ms * 1e-3) / 1e9, 1)
+    out = {}
+    for kind, name, nbytes in ((0, "copy_gbs", 2 * 8 * n), (1, "triad_gbs", 3 * 8 * n)):
+        for _ in range(3):
+            spk.spk_stream_probe(kind, a, b, c)
+        torch.cuda.synchronize()
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            spk.spk_stream_probe(kind, a, b, c)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = round(nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9, 1)
+    del a, b, c
+    return out
 
 
 def vector_sweep(spk, torch, I, dev):

@@ -7,7 +7,6 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
-#include <sstream>
 
 #include "device_common.h"
 #include "internal.h"
@@ -51,8 +50,6 @@ int64_t spmv_bytes(int64_t m, int64_t n, int64_t nnz, int dtype, bool fused)
 }
 
 // ------------------------------------------------------------ variants --
-
-static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 const VecEntry *find_vec_entry(int op, int dtype, const spk_variant &v)
 {

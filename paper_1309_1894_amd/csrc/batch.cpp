@@ -411,11 +411,7 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
     SPK_TRY(launch(b, (int64_t)b->tiles.size(), alpha, x, y, w, s));
     SPK_HIP(launch_widen(b->dtype, nvec, y, ref_y, s));
     if (w) SPK_HIP(launch_widen(b->dtype, nvec, w, ref_w, s));
-    for (int64_t i = 0; i < b->count; ++i) {
-        const char *xv = (const char *)x + vs * b->vec_off[i];
-        SPK_HIP(launch_row_absum(b->dtype, (int32_t)b->m[i], b->rp + b->rp_off[i], b->ci + b->nz_off[i],
-                                 (const char *)b->val + vs * b->nz_off[i], xv, scale + b->vec_off[i], s));
-    }
+    SPK_HIP(launch_tiles_absum(b->dtype, b->d_tiles, (int64_t)b->tiles.size(), x, scale, s));
     if (w) {
         std::vector<double> sc((size_t)nvec), wr((size_t)nvec);
         SPK_HIP(hipMemcpyAsync(sc.data(), scale, 8 * nvec, hipMemcpyDeviceToHost, s));

@@ -50,7 +50,8 @@ __device__ __forceinline__ void wave_products(const int32_t *ci, const T *val, c
 // One wavefront streams a run of short rows [r0, r1) with entries [k0, k1)
 // (k1 - k0 <= 64*ITEMS, r1 - r0 <= 128) through its private LDS slice:
 // all value/column/row-offset/own-x loads at once, then the x gather,
-// products to LDS, one lane per row sums from LDS.  No workgroup barrier:
+// products to LDS, one lane per row sums from LDS (four interleaved
+// partial sums).  No workgroup barrier:
 // every wavefront of a CU is an independent stream.
 template <typename T, int ITEMS>
 __device__ __forceinline__ void wave_stream(const int32_t *rp, const int32_t *ci, const T *val, const T *x, T *y,
@@ -74,15 +75,20 @@ __device__ __forceinline__ void wave_stream(const int32_t *rp, const int32_t *ci
     for (int q = 0; q < 2; ++q) {
         const int i = l + q * kWave;
         if (i < nr) {
+            // four interleaved partial sums: four LDS reads in flight
             const int s = srp[i], e = srp[i + 1];
-            double a0 = 0.0, a1 = 0.0;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
             int k = s;
-            for (; k + 1 < e; k += 2) {
+            for (; k + 3 < e; k += 4) {
                 a0 += sp[k];
                 a1 += sp[k + 1];
+                a2 += sp[k + 2];
+                a3 += sp[k + 3];
             }
             if (k < e) a0 += sp[k];
-            const T yt = (T)(a0 + a1);
+            if (k + 1 < e) a1 += sp[k + 1];
+            if (k + 2 < e) a2 += sp[k + 2];
+            const T yt = (T)((a0 + a1) + (a2 + a3));
             __builtin_nontemporal_store(yt, y + r0 + i);
             if (w) __builtin_nontemporal_store(fma_t(alpha, yt, xo[q]), w + r0 + i);
         }

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "batch_types.h"
+
 namespace spk {
 
 // ----------------------------------------------------------- vector kernels
@@ -84,6 +86,10 @@ hipError_t launch_widen(int dtype, int64_t n, const void *in, double *out, hipSt
 // scale_i = sum_k |a_ik * x_k| over rows [0, m)
 hipError_t launch_row_absum(int dtype, int32_t m, const int32_t *rp, const int32_t *ci,
                             const void *val, const void *x, double *scale, hipStream_t s);
+
+// scale[vec_off + r] = sum_k |a_rk * x_k| for every row of every tile
+hipError_t launch_tiles_absum(int dtype, const BatchTile *tiles, int64_t ntiles, const void *x, double *scale,
+                              hipStream_t s);
 
 // scale_i = |x_i * y_i| summed into one double (dot tolerance scale)
 hipError_t launch_dot_absum(int dtype, int64_t n, const void *x, const void *y, double *out,

@@ -79,6 +79,21 @@ __global__ __launch_bounds__(kBS) void k_row_absum(int32_t m, const int32_t *rp,
     scale[r] = s;
 }
 
+// Tolerance scales of a batched launch: one workgroup per tile, one lane per
+// row of the tile.
+template <typename T>
+__global__ __launch_bounds__(kBS) void k_tiles_absum(const BatchTile *tiles, const T *x, double *scale)
+{
+    const BatchTile td = tiles[blockIdx.x];
+    const T *val = (const T *)td.val;
+    const T *xi = x + td.vec_off;
+    for (int r = td.r0 + (int)threadIdx.x; r < td.r1; r += kBS) {
+        double s = 0.0;
+        for (int k = td.rp[r]; k < td.rp[r + 1]; ++k) s += __builtin_fabs((double)val[k] * (double)xi[td.ci[k]]);
+        scale[td.vec_off + r] = s;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBS) void k_dot_absum(int64_t n, const T *x, const T *y, double *out)
 {
@@ -97,22 +112,24 @@ __global__ __launch_bounds__(kBS) void k_fill(uint4 *p, int64_t n16, uint32_t pa
         p[i] = v;
 }
 
-// STREAM copy: 16-byte accesses, four in flight per lane, one pass.
+// STREAM copy and triad: 16-byte accesses, four in flight per lane, one
+// pass, non-temporal (every element is touched once).
 constexpr int kCopyUnroll = 4;
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
 
 __global__ __launch_bounds__(kBS) void k_copy(int64_t n2, const double2 *a, double2 *b)
 {
     const int64_t base = (int64_t)blockIdx.x * kBS * kCopyUnroll + threadIdx.x;
-    double2 v[kCopyUnroll];
+    f64x2_t v[kCopyUnroll];
 #pragma unroll
     for (int u = 0; u < kCopyUnroll; ++u) {
         const int64_t i = base + (int64_t)u * kBS;
-        if (i < n2) v[u] = a[i];
+        if (i < n2) v[u] = __builtin_nontemporal_load(reinterpret_cast<const f64x2_t *>(a) + i);
     }
 #pragma unroll
     for (int u = 0; u < kCopyUnroll; ++u) {
         const int64_t i = base + (int64_t)u * kBS;
-        if (i < n2) b[i] = v[u];
+        if (i < n2) __builtin_nontemporal_store(v[u], reinterpret_cast<f64x2_t *>(b) + i);
     }
 }
 
@@ -125,9 +142,23 @@ __global__ __launch_bounds__(kBS) void k_copy_tail(int64_t lo, int64_t n, const 
 __global__ __launch_bounds__(kBS) void k_triad(int64_t n2, const double2 *a, const double2 *b, double s,
                                               double2 *c)
 {
-    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n2; i += (int64_t)gridDim.x * kBS) {
-        const double2 u = a[i], v = b[i];
-        c[i] = make_double2(__builtin_fma(s, v.x, u.x), __builtin_fma(s, v.y, u.y));
+    const int64_t base = (int64_t)blockIdx.x * kBS * kCopyUnroll + threadIdx.x;
+    f64x2_t u[kCopyUnroll], v[kCopyUnroll];
+#pragma unroll
+    for (int q = 0; q < kCopyUnroll; ++q) {
+        const int64_t i = base + (int64_t)q * kBS;
+        if (i < n2) {
+            u[q] = __builtin_nontemporal_load(reinterpret_cast<const f64x2_t *>(a) + i);
+            v[q] = __builtin_nontemporal_load(reinterpret_cast<const f64x2_t *>(b) + i);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kCopyUnroll; ++q) {
+        const int64_t i = base + (int64_t)q * kBS;
+        if (i < n2) {
+            const f64x2_t r = {__builtin_fma(s, v[q].x, u[q].x), __builtin_fma(s, v[q].y, u[q].y)};
+            __builtin_nontemporal_store(r, reinterpret_cast<f64x2_t *>(c) + i);
+        }
     }
 }
 
@@ -208,6 +239,19 @@ hipError_t launch_row_absum(int dtype, int32_t m, const int32_t *rp, const int32
     return hipGetLastError();
 }
 
+hipError_t launch_tiles_absum(int dtype, const BatchTile *tiles, int64_t ntiles, const void *x, double *scale,
+                              hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    if (dtype == 1)
+        hipLaunchKernelGGL(k_tiles_absum<double>, dim3((unsigned)ntiles), dim3(kBS), 0, s, tiles, (const double *)x,
+                           scale);
+    else
+        hipLaunchKernelGGL(k_tiles_absum<float>, dim3((unsigned)ntiles), dim3(kBS), 0, s, tiles, (const float *)x,
+                           scale);
+    return hipGetLastError();
+}
+
 hipError_t launch_dot_absum(int dtype, int64_t n, const void *x, const void *y, double *out, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
@@ -246,7 +290,8 @@ hipError_t launch_triad(int64_t n, const double *a, const double *b, double s_, 
 {
     const int64_t n2 = n / 2;
     if (n2 > 0) {
-        hipLaunchKernelGGL(k_triad, dim3(grid_for(n2, 8)), dim3(kBS), 0, s, n2, (const double2 *)a,
+        const int64_t per = (int64_t)kBS * kCopyUnroll;
+        hipLaunchKernelGGL(k_triad, dim3((unsigned)((n2 + per - 1) / per)), dim3(kBS), 0, s, n2, (const double2 *)a,
                            (const double2 *)b, s_, (double2 *)c);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -12,6 +12,55 @@
 
 namespace spk {
 
+// Streams are touched once: loads and stores carry the non-temporal hint.
+template <typename T, int VEC>
+struct ntvec;
+template <typename T>
+struct ntvec<T, 1> {
+    typedef T type;
+};
+template <>
+struct ntvec<double, 2> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct ntvec<float, 2> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct ntvec<float, 4> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+
+template <typename T, int VEC>
+__device__ __forceinline__ vec_t<T, VEC> nt_load(const T *p)
+{
+    using N = typename ntvec<T, VEC>::type;
+    const N v = __builtin_nontemporal_load(reinterpret_cast<const N *>(p));
+    vec_t<T, VEC> r;
+    if constexpr (VEC == 1) {
+        r.v[0] = v;
+    } else {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) r.v[j] = v[j];
+    }
+    return r;
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void nt_store(T *p, const vec_t<T, VEC> &r)
+{
+    using N = typename ntvec<T, VEC>::type;
+    N v;
+    if constexpr (VEC == 1) {
+        v = r.v[0];
+    } else {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) v[j] = r.v[j];
+    }
+    __builtin_nontemporal_store(v, reinterpret_cast<N *>(p));
+}
+
 // w_i = alpha*x_i + y_i.  w may be x or y (each element is read before it
 // is written by the same lane, and no lane touches another's elements).
 template <typename T, int BS, int VEC, int UNR>
@@ -27,8 +76,8 @@ __global__ __launch_bounds__(BS) void k_waxpy(int64_t n, T alpha, const T *x, co
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 const int64_t i = base + ((int64_t)u * BS + t) * VEC;
-                xv[u] = *reinterpret_cast<const V *>(x + i);
-                yv[u] = *reinterpret_cast<const V *>(y + i);
+                xv[u] = nt_load<T, VEC>(x + i);
+                yv[u] = nt_load<T, VEC>(y + i);
             }
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
@@ -36,7 +85,7 @@ __global__ __launch_bounds__(BS) void k_waxpy(int64_t n, T alpha, const T *x, co
                 V r;
 #pragma unroll
                 for (int j = 0; j < VEC; ++j) r.v[j] = fma_t(alpha, xv[u].v[j], yv[u].v[j]);
-                *reinterpret_cast<V *>(w + i) = r;
+                nt_store<T, VEC>(w + i, r);
             }
         } else {
 #pragma unroll
@@ -75,8 +124,8 @@ __global__ __launch_bounds__(BS) void k_dot(int64_t n, const T *x, const T *y, d
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 const int64_t i = base + ((int64_t)u * BS + t) * VEC;
-                xv[u] = *reinterpret_cast<const V *>(x + i);
-                yv[u] = *reinterpret_cast<const V *>(y + i);
+                xv[u] = nt_load<T, VEC>(x + i);
+                yv[u] = nt_load<T, VEC>(y + i);
             }
 #pragma unroll
             for (int u = 0; u < UNR; ++u)

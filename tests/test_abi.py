@@ -99,3 +99,13 @@ def test_create_without_a_gpu_fails_cleanly(lib):
     h = ctypes.c_void_p()
     s = spk.lib.spk_create(0, None, ctypes.byref(h))
     assert s != 0 and h.value is None
+
+
+def test_header_is_plain_c99(tmp_path):
+    """The boundary header compiles as C99 on its own (no C++ or HIP types)."""
+    import subprocess
+    src = tmp_path / "use.c"
+    src.write_text('#include "spk.h"\nint main(void) { spk_variant v = {0}; (void)v; return spk_abi_version() < 0; }\n')
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-pedantic", "-fsyntax-only",
+                        "-I", os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
