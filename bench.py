@@ -95,7 +95,7 @@ def main():
 
     # tuning (Section 2's search, per shape class), not timed
     t0 = time.time()
-    rep = batch.tune(alpha, d_x, d_y, d_w, reps=5, warmup=1, verbose=args.verbose)
+    rep = batch.tune(alpha, d_x, d_y, d_w, reps=10, warmup=2, verbose=args.verbose)
     info = batch.info()
     log(f"batch tune: {rep.tried} candidates timed, {rep.rejected} rejected, {info['classes']} classes, "
         f"{info['tiles']} tiles ({time.time() - t0:.1f}s)")
