@@ -258,28 +258,35 @@ def stream_copy(spk, torch, dev, stream):
 
 
 def vector_sweep(spk, torch, I, dev):
-    """WAXPY/AXPY/dot at n = 2^27, FP64 and FP32: tuned vs plain (HBM-sized)."""
+    """WAXPY/AXPY/dot, FP64 and FP32, n in {1e4, 1e5, 1e6, 1e7, 2^27}:
+    tuned vs plain.  Up to 1e7 every timed rep starts with a flushed
+    last-level cache (those sizes fit in it); 2^27 is HBM-sized anyway."""
+    import numpy as np
     res = {}
-    n = 1 << 27
-    for dt, tdt, ndt in ((1, torch.float64, "f64"), (0, torch.float32, "f32")):
-        npdt = __import__("numpy").float64 if dt == 1 else __import__("numpy").float32
-        x = torch.from_numpy(I.uniform(21, 0, n, npdt)).to(dev)
-        y = torch.from_numpy(I.uniform(22, 0, n, npdt)).to(dev)
-        w = torch.empty_like(x)
-        d = torch.empty(1, dtype=torch.float64, device=dev)
-        s = x.element_size()
-        for op, nm, nbytes in ((spk.SPK_OP_WAXPY, "waxpy", 3 * n * s), (spk.SPK_OP_AXPY, "axpy", 3 * n * s),
-                               (spk.SPK_OP_DOT, "dot", 2 * n * s)):
-            p = spk.problem(op, x=x, y=y, w=w if op == spk.SPK_OP_WAXPY else None,
-                            d_result=d if op == spk.SPK_OP_DOT else None, alpha=1.5)
-            rep = spk.spk_tune(p, reps=5, warmup=1, record=True)
-            res[f"{nm}_{ndt}"] = {"tuned_gbs": round(nbytes / (rep.best_us * 1e-6) / 1e9, 1),
-                                  "plain_gbs": round(nbytes / (rep.plain_us * 1e-6) / 1e9, 1),
-                                  "tuned_us": round(rep.best_us, 2), "plain_us": round(rep.plain_us, 2),
-                                  "best": rep.best.as_dict(), "variants_timed": rep.tried,
-                                  "rejected": rep.rejected}
-            log(f"sweep {nm} {ndt}: {res[f'{nm}_{ndt}']}")
-        del x, y, w
+    for n in (10 ** 4, 10 ** 5, 10 ** 6, 10 ** 7, 1 << 27):
+        key = "2^27" if n == 1 << 27 else f"1e{int(round(np.log10(n)))}"
+        for dt, ndt in ((1, "f64"), (0, "f32")):
+            npdt = np.float64 if dt == 1 else np.float32
+            x = torch.from_numpy(I.uniform(21, 0, n, npdt)).to(dev)
+            y = torch.from_numpy(I.uniform(22, 0, n, npdt)).to(dev)
+            w = torch.empty_like(x)
+            d = torch.empty(1, dtype=torch.float64, device=dev)
+            s = x.element_size()
+            for op, nm, nbytes in ((spk.SPK_OP_WAXPY, "waxpy", 3 * n * s), (spk.SPK_OP_AXPY, "axpy", 3 * n * s),
+                                   (spk.SPK_OP_DOT, "dot", 2 * n * s)):
+                p = spk.problem(op, x=x, y=y, w=w if op == spk.SPK_OP_WAXPY else None,
+                                d_result=d if op == spk.SPK_OP_DOT else None, alpha=1.5)
+                rep = spk.spk_tune(p, reps=5, warmup=1, flush=n <= 10 ** 7, record=True)
+                res[f"{nm}_{ndt}_n{key}"] = {
+                    "tuned_gbs": round(nbytes / (rep.best_us * 1e-6) / 1e9, 1),
+                    "plain_gbs": round(nbytes / (rep.plain_us * 1e-6) / 1e9, 1),
+                    "tuned_us": round(rep.best_us, 2), "plain_us": round(rep.plain_us, 2),
+                    "best": [rep.best.block, rep.best.vec, rep.best.unroll, rep.best.grid],
+                    "variants_timed": rep.tried, "rejected": rep.rejected}
+                if n == 1 << 27:
+                    log(f"sweep {nm} {ndt} n={key}: {res[f'{nm}_{ndt}_n{key}']}")
+            del x, y, w
+    res["best_fields"] = "block, vec, unroll, grid (0 = one pass, else workgroups per CU)"
     torch.cuda.empty_cache()
     return res
 
@@ -303,9 +310,49 @@ def spmv_large(spk, torch, I, dev):
                      "tuned_us": round(rep.best_us, 2), "plain_us": round(rep.plain_us, 2),
                      "best": rep.best.as_dict(), "variants_timed": rep.tried, "pruned": rep.pruned,
                      "rejected": rep.rejected, "bytes": nbytes}
+        res[name]["best_us_per_format"] = per_format(spk, torch, M, xd, y)
         log(f"spmv {name}: {res[name]}")
         M.release()
     return res
+
+
+def per_format(spk, torch, M, xd, y, reps=5):
+    """Best cold-cache time (us) of every compiled variant, per storage
+    format (the tuner's search, reported format by format)."""
+    names = {spk.SPK_FMT_SCALAR: "csr_scalar", spk.SPK_FMT_VECTOR: "csr_vector", spk.SPK_FMT_SELL: "sliced_ell",
+             spk.SPK_FMT_ADAPTIVE: "csr_lds_tiles"}
+    stream = torch.cuda.current_stream()
+    best = {}
+    p = spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y)
+    for v in spk.variants(spk.SPK_OP_SPMV, M.dtype_code):
+        # the tuner's byte model: sliced ELL only when padding at most doubles the entries
+        if v.format == spk.SPK_FMT_SELL and M.nnz and sell_padding(M, v.group) > 2.0:
+            continue
+        spk.spk_run(p, v)
+        ev = []
+        for _ in range(reps):
+            spk.spk_flush_cache()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            spk.spk_run(p, v)
+            b.record(stream)
+            ev.append((a, b))
+        torch.cuda.synchronize()
+        t = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)[reps // 2]
+        k = names[v.format]
+        if k not in best or t < best[k]:
+            best[k] = round(t, 2)
+    return best
+
+
+def sell_padding(M, C):
+    """Stored entries of sliced ELL with slices of C rows, over nnz."""
+    import numpy as np
+    lens = np.diff(M.row_ptr_host.astype(np.int64))
+    pad = len(lens) % C
+    if pad:
+        lens = np.concatenate([lens, np.zeros(C - pad, np.int64)])
+    return float(lens.reshape(-1, C).max(axis=1).sum() * C) / max(1, M.nnz)
 
 
 def lap2d_step(spk, torch, I, dev):

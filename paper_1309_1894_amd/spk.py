@@ -308,6 +308,7 @@ class Matrix:
         self.nrows, self.ncols, self.nnz = int(csr.nrows), int(csr.ncols), int(ci.size)
         self.dtype_code = SPK_F64 if val.dtype == np.float64 else SPK_F32
         self.np_dtype = val.dtype
+        self.row_ptr_host = rp
         A = _csr_struct(self.nrows, self.ncols, self.nnz, self.dtype_code, rp.ctypes.data,
                         ci.ctypes.data if ci.size else None, val.ctypes.data if val.size else None)
         m = _P()
