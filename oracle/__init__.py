@@ -66,6 +66,7 @@ def lib():
             "orc_max_ulp_f64": (_I64, [_I64, _P, _P, _P]),
             "orc_max_ulp_f32": (_I64, [_I64, _P, _P, _P]),
             "orc_check_rows": (_I64, [_I64, _P, _P, _P, _D, _P, _P]),
+            "orc_cg_f64": (None, [_I64, _P, _P, _P, _P, _P, _I64, _P, _P, _P, _P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -182,6 +183,22 @@ def batch_spmv_waxpy(B, x: np.ndarray, alpha: float, count: int | None = None):
                                    _ptr(rp), _ptr(ci), _ptr(val), _ptr(x), float(alpha),
                                    _ptr(y), _ptr(w), _ptr(absum))
     return y, w, absum
+
+
+def cg(A, b: np.ndarray, iters: int, x0: np.ndarray | None = None):
+    """Conjugate gradients (FP64) on a square SPD CSR matrix: returns (x after
+    `iters` iterations, rr_hist[0..iters]) -- the Krylov iteration built
+    from the SpMV, dot and AXPY/WAXPY kernels of the library."""
+    n = A.nrows
+    assert A.ncols == n
+    rp, ci, val = _c(A.row_ptr, np.int32), _c(A.col_idx, np.int32), _c(A.val, np.float64)
+    b = _c(b, np.float64)
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    hist = np.empty(iters + 1)
+    r, p, q = np.empty(n), np.empty(n), np.empty(n)
+    lib().orc_cg_f64(n, _ptr(rp), _ptr(ci), _ptr(val), _ptr(b), _ptr(x), int(iters), _ptr(hist), _ptr(r), _ptr(p),
+                     _ptr(q))
+    return x, hist
 
 
 def max_ulp(a: np.ndarray, b: np.ndarray):

@@ -339,3 +339,44 @@ ORC_API int64_t orc_check_rows(int64_t m, const double *y, const double *ref, co
     if (where) *where = at;
     return bad;
 }
+
+/* ------------------------------------------------------------------- CG -- */
+
+/* Conjugate gradients on a square symmetric positive definite CSR matrix
+ * (FP64), the textbook recurrence in its usual order: r = b - A x, p = r,
+ * rr = r.r; then per iteration q = A p, alpha = rr / (p.q), x += alpha p,
+ * r -= alpha q, rr' = r.r, beta = rr' / rr, p = r + beta p.  x holds the
+ * initial guess on entry and the iterate on return; rr_hist[k] = r_k.r_k for
+ * k = 0..iters.  Every update is one fused multiply-add per element.  Once
+ * the residual is exactly zero the step sizes are taken as zero (instead of
+ * 0/0), so the iterate stays put. */
+ORC_API void orc_cg_f64(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val,
+                        const double *b, double *x, int64_t iters, double *rr_hist,
+                        double *r, double *p, double *q)
+{
+    orc_spmv_csr_f64(n, row_ptr, col_idx, val, x, q, NULL);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        r[i] = fma(-1.0, q[i], b[i]);
+        p[i] = r[i];
+    }
+    double rr = orc_dot_f64(n, r, r);
+    rr_hist[0] = rr;
+    for (int64_t k = 0; k < iters; ++k) {
+        orc_spmv_csr_f64(n, row_ptr, col_idx, val, p, q, NULL);
+        const double pq = orc_dot_f64(n, p, q);
+        const double alpha = pq != 0.0 ? rr / pq : 0.0;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = fma(alpha, p[i], x[i]);
+            r[i] = fma(-alpha, q[i], r[i]);
+        }
+        const double rr_new = orc_dot_f64(n, r, r);
+        const double beta = rr != 0.0 ? rr_new / rr : 0.0;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            p[i] = fma(beta, p[i], r[i]);
+        rr = rr_new;
+        rr_hist[k + 1] = rr;
+    }
+}

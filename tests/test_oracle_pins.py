@@ -435,3 +435,54 @@ def test_wrong_sign_fails_exact_waxpy():
     w = O.waxpy(-1.5, x, y)
     ex = [_round_exact(Fraction(1.5) * Fraction(float(a)) + Fraction(float(b))) for a, b in zip(x, y)]
     assert not np.array_equal(w, np.array(ex))
+
+
+# --- the Krylov iteration (CG) built on the kernels -------------------------
+
+def test_cg_terminates_on_k_distinct_eigenvalues():
+    """In exact arithmetic CG on a matrix with k distinct eigenvalues reaches
+    the solution in k iterations (a textbook property); in FP64 the residual
+    is then at rounding level."""
+    n = 500
+    d = np.array([1.0, 2.0, 3.5, 7.0, 11.0])[np.arange(n) % 5]
+    A = I.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    b = I.uniform(3, 0, n)
+    x, hist = O.cg(A, b, 5)
+    assert np.sqrt(hist[5]) <= 1e-12 * np.sqrt(hist[0])
+    assert np.max(np.abs(x - b / d)) <= 1e-12 * np.max(np.abs(b / d))
+
+
+def test_cg_matches_direct_solve_on_laplacian():
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    A = I.lap2d(24)
+    b = I.uniform(4, 0, A.nrows)
+    x, hist = O.cg(A, b, 400)
+    S = sp.csr_matrix((A.val, A.col_idx, A.row_ptr), shape=(A.nrows, A.ncols))
+    xd = spla.spsolve(S.tocsc(), b)
+    assert np.max(np.abs(x - xd)) <= 1e-9 * np.max(np.abs(xd))
+    # the recurrence residual tracks the true residual
+    assert abs(np.sqrt(hist[-1]) - np.linalg.norm(b - S @ x)) <= 1e-9 * np.linalg.norm(b)
+
+
+def test_cg_first_step_closed_form():
+    """One iteration from x0 = 0: x1 = (b.b / b.Ab) b."""
+    A = I.lap2d(10)
+    b = I.uniform(5, 0, A.nrows)
+    x, hist = O.cg(A, b, 1)
+    Ab, _ = O.spmv(A, b)
+    alpha = Fraction(float(np.dot(b, b))) / Fraction(float(np.dot(b, Ab)))
+    assert np.max(np.abs(x - float(alpha) * b)) <= 1e-14 * np.max(np.abs(b))
+    assert hist[0] == O.dot(b, b)
+
+
+def test_cg_exact_solution_stays_put():
+    """Starting from the exact solution the residual is zero and the guarded
+    step sizes keep the iterate unchanged (no 0/0)."""
+    n = 64
+    d = np.full(n, 2.0)
+    A = I.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    x0 = I.uniform(6, 0, n)
+    b = 2.0 * x0
+    x, hist = O.cg(A, b, 3, x0=x0)
+    assert np.array_equal(x, x0) and np.all(hist == 0.0)
