@@ -143,6 +143,7 @@ def main():
         out["vector_sweep"] = vector_sweep(spk, torch, I, dev)
         out["spmv_large"] = spmv_large(spk, torch, I, dev)
         out["krylov_step_lap2d"] = lap2d_step(spk, torch, I, dev)
+        out["cg_lap3d_128"] = cg_lap3d(spk, torch, I, dev)
         out["serving"] = serving(spk, I, args.serve_requests)
 
     cpu = None
@@ -367,6 +368,81 @@ def lap2d_step(spk, torch, I, dev):
     M.release()
     return {"tuned_us": round(rep.best_us, 2), "plain_us": round(rep.plain_us, 2), "best": rep.best.as_dict(),
             "variants_timed": rep.tried, "rejected": rep.rejected}
+
+
+def cg_lap3d(spk, torch, I, dev, iters=100):
+    """Conjugate gradients on the 7-point Laplacian 128^3 (2,097,152 rows):
+    the fused solve (three launches per iteration, scalars on the device)
+    vs. the same iteration composed from the library's separately tuned
+    SpMV, dot, AXPY and WAXPY calls with the step sizes read back to the
+    host.  Per-iteration time = (solve of `iters` - solve of 0) / iters."""
+    import numpy as np
+    A = I.lap3d(128)
+    n, nnz = A.nrows, A.nnz
+    M = spk.Matrix(A)
+    b = torch.from_numpy(I.uniform(61, 0, n)).to(dev)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    hist = torch.empty(iters + 1, dtype=torch.float64, device=dev)
+    key = spk.spk_class_key(spk.problem(spk.SPK_OP_SPMV, A=M))
+    plan = spk.spk_plan_get(key)
+
+    def solve(k):
+        x.zero_()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        spk.spk_cg(M, b, x, k, hist=hist[:k + 1])
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3
+
+    solve(10)
+    t_full = min(solve(iters) for _ in range(3))
+    t_zero = min(solve(0) for _ in range(3))
+    fused_us = (t_full - t_zero) / iters
+    rr = hist.cpu().numpy()
+
+    # the same iteration from separate library calls, host-synchronised
+    r = torch.empty_like(x)
+    p = torch.empty_like(x)
+    q = torch.empty_like(x)
+    d = torch.empty(1, dtype=torch.float64, device=dev)
+
+    def unfused(k):
+        x.zero_()
+        spk.spk_spmv_mat(M, x, q)
+        spk.spk_waxpy(-1.0, q, b, r)
+        p.copy_(r)
+        rr_ = spk.spk_dot(r, r, d).item()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            spk.spk_spmv_mat(M, p, q)
+            pq = spk.spk_dot(p, q, d).item()
+            a = rr_ / pq if pq != 0.0 else 0.0
+            spk.spk_axpy(a, p, x)
+            spk.spk_axpy(-a, q, r)
+            rn = spk.spk_dot(r, r, d).item()
+            beta = rn / rr_ if rr_ != 0.0 else 0.0
+            spk.spk_waxpy(beta, p, r, p)
+            rr_ = rn
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e6 / k, rr_
+
+    unfused(5)
+    unfused_us, rr_unfused = min(unfused(50) for _ in range(2))
+    fused_bytes = 12 * nnz + 4 * (n + 1) + 88 * n
+    res = {"rows": n, "nnz": nnz, "iters": iters,
+           "fused_us_per_iter": round(fused_us, 2), "unfused_us_per_iter": round(unfused_us, 2),
+           "speedup": round(unfused_us / fused_us, 2),
+           "bytes_per_iter": fused_bytes,
+           "fused_gbs": round(fused_bytes / (fused_us * 1e-6) / 1e9, 1),
+           "unfused_gbs_same_bytes": round(fused_bytes / (unfused_us * 1e-6) / 1e9, 1),
+           "rr_ratio_end": float(rr[-1] / rr[0]),
+           "spmv_plan": plan.as_dict() if plan is not None else None}
+    log(f"cg lap3d_128: {res}")
+    M.release()
+    return res
 
 
 def serving(spk, I, nreq):

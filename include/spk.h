@@ -207,6 +207,29 @@ spk_status spk_spmv_mat(spk_handle h, spk_matrix A, const void *x, void *y, spk_
 spk_status spk_spmv_waxpy(spk_handle h, spk_matrix A, double alpha, const void *x, void *y,
                           void *w, spk_stream stream);
 
+/* ------------------------------------------------- conjugate gradients -- */
+
+/* Conjugate gradients on a square symmetric positive definite registered
+ * FP64 matrix: `iters` iterations of the textbook recurrence (r = b - A x,
+ * p = r; per iteration q = A p, alpha = r.r / p.q, x += alpha p,
+ * r -= alpha q, beta = r'.r' / r.r, p = r + beta p), a step size whose
+ * denominator is exactly zero being taken as zero.  The iteration is not in
+ * the paper: it is the Krylov solver whose per-iteration kernels are the
+ * vector update of Figure 1 and the SpMV of Section 3, i.e. the hotspot
+ * kernels Section 1 sets out to specialize.  Each iteration is three
+ * launches (SpMV fused with p.q, both AXPYs fused with r.r, the direction
+ * update) with the scalars kept on the device: no host round trip.
+ *   b        device, n doubles (right-hand side), read only
+ *   x        device, n doubles, 8-byte aligned: initial guess on entry, the
+ *            iterate after `iters` iterations on return
+ *   d_rr_hist device, iters + 1 doubles: r_k.r_k for k = 0..iters
+ * Asynchronous on `stream`; the solve's working vectors are owned by the
+ * handle (one set per stream, grown on demand).  Errors: SPK_ERR_DTYPE for
+ * FP32 matrices, SPK_ERR_SHAPE for a non-square matrix or iters < 0,
+ * SPK_ERR_ALIAS when x overlaps b or the history. */
+spk_status spk_cg(spk_handle h, spk_matrix A, const void *b, void *x, int32_t iters, double *d_rr_hist,
+                  spk_stream stream);
+
 /* ------------------------------------------------- variants and tuning -- */
 
 /* A problem for spk_run / spk_tune.  SPMV/SPMV_WAXPY use A (registered) and

@@ -262,10 +262,11 @@ spk_status run_dot(spk_handle h, int dtype, int64_t n, const void *x, const void
     L.x = x;
     L.y = y;
     L.partial = d->partial;
-    L.ticket = d->ticket;
+    L.ticket = g <= kDotTicketMaxGrid ? d->ticket : nullptr;
     L.out = out;
     L.grid = g;
     SPK_HIP(e->fn[dtype](L, s));
+    if (!L.ticket) SPK_HIP(launch_dot_final(d->partial, g, out, s));
     return SPK_OK;
 }
 
@@ -541,6 +542,30 @@ void db_append(spk_handle h, const std::string &key, const spk_variant &v, doubl
     fclose(f);
 }
 
+spk_status resolve(spk_handle h, const spk_problem &p, const spk_csr *csr, spk_variant *v)
+{
+    if (h->plain) {
+        *v = plain_variant(p.op, 0);
+        if ((p.op == SPK_OP_SPMV || p.op == SPK_OP_SPMV_WAXPY) && csr && csr->nrows > 0 &&
+            (double)csr->nnz / (double)csr->nrows > 8.0)
+            *v = plain_variant(p.op, 1);
+        if ((p.op == SPK_OP_SPMV || p.op == SPK_OP_SPMV_WAXPY) && p.A && p.A->mean_len > 8.0)
+            *v = plain_variant(p.op, 1);
+        return SPK_OK;
+    }
+    const std::string key = class_key(p, csr);
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        auto it = h->plans.find(key);
+        if (it != h->plans.end()) {
+            *v = it->second;
+            return SPK_OK;
+        }
+    }
+    *v = default_variant(h, p, csr);
+    return SPK_OK;
+}
+
 }  // namespace spk
 
 using namespace spk;
@@ -626,7 +651,10 @@ static void free_mat(spk_mat *A)
         (void)hipFree(kv.second.ci);
         (void)hipFree(kv.second.val);
     }
-    for (auto &kv : A->blocks) hipFree(kv.second.blk);
+    for (auto &kv : A->blocks) {
+        (void)hipFree(kv.second.blk);
+        (void)hipFree(kv.second.bk);
+    }
     delete A;
 }
 
@@ -639,6 +667,11 @@ spk_status spk_destroy(spk_handle h)
     for (auto &kv : h->dot) {
         (void)hipFree(kv.second.partial);
         (void)hipFree(kv.second.ticket);
+    }
+    for (auto &kv : h->cg) {
+        (void)hipFree(kv.second.vec);
+        (void)hipFree(kv.second.part);
+        (void)hipFree(kv.second.sc);
     }
     if (h->flush_buf) (void)hipFree(h->flush_buf);
     for (int i = 0; i < 4; ++i) {
@@ -677,29 +710,6 @@ spk_status spk_device_info(spk_handle h, int32_t *num_cu, char *name, int32_t na
 
 // ----------------------------------------------------------- vector ops --
 
-static spk_status resolve(spk_handle h, const spk_problem &p, const spk_csr *csr, spk_variant *v)
-{
-    if (h->plain) {
-        *v = plain_variant(p.op, 0);
-        if ((p.op == SPK_OP_SPMV || p.op == SPK_OP_SPMV_WAXPY) && csr && csr->nrows > 0 &&
-            (double)csr->nnz / (double)csr->nrows > 8.0)
-            *v = plain_variant(p.op, 1);
-        if ((p.op == SPK_OP_SPMV || p.op == SPK_OP_SPMV_WAXPY) && p.A && p.A->mean_len > 8.0)
-            *v = plain_variant(p.op, 1);
-        return SPK_OK;
-    }
-    const std::string key = class_key(p, csr);
-    {
-        std::lock_guard<std::mutex> lk(h->mu);
-        auto it = h->plans.find(key);
-        if (it != h->plans.end()) {
-            *v = it->second;
-            return SPK_OK;
-        }
-    }
-    *v = default_variant(h, p, csr);
-    return SPK_OK;
-}
 
 spk_status spk_waxpy(spk_handle h, int32_t dtype, int64_t n, double alpha, const void *x, const void *y, void *w,
                      spk_stream stream)

@@ -53,9 +53,11 @@ __device__ __forceinline__ void wave_products(const int32_t *ci, const T *val, c
 // products to LDS, one lane per row sums from LDS (four interleaved
 // partial sums).  No workgroup barrier:
 // every wavefront of a CU is an independent stream.
-template <typename T, int ITEMS>
-__device__ __forceinline__ void wave_stream(const int32_t *rp, const int32_t *ci, const T *val, const T *x, T *y,
-                                            T *w, T alpha, int r0, int r1, int k0, int k1, double *sp, int *srp)
+// With DOT, also returns the lane's part of sum_i x_i*y_i over the tile's
+// rows (square matrices: x_i is the row's own entry of x).
+template <typename T, int ITEMS, bool DOT = false>
+__device__ __forceinline__ double wave_stream(const int32_t *rp, const int32_t *ci, const T *val, const T *x, T *y,
+                                              T *w, T alpha, int r0, int r1, int k0, int k1, double *sp, int *srp)
 {
     const int l = threadIdx.x & (kWave - 1);
     const int nr = r1 - r0;
@@ -65,8 +67,9 @@ __device__ __forceinline__ void wave_stream(const int32_t *rp, const int32_t *ci
     for (int q = 0; q < 3; ++q) rpv[q] = (l + q * kWave <= nr) ? rp[r0 + l + q * kWave] - k0 : 0;
     T xo[2];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) xo[q] = (w && l + q * kWave < nr) ? x[r0 + l + q * kWave] : T(0);
+    for (int q = 0; q < 2; ++q) xo[q] = ((DOT || w) && l + q * kWave < nr) ? x[r0 + l + q * kWave] : T(0);
     wave_products<T, ITEMS>(ci, val, x, k0, nk, sp);
+    double dot = 0.0;
 #pragma unroll
     for (int q = 0; q < 3; ++q)
         if (l + q * kWave <= nr) srp[l + q * kWave] = rpv[q];
@@ -91,9 +94,11 @@ __device__ __forceinline__ void wave_stream(const int32_t *rp, const int32_t *ci
             const T yt = (T)((a0 + a1) + (a2 + a3));
             __builtin_nontemporal_store(yt, y + r0 + i);
             if (w) __builtin_nontemporal_store(fma_t(alpha, yt, xo[q]), w + r0 + i);
+            if constexpr (DOT) dot = fma_t((double)xo[q], (double)yt, dot);
         }
     }
     wave_lds_sync();
+    return dot;
 }
 
 // G lanes per row over rows [r0, r1), one wavefront (64/G rows per pass).
@@ -132,11 +137,12 @@ __device__ __forceinline__ void wave_group_rows(const int32_t *rp, const int32_t
 // gathers, before it accumulates, so a row keeps 64*UNR gathers in flight
 // (the gathers of random-column rows are latency-bound).  UNR partial sums
 // per lane, combined in a fixed order, then the wavefront sum.
-template <typename T, int UNR>
-__device__ __forceinline__ void wave_rows_mlp(const int32_t *rp, const int32_t *ci, const T *val, const T *x, T *y,
-                                              T *w, T alpha, int r0, int r1)
+template <typename T, int UNR, bool DOT = false>
+__device__ __forceinline__ double wave_rows_mlp(const int32_t *rp, const int32_t *ci, const T *val, const T *x, T *y,
+                                                T *w, T alpha, int r0, int r1)
 {
     const int l = threadIdx.x & (kWave - 1);
+    double dot = 0.0;
     for (int row = r0; row < r1; ++row) {
         const int s = rp[row], e = rp[row + 1];
         double acc[UNR];
@@ -166,8 +172,10 @@ __device__ __forceinline__ void wave_rows_mlp(const int32_t *rp, const int32_t *
             const T yt = (T)sum;
             y[row] = yt;
             if (w) w[row] = fma_t(alpha, yt, x[row]);
+            if constexpr (DOT) dot = fma_t((double)x[row], (double)yt, dot);
         }
     }
+    return dot;
 }
 
 }  // namespace spk

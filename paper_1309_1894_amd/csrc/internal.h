@@ -97,6 +97,17 @@ struct DotScratch {
     int64_t cap = 0;
 };
 
+// Working set of a CG solve on one stream: r, p, q and an aligned copy of
+// x (vec_cap doubles each), two partial arrays (part_cap doubles each) and
+// the scalars.
+struct CgScratch {
+    double *vec = nullptr;
+    int64_t vec_cap = 0;
+    double *part = nullptr;
+    int64_t part_cap = 0;
+    double *sc = nullptr;         // kCgScalars doubles
+};
+
 }  // namespace spk
 
 struct spk_ctx {
@@ -109,6 +120,7 @@ struct spk_ctx {
     std::mutex mu;
     std::map<std::string, spk_variant> plans;
     std::map<hipStream_t, spk::DotScratch> dot;
+    std::map<hipStream_t, spk::CgScratch> cg;
     void *flush_buf = nullptr;
     int64_t flush_bytes = 0;
     hipStream_t sub[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -160,6 +172,10 @@ struct SpmvProblem {
 };
 
 spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hipStream_t s);
+
+// Variant the dispatcher uses for a problem (the plan recorded for its
+// class, else the default).
+spk_status resolve(spk_handle h, const spk_problem &p, const spk_csr *csr, spk_variant *v);
 
 // Variant used when the caller does not name one.
 spk_variant default_variant(spk_handle h, const spk_problem &p, const spk_csr *csr);

@@ -22,7 +22,8 @@ struct VecLaunch {
     const void *y;
     void *w;             // WAXPY/AXPY output
     double *partial;     // DOT: one double per workgroup
-    uint32_t *ticket;    // DOT: zero on entry, left zero on exit
+    uint32_t *ticket;    // DOT: zero on entry, left zero on exit; null = partials
+                         // only (finished by launch_dot_final)
     double *out;         // DOT: result
     int64_t grid;        // workgroups to launch
 };
@@ -36,6 +37,15 @@ struct VecEntry {
 
 const VecEntry *waxpy_table(int *count);
 const VecEntry *dot_table(int *count);
+
+// Second launch of a dot whose kernel ran without a ticket: *out = sum of
+// partial[0, count) in a fixed order.
+hipError_t launch_dot_final(const double *partial, int64_t count, double *out, hipStream_t s);
+
+// Largest dot grid finished by the ticket (each workgroup then publishes
+// its partial with a device-scope release, which writes back the XCD's L2
+// and serialises there); larger grids use launch_dot_final.
+constexpr int64_t kDotTicketMaxGrid = 16;
 
 // Elements covered by one workgroup in one pass.
 inline int64_t vec_per_block(const VecEntry &e) { return (int64_t)e.block * e.vec * e.unroll; }
@@ -71,6 +81,48 @@ const BatchEntry *batch_table(int *count);
 
 // Row-stream capacity (entries) of one wavefront's tile.
 inline int batch_wave_entries(const BatchEntry &e) { return e.tile / (e.block / 64); }
+
+// ------------------------------------------------------ conjugate gradients
+
+// Device scalars of one solve: r.r of the current iteration alternates
+// between sc[0] and sc[1] (the slot of iteration k is k & 1), so a kernel
+// can read one while its first workgroup writes the other.
+constexpr int kCgScalars = 2;
+constexpr int kCgVecBlock = 256, kCgVecUnroll = 2;
+constexpr int64_t kCgVecPer = (int64_t)kCgVecBlock * 2 * kCgVecUnroll;   // elements per workgroup pass
+
+struct CgLaunch {
+    int64_t n;                 // rows (= columns)
+    const int32_t *rp, *ci;    // CSR of the matrix
+    const double *val;
+    const uint32_t *blocks;    // wavefront tiles: nblk + 1 packed starts
+    const int32_t *block_k;    // first entry of each tile
+    int32_t nblk;
+    int32_t spmv_grid;         // workgroups of the SpMV kernel (slots of part1)
+    const double *spmv_x;      // operand of the product (p, or x at the start)
+    const double *b;
+    double *x, *r, *p, *q;     // x, r, p, q 16-byte aligned
+    double *part1;             // p.q partials, one per SpMV workgroup (null: no dot)
+    double *part2;             // r.r partials, one per vector workgroup
+    double *sc;                // kCgScalars doubles
+    double *hist;              // where this launch records r.r
+    int32_t slot;              // iteration parity
+    int64_t grid;              // workgroups of the vector kernels (slots of part2)
+};
+
+using CgFn = hipError_t (*)(const CgLaunch &, hipStream_t);
+
+struct CgEntry {
+    int block, entries;        // threads per workgroup, row-stream entries per wavefront
+    CgFn spmv_dot;
+};
+
+const CgEntry *cg_table(int *count);
+hipError_t launch_cg_start(const CgLaunch &c, hipStream_t s);
+hipError_t launch_cg_update(const CgLaunch &c, hipStream_t s);
+hipError_t launch_cg_direction(const CgLaunch &c, hipStream_t s);
+hipError_t launch_cg_record(const CgLaunch &c, hipStream_t s);
+hipError_t launch_cg_zero(double *hist, int64_t count, hipStream_t s);
 
 // ------------------------------------------------------------- utilities
 

@@ -1,0 +1,271 @@
+// kernels_cg.hip -- conjugate-gradient iteration on the library's kernels.
+//
+// One CG iteration (textbook order) needs q = A p, p.q, two AXPYs, r.r and
+// the direction update p = r + beta p.  Composed from separate library calls
+// that is one SpMV, two dot passes, three vector passes and two host round
+// trips for the step sizes.  Here it is three launches with every scalar
+// kept on the device:
+//
+//   k_cg_spmv_dot   q = A p on the wavefront tiles of the matrix; each
+//                   workgroup also leaves its part of p.q (the own-row entry
+//                   of p is already loaded for the tile).
+//   k_cg_update     alpha = r.r / p.q from those parts, then x += alpha p,
+//                   r -= alpha q and this workgroup's part of the new r.r.
+//   k_cg_direction  beta = r'.r' / r.r from those parts, p = r + beta p; the
+//                   first workgroup records r'.r'.
+//
+// A reduction is finished by the kernel that consumes it: every workgroup
+// of the consumer adds the producer's partials in the same fixed order, so
+// all of them hold the same bits and no workgroup of the producer has to
+// publish its partial with a device-scope release (on this GPU such a
+// release writes back the XCD's L2 and serialises there, which costs more
+// than the whole SpMV at thousands of workgroups).  A step size whose
+// denominator is exactly zero is taken as zero.
+#include "device_rows.h"
+#include "kernels.h"
+
+namespace spk {
+
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+
+namespace {
+
+// Sum of part[0, n) in a fixed order (lane-strided, then the block tree),
+// returned to every thread.
+template <int BS>
+__device__ __forceinline__ double sum_partials(const double *part, int64_t n, double *red)
+{
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += BS) a += part[i];
+    return block_sum<BS>(a, red);
+}
+
+}  // namespace
+
+// q = A p over wavefront tiles.  Workgroup slot s (XCD-contiguous) runs the
+// tile groups [s*G/grid, (s+1)*G/grid), wavefront w tile w of each group.
+template <int BS, int E>
+__global__ __launch_bounds__(BS) void k_cg_spmv_dot(CgLaunch c)
+{
+    constexpr int NW = BS / kWave;
+    __shared__ double sp[NW * E];
+    __shared__ int srp[NW * (kWaveTileRows + 1)];
+    __shared__ double red[NW];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int ngroups = (c.nblk + NW - 1) / NW;
+    const int slot = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int g0 = (int)((int64_t)ngroups * slot / gridDim.x);
+    const int g1 = (int)((int64_t)ngroups * (slot + 1) / gridDim.x);
+    const double *p = c.spmv_x;
+    double d = 0.0;
+    for (int g = g0; g < g1; ++g) {
+        const int bl = g * NW + wv;
+        if (bl >= c.nblk) break;
+        const uint32_t e0 = c.blocks[bl], e1 = c.blocks[bl + 1];
+        const int r0 = (int)(e0 & kBlkRowMask), r1 = (int)(e1 & kBlkRowMask);
+        if ((e0 >> 30) == kBlkStream)
+            d += wave_stream<double, E / kWave, true>(c.rp, c.ci, c.val, p, c.q, nullptr, 0.0, r0, r1,
+                                                      c.block_k[bl], c.block_k[bl + 1], sp + wv * E,
+                                                      srp + wv * (kWaveTileRows + 1));
+        else
+            d += wave_rows_mlp<double, 8, true>(c.rp, c.ci, c.val, p, c.q, nullptr, 0.0, r0, r1);
+    }
+    if (!c.part1) return;   // same for the whole grid
+    d = block_sum<BS>(d, red);
+    if (threadIdx.x == 0) c.part1[slot] = d;
+}
+
+// alpha = rr / p.q, x += alpha p, r -= alpha q, part2 = this workgroup's
+// r.r.  Two doubles per lane access, UNR accesses in flight.
+template <int BS, int UNR>
+__global__ __launch_bounds__(BS) void k_cg_update(CgLaunch c)
+{
+    constexpr int64_t PER = (int64_t)BS * 2 * UNR;
+    __shared__ double red[BS / kWave];
+    const double pq = sum_partials<BS>(c.part1, c.spmv_grid, red);
+    const double rr = c.sc[c.slot];
+    const double alpha = pq != 0.0 ? rr / pq : 0.0;
+    const int t = threadIdx.x;
+    const int64_t n = c.n;
+    double acc[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) acc[u] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * PER;
+    for (int64_t base = (int64_t)blockIdx.x * PER; base < n; base += stride) {
+        if (base + PER <= n) {
+            f64x2_t xv[UNR], rv[UNR], pv[UNR], qv[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int64_t i = base + ((int64_t)u * BS + t) * 2;
+                xv[u] = __builtin_nontemporal_load((const f64x2_t *)(c.x + i));
+                rv[u] = *(const f64x2_t *)(c.r + i);
+                pv[u] = *(const f64x2_t *)(c.p + i);
+                qv[u] = __builtin_nontemporal_load((const f64x2_t *)(c.q + i));
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int64_t i = base + ((int64_t)u * BS + t) * 2;
+                f64x2_t xn, rn;
+                xn[0] = fma_t(alpha, pv[u][0], xv[u][0]);
+                xn[1] = fma_t(alpha, pv[u][1], xv[u][1]);
+                rn[0] = fma_t(-alpha, qv[u][0], rv[u][0]);
+                rn[1] = fma_t(-alpha, qv[u][1], rv[u][1]);
+                acc[u] = fma_t(rn[0], rn[0], acc[u]);
+                acc[u] = fma_t(rn[1], rn[1], acc[u]);
+                __builtin_nontemporal_store(xn, (f64x2_t *)(c.x + i));
+                *(f64x2_t *)(c.r + i) = rn;
+            }
+        } else {
+            for (int64_t i = base + t; i < n && i < base + PER; i += BS) {
+                c.x[i] = fma_t(alpha, c.p[i], c.x[i]);
+                const double rn = fma_t(-alpha, c.q[i], c.r[i]);
+                c.r[i] = rn;
+                acc[0] = fma_t(rn, rn, acc[0]);
+            }
+        }
+    }
+    double s = acc[0];
+#pragma unroll
+    for (int u = 1; u < UNR; ++u) s += acc[u];
+    s = block_sum<BS>(s, red);
+    if (t == 0) c.part2[blockIdx.x] = s;
+}
+
+// beta = rr' / rr with rr' the sum of part2, p = r + beta p; the first
+// workgroup records rr' (hist, and the other scalar slot).
+template <int BS, int UNR>
+__global__ __launch_bounds__(BS) void k_cg_direction(CgLaunch c)
+{
+    constexpr int64_t PER = (int64_t)BS * 2 * UNR;
+    __shared__ double red[BS / kWave];
+    const double rr_new = sum_partials<BS>(c.part2, c.grid, red);
+    const double rr = c.sc[c.slot];
+    const double beta = rr != 0.0 ? rr_new / rr : 0.0;
+    const int t = threadIdx.x;
+    if (blockIdx.x == 0 && t == 0) {
+        c.sc[c.slot ^ 1] = rr_new;
+        *c.hist = rr_new;
+    }
+    const int64_t n = c.n;
+    const int64_t stride = (int64_t)gridDim.x * PER;
+    for (int64_t base = (int64_t)blockIdx.x * PER; base < n; base += stride) {
+        if (base + PER <= n) {
+            f64x2_t rv[UNR], pv[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int64_t i = base + ((int64_t)u * BS + t) * 2;
+                rv[u] = __builtin_nontemporal_load((const f64x2_t *)(c.r + i));
+                pv[u] = *(const f64x2_t *)(c.p + i);
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int64_t i = base + ((int64_t)u * BS + t) * 2;
+                f64x2_t pn;
+                pn[0] = fma_t(beta, pv[u][0], rv[u][0]);
+                pn[1] = fma_t(beta, pv[u][1], rv[u][1]);
+                *(f64x2_t *)(c.p + i) = pn;
+            }
+        } else {
+            for (int64_t i = base + t; i < n && i < base + PER; i += BS) c.p[i] = fma_t(beta, c.p[i], c.r[i]);
+        }
+    }
+}
+
+// Start of the solve, after q = A x: r = b - q, p = r, part2 = r.r parts.
+template <int BS, int UNR>
+__global__ __launch_bounds__(BS) void k_cg_start(CgLaunch c)
+{
+    constexpr int64_t PER = (int64_t)BS * 2 * UNR;
+    __shared__ double red[BS / kWave];
+    const int t = threadIdx.x;
+    const int64_t n = c.n;
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * PER;
+    for (int64_t base = (int64_t)blockIdx.x * PER; base < n; base += stride) {
+        for (int64_t i = base + t; i < n && i < base + PER; i += BS) {
+            const double rn = fma_t(-1.0, c.q[i], c.b[i]);
+            c.r[i] = rn;
+            c.p[i] = rn;
+            acc = fma_t(rn, rn, acc);
+        }
+    }
+    const double s = block_sum<BS>(acc, red);
+    if (t == 0) c.part2[blockIdx.x] = s;
+}
+
+// One workgroup: rr = sum of part2 (same order as k_cg_direction) into
+// sc[slot] and hist.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_cg_record(CgLaunch c)
+{
+    __shared__ double red[BS / kWave];
+    const double rr = sum_partials<BS>(c.part2, c.grid, red);
+    if (threadIdx.x == 0) {
+        c.sc[c.slot] = rr;
+        *c.hist = rr;
+    }
+}
+
+// hist[0, count) = 0 (the solve of an empty system).
+__global__ __launch_bounds__(256) void k_cg_zero(double *hist, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) hist[i] = 0.0;
+}
+
+namespace {
+
+template <int BS, int E>
+hipError_t L_spmv_dot(const CgLaunch &c, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_cg_spmv_dot<BS, E>), dim3((unsigned)c.spmv_grid), dim3(BS), 0, s, c);
+    return hipGetLastError();
+}
+
+const CgEntry kCg[] = {
+    {128, 256, L_spmv_dot<128, 256>},  {128, 512, L_spmv_dot<128, 512>},  {128, 1024, L_spmv_dot<128, 1024>},
+    {256, 256, L_spmv_dot<256, 256>},  {256, 512, L_spmv_dot<256, 512>},  {256, 1024, L_spmv_dot<256, 1024>},
+    {512, 256, L_spmv_dot<512, 256>},  {512, 512, L_spmv_dot<512, 512>},  {512, 1024, L_spmv_dot<512, 1024>},
+};
+
+}  // namespace
+
+const CgEntry *cg_table(int *count)
+{
+    *count = (int)(sizeof(kCg) / sizeof(kCg[0]));
+    return kCg;
+}
+
+hipError_t launch_cg_start(const CgLaunch &c, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_cg_start<kCgVecBlock, kCgVecUnroll>), dim3((unsigned)c.grid), dim3(kCgVecBlock), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const CgLaunch &c, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_cg_update<kCgVecBlock, kCgVecUnroll>), dim3((unsigned)c.grid), dim3(kCgVecBlock), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_direction(const CgLaunch &c, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_cg_direction<kCgVecBlock, kCgVecUnroll>), dim3((unsigned)c.grid), dim3(kCgVecBlock), 0, s,
+                       c);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_record(const CgLaunch &c, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_cg_record<kCgVecBlock>), dim3(1), dim3(kCgVecBlock), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_zero(double *hist, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cg_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, hist, count);
+    return hipGetLastError();
+}
+
+}  // namespace spk

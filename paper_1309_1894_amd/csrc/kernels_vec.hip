@@ -102,8 +102,13 @@ __global__ __launch_bounds__(BS) void k_waxpy(int64_t n, T alpha, const T *x, co
 
 // d = sum_i x_i*y_i in FP64.  Each lane keeps UNR running FMA chains over a
 // fixed set of elements, the workgroup reduces them (DPP within waves, LDS
-// across waves) into partial[blockIdx.x], and the last workgroup to finish
-// (ticket) adds the partials in index order.  The order of every addition
+// across waves) into partial[blockIdx.x].  Small grids finish in the same
+// launch: the last workgroup to finish (ticket) adds the partials in index
+// order.  Without a ticket the kernel only leaves the partials and
+// k_dot_final adds them in the same order in a second launch: each
+// workgroup would otherwise publish its partial with a device-scope
+// release, which writes back its XCD's L2 and serialises there (tens of
+// microseconds at a thousand workgroups).  The order of every addition
 // depends only on (n, variant), so results are reproducible bit for bit.
 template <typename T, int BS, int VEC, int UNR>
 __global__ __launch_bounds__(BS) void k_dot(int64_t n, const T *x, const T *y, double *partial,
@@ -146,6 +151,10 @@ __global__ __launch_bounds__(BS) void k_dot(int64_t n, const T *x, const T *y, d
 #pragma unroll
     for (int u = 1; u < UNR; ++u) s += acc[u];
     s = block_sum<BS>(s, red);
+    if (!ticket) {
+        if (t == 0) partial[blockIdx.x] = s;
+        return;
+    }
     if (t == 0) {
         partial[blockIdx.x] = s;
         __threadfence();
@@ -163,6 +172,24 @@ __global__ __launch_bounds__(BS) void k_dot(int64_t n, const T *x, const T *y, d
             *ticket = 0u;
         }
     }
+}
+
+// *out = sum of partial[0, count): the partials in index-strided order
+// per lane, then the workgroup tree.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_dot_final(const double *partial, int64_t count, double *out)
+{
+    __shared__ double red[BS / kWave];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += BS) a += partial[i];
+    a = block_sum<BS>(a, red);
+    if (threadIdx.x == 0) *out = a;
+}
+
+hipError_t launch_dot_final(const double *partial, int64_t count, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot_final<1024>, dim3(1), dim3(1024), 0, s, partial, count, out);
+    return hipGetLastError();
 }
 
 namespace {

@@ -23,6 +23,11 @@ library is specified against):
 * ``zipf(m, ...)`` -- row lengths i.i.d. truncated Zipf P(L=k) ~ k^-s on
   1..min(kmax, n); one seed-chosen row forced to the maximum length; columns
   uniform without replacement, sorted; values uniform[-1, 1).
+* ``spd_zipf(m)`` -- the zipf pattern made symmetric (each unordered pair
+  {i, j} of an entry gets one value uniform[-1, 1)), plus a diagonal of
+  1 + (off-diagonal entries in the row): strictly diagonally dominant,
+  hence symmetric positive definite (the conjugate-gradient input with
+  irregular rows).
 * ``banded(m, b, fill)`` -- every position with |r - c| <= b kept
   independently with probability ``fill``; values uniform[-1, 1).
 * ``batch_banded(count, ...)`` -- ``count`` banded instances with row counts
@@ -223,6 +228,29 @@ def zipf(m: int, n: int | None = None, mean_target_s: float = ZIPF_S_MEAN16, kma
     cols = _distinct_sorted_cols(rows, n, seed_struct, 100) if rows.size else rows
     val = uniform(seed_val, 0, rows.size, dtype)
     return _csr_from_sorted(m, n, rows, cols, val)
+
+
+def spd_zipf(m: int, kmax: int = 4096, s: float = ZIPF_S_MEAN16, seed_struct: int = 34,
+             seed_val: int = 35) -> CSR:
+    """Symmetric positive definite matrix on the symmetrized zipf pattern.
+
+    Off-diagonal values |v| < 1 and diagonal 1 + (off-diagonal count of the
+    row) make every row strictly diagonally dominant."""
+    Z = zipf(m, m, s, kmax, seed_struct, seed_val)
+    rows = np.repeat(np.arange(m, dtype=np.int64), Z.row_lengths())
+    cols = Z.col_idx.astype(np.int64)
+    off = rows != cols
+    lo, hi = np.minimum(rows[off], cols[off]), np.maximum(rows[off], cols[off])
+    key = np.unique(lo * m + hi)
+    lo, hi = key // m, key % m
+    v = sym_f64(u64_at(seed_val, 1, key.astype(np.uint64)))
+    diag = np.arange(m, dtype=np.int64)
+    r = np.concatenate([lo, hi, diag])
+    c = np.concatenate([hi, lo, diag])
+    deg = np.bincount(np.concatenate([lo, hi]), minlength=m).astype(np.float64)
+    vals = np.concatenate([v, v, 1.0 + deg])
+    order = np.lexsort((c, r))
+    return _csr_from_sorted(m, m, r[order], c[order], np.ascontiguousarray(vals[order]))
 
 
 def banded(m: int, b: int, fill: float = 0.6, seed_struct: int = 41, seed_val: int = 42,

@@ -111,6 +111,7 @@ _SIGS = {
     "spk_matrix_bytes": (_S, [_P, _P, C.POINTER(_I64)]),
     "spk_spmv_mat": (_S, [_P, _P, _P, _P, _P]),
     "spk_spmv_waxpy": (_S, [_P, _P, _D, _P, _P, _P, _P]),
+    "spk_cg": (_S, [_P, _P, _P, _P, _I32, _P, _P]),
     "spk_run": (_S, [_P, C.POINTER(spk_problem), C.POINTER(spk_variant), _P]),
     "spk_variant_count": (_S, [_I32, _I32, C.POINTER(_I32)]),
     "spk_variant_get": (_S, [_I32, _I32, _I32, C.POINTER(spk_variant)]),
@@ -350,6 +351,18 @@ def spk_spmv_waxpy(A: Matrix, alpha: float, x, y=None, w=None, stream=None):
     _ok(_lib.spk_spmv_waxpy(A.handle.ptr, A.ptr, float(alpha), _dev(x, "x"), _dev(y, "y"), _dev(w, "w"),
                             _stream(stream)), "spk_spmv_waxpy")
     return y, w
+
+
+def spk_cg(A: Matrix, b, x, iters: int, hist=None, stream=None):
+    """Conjugate gradients on a registered FP64 SPD matrix: ``iters``
+    iterations starting from (and overwriting) ``x``.  Returns ``hist``, a
+    float64 device tensor of r_k.r_k for k = 0..iters."""
+    torch = _torch()
+    if hist is None:
+        hist = torch.empty(int(iters) + 1, dtype=torch.float64, device=x.device)
+    _ok(_lib.spk_cg(A.handle.ptr, A.ptr, _dev(b, "b"), _dev(x, "x"), int(iters), _dev(hist, "hist"),
+                    _stream(stream)), "spk_cg")
+    return hist
 
 
 # ------------------------------------------------------ variants, tuning --

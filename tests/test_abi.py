@@ -28,7 +28,7 @@ def declared():
 def test_header_declares_the_boundary():
     names = declared()
     for must in ["spk_spmv_csr", "spk_waxpy", "spk_axpy", "spk_dot", "spk_tune", "spk_matrix_register",
-                 "spk_spmv_waxpy", "spk_batch_plan", "spk_batch_run", "spk_serve_create", "spk_serve_replay"]:
+                 "spk_spmv_waxpy", "spk_cg", "spk_batch_plan", "spk_batch_run", "spk_serve_create", "spk_serve_replay"]:
         assert must in names
 
 
@@ -57,6 +57,7 @@ def test_null_handle_rejected_before_hip(lib):
     assert L.spk_axpy(None, 1, 10, 1.0, None, None, None) == 1
     assert L.spk_dot(None, 1, 10, None, None, None, None) == 1
     assert L.spk_spmv_csr(None, None, None, None, None) == 1
+    assert L.spk_cg(None, None, None, None, 0, None, None) == 1
     assert L.spk_destroy(None) == 1
     assert L.spk_batch_free(None, None) == 1
     assert L.spk_serve_destroy(None) == 1

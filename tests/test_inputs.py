@@ -94,3 +94,25 @@ def test_poisson_arrivals_rate():
     t = I.poisson_arrivals(100000, 1000.0)
     assert np.all(np.diff(t) > 0)
     assert abs(t[-1] / 100000 - 1e-3) < 2e-5
+
+
+def test_spd_zipf_symmetric_dominant_sorted():
+    A = I.spd_zipf(2000, seed_struct=5, seed_val=6)
+    rp, ci, v = A.row_ptr.astype(np.int64), A.col_idx.astype(np.int64), A.val
+    r = np.repeat(np.arange(A.nrows), A.row_lengths())
+    # sorted, distinct columns in every row
+    same = r[1:] == r[:-1]
+    assert np.all(ci[1:][same] > ci[:-1][same])
+    # symmetric: the transposed entry list is the same list
+    fwd = sorted(zip(r.tolist(), ci.tolist(), v.tolist()))
+    bwd = sorted(zip(ci.tolist(), r.tolist(), v.tolist()))
+    assert fwd == bwd
+    # strictly diagonally dominant with a positive diagonal (hence SPD)
+    diag = r == ci
+    assert np.array_equal(r[diag], np.arange(A.nrows))
+    off_abs = np.bincount(r[~diag], weights=np.abs(v[~diag]), minlength=A.nrows)
+    assert np.all(v[diag] > off_abs)
+    # the zipf hub row survives symmetrization
+    assert A.row_lengths().max() >= 2000
+    B = I.spd_zipf(2000, seed_struct=5, seed_val=6)
+    assert np.array_equal(A.val, B.val) and np.array_equal(A.col_idx, B.col_idx)
