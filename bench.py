@@ -372,10 +372,14 @@ def lap2d_step(spk, torch, I, dev):
 
 def cg_lap3d(spk, torch, I, dev, iters=100):
     """Conjugate gradients on the 7-point Laplacian 128^3 (2,097,152 rows):
-    the fused solve (three launches per iteration, scalars on the device)
-    vs. the same iteration composed from the library's separately tuned
-    SpMV, dot, AXPY and WAXPY calls with the step sizes read back to the
-    host.  Per-iteration time = (solve of `iters` - solve of 0) / iters."""
+    the fused solve (three launches per iteration, scalars on the device,
+    SpMV tile shape tuned by spk_cg_tune) vs. the same iteration composed
+    from the library's separately tuned SpMV, dot, AXPY and WAXPY calls with
+    the step sizes read back to the host.  Per-iteration time = (solve of
+    `iters` - solve of 0) / iters; bytes per iteration are the algorithmic
+    traffic of the fused schedule: the matrix (12 nnz + 4 (n+1)), p read and
+    q written by the SpMV (16 n), r and q read and r written (24 n), x, r, p
+    read and x, p written (40 n)."""
     import numpy as np
     A = I.lap3d(128)
     n, nnz = A.nrows, A.nnz
@@ -383,8 +387,8 @@ def cg_lap3d(spk, torch, I, dev, iters=100):
     b = torch.from_numpy(I.uniform(61, 0, n)).to(dev)
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     hist = torch.empty(iters + 1, dtype=torch.float64, device=dev)
-    key = spk.spk_class_key(spk.problem(spk.SPK_OP_SPMV, A=M))
-    plan = spk.spk_plan_get(key)
+    # Section 2's search over the SpMV tile shape of the solve (not timed)
+    tune = spk.spk_cg_tune(M, b, 10, reps=5, warmup=1)
 
     def solve(k):
         x.zero_()
@@ -431,7 +435,7 @@ def cg_lap3d(spk, torch, I, dev, iters=100):
 
     unfused(5)
     unfused_us, rr_unfused = min(unfused(50) for _ in range(2))
-    fused_bytes = 12 * nnz + 4 * (n + 1) + 88 * n
+    fused_bytes = 12 * nnz + 4 * (n + 1) + 80 * n
     res = {"rows": n, "nnz": nnz, "iters": iters,
            "fused_us_per_iter": round(fused_us, 2), "unfused_us_per_iter": round(unfused_us, 2),
            "speedup": round(unfused_us / fused_us, 2),
@@ -439,7 +443,9 @@ def cg_lap3d(spk, torch, I, dev, iters=100):
            "fused_gbs": round(fused_bytes / (fused_us * 1e-6) / 1e9, 1),
            "unfused_gbs_same_bytes": round(fused_bytes / (unfused_us * 1e-6) / 1e9, 1),
            "rr_ratio_end": float(rr[-1] / rr[0]),
-           "spmv_plan": plan.as_dict() if plan is not None else None}
+           "tuned_shape": {"block": tune.best.block, "entries": tune.best.lds},
+           "tune_10_iters_us": {"tuned": round(tune.best_us, 1), "default_shape": round(tune.plain_us, 1),
+                                "shapes_timed": tune.tried, "rejected": tune.rejected}}
     log(f"cg lap3d_128: {res}")
     M.release()
     return res

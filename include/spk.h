@@ -217,8 +217,10 @@ spk_status spk_spmv_waxpy(spk_handle h, spk_matrix A, double alpha, const void *
  * the paper: it is the Krylov solver whose per-iteration kernels are the
  * vector update of Figure 1 and the SpMV of Section 3, i.e. the hotspot
  * kernels Section 1 sets out to specialize.  Each iteration is three
- * launches (SpMV fused with p.q, both AXPYs fused with r.r, the direction
- * update) with the scalars kept on the device: no host round trip.
+ * launches with the scalars kept on the device (no host round trip): the
+ * SpMV fused with p.q, the residual update fused with r.r, and the x and
+ * direction updates in one pass over p.  The SpMV tile shape is the one
+ * spk_cg_tune recorded for A's class, else a default.
  *   b        device, n doubles (right-hand side), read only
  *   x        device, n doubles, 8-byte aligned: initial guess on entry, the
  *            iterate after `iters` iterations on return
@@ -303,6 +305,24 @@ spk_status spk_class_key(spk_handle h, const spk_problem *problem, char *out, in
 /* Looks up / stores a plan DB entry directly. */
 spk_status spk_plan_get(spk_handle h, const char *class_key, spk_variant *out);
 spk_status spk_plan_put(spk_handle h, const char *class_key, const spk_variant *v);
+
+/* Section 2's search applied to the solve.  The one knob is the
+ * wavefront-tile shape of the SpMV+dot kernel (threads per workgroup and
+ * row-stream entries per wavefront, reported as an SPK_FMT_ADAPTIVE variant
+ * with `block` and `lds`): it sets the number of partial sums every
+ * workgroup of the residual kernel adds, so the solve's best shape can
+ * differ from a lone SpMV's.  Every compiled shape runs `iters` iterations
+ * from x = 0 on b (device, n doubles); its r.r history and x must match
+ * the default shape's run within tau (relative per entry of the history,
+ * relative to max |x| for x; opts->tau, 0 -> 1e-10) or it is discarded
+ * before it is timed (median of opts->reps solves after opts->warmup).
+ * The winner is filed under "cg:" + the SpMV class key of A (spk_class_key)
+ * and used by later spk_cg calls on that class.  On matrices whose CG
+ * trajectories separate quickly in rounding (an isolated extreme
+ * eigenvalue) keep iters small.  Synchronises the handle's internal
+ * stream; opts may be NULL. */
+spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters, const spk_tune_opts *opts,
+                       spk_tune_report *report);
 
 /* ------------------------------------------------------------- batching -- */
 

@@ -86,8 +86,9 @@ inline int batch_wave_entries(const BatchEntry &e) { return e.tile / (e.block / 
 
 // Device scalars of one solve: r.r of the current iteration alternates
 // between sc[0] and sc[1] (the slot of iteration k is k & 1), so a kernel
-// can read one while its first workgroup writes the other.
-constexpr int kCgScalars = 2;
+// can read one while its first workgroup writes the other; sc[kCgAlpha]
+// carries alpha from the residual kernel to the direction kernel.
+constexpr int kCgAlpha = 2, kCgScalars = 3;
 constexpr int kCgVecBlock = 256, kCgVecUnroll = 2;
 constexpr int64_t kCgVecPer = (int64_t)kCgVecBlock * 2 * kCgVecUnroll;   // elements per workgroup pass
 
@@ -98,7 +99,7 @@ struct CgLaunch {
     const uint32_t *blocks;    // wavefront tiles: nblk + 1 packed starts
     const int32_t *block_k;    // first entry of each tile
     int32_t nblk;
-    int32_t spmv_grid;         // workgroups of the SpMV kernel (slots of part1)
+    int32_t spmv_grid;         // workgroups of the SpMV kernel = tile groups (slots of part1)
     const double *spmv_x;      // operand of the product (p, or x at the start)
     const double *b;
     double *x, *r, *p, *q;     // x, r, p, q 16-byte aligned
@@ -119,7 +120,7 @@ struct CgEntry {
 
 const CgEntry *cg_table(int *count);
 hipError_t launch_cg_start(const CgLaunch &c, hipStream_t s);
-hipError_t launch_cg_update(const CgLaunch &c, hipStream_t s);
+hipError_t launch_cg_residual(const CgLaunch &c, hipStream_t s);
 hipError_t launch_cg_direction(const CgLaunch &c, hipStream_t s);
 hipError_t launch_cg_record(const CgLaunch &c, hipStream_t s);
 hipError_t launch_cg_zero(double *hist, int64_t count, hipStream_t s);

@@ -100,9 +100,12 @@ __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs<T> a)
         for (int tile = c0; tile < c1; ++tile) run_wave_tile<T, BS, TILE>(a, tile, my_sp, my_srp);
     }
     // Every wavefront has drawn past the end of its queue before it counts
-    // itself done, so the last one may reset all counters.
+    // itself done, so the last one may reset all counters.  Only atomics
+    // are involved, and each one this wavefront issued has returned its
+    // value (it decided the exit) before the done count is incremented, so
+    // no fence is needed; a device-scope release here would write back the
+    // XCD's L2 once per wavefront, serialised per XCD.
     if (l == 0) {
-        __threadfence();
         const uint32_t d = atomicAdd(a.done, 1u);
         if (d == gridDim.x * (uint32_t)WT::NW - 1u) {
             for (int k = 0; k < kXcds; ++k) atomicExch(a.next + k * kCtrStride, 0u);

@@ -9,10 +9,12 @@
 //   k_cg_spmv_dot   q = A p on the wavefront tiles of the matrix; each
 //                   workgroup also leaves its part of p.q (the own-row entry
 //                   of p is already loaded for the tile).
-//   k_cg_update     alpha = r.r / p.q from those parts, then x += alpha p,
-//                   r -= alpha q and this workgroup's part of the new r.r.
-//   k_cg_direction  beta = r'.r' / r.r from those parts, p = r + beta p; the
-//                   first workgroup records r'.r'.
+//   k_cg_residual   alpha = r.r / p.q from those parts, r -= alpha q and
+//                   this workgroup's part of the new r.r.
+//   k_cg_direction  beta = r'.r' / r.r from those parts, then x += alpha p
+//                   and p = r + beta p in one pass over p (x's update waits
+//                   for this pass so that p is read once); the first
+//                   workgroup records r'.r'.
 //
 // A reduction is finished by the kernel that consumes it: every workgroup
 // of the consumer adds the producer's partials in the same fixed order, so
@@ -42,8 +44,10 @@ __device__ __forceinline__ double sum_partials(const double *part, int64_t n, do
 
 }  // namespace
 
-// q = A p over wavefront tiles.  Workgroup slot s (XCD-contiguous) runs the
-// tile groups [s*G/grid, (s+1)*G/grid), wavefront w tile w of each group.
+// q = A p over wavefront tiles: wavefront w of workgroup b runs tile w of
+// tile group xcd_remap(b) (each XCD sweeps a contiguous range of groups, so
+// the groups in flight on an XCD share their x entries in its L2), and the
+// workgroup leaves its part of p.q at that group's index.
 template <int BS, int E>
 __global__ __launch_bounds__(BS) void k_cg_spmv_dot(CgLaunch c)
 {
@@ -52,77 +56,77 @@ __global__ __launch_bounds__(BS) void k_cg_spmv_dot(CgLaunch c)
     __shared__ int srp[NW * (kWaveTileRows + 1)];
     __shared__ double red[NW];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int ngroups = (c.nblk + NW - 1) / NW;
-    const int slot = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int g0 = (int)((int64_t)ngroups * slot / gridDim.x);
-    const int g1 = (int)((int64_t)ngroups * (slot + 1) / gridDim.x);
+    const int g = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int bl = g * NW + wv;
     const double *p = c.spmv_x;
     double d = 0.0;
-    for (int g = g0; g < g1; ++g) {
-        const int bl = g * NW + wv;
-        if (bl >= c.nblk) break;
+    if (bl < c.nblk) {
         const uint32_t e0 = c.blocks[bl], e1 = c.blocks[bl + 1];
         const int r0 = (int)(e0 & kBlkRowMask), r1 = (int)(e1 & kBlkRowMask);
         if ((e0 >> 30) == kBlkStream)
-            d += wave_stream<double, E / kWave, true>(c.rp, c.ci, c.val, p, c.q, nullptr, 0.0, r0, r1,
-                                                      c.block_k[bl], c.block_k[bl + 1], sp + wv * E,
-                                                      srp + wv * (kWaveTileRows + 1));
+            d = wave_stream<double, E / kWave, true>(c.rp, c.ci, c.val, p, c.q, nullptr, 0.0, r0, r1,
+                                                     c.block_k[bl], c.block_k[bl + 1], sp + wv * E,
+                                                     srp + wv * (kWaveTileRows + 1));
         else
-            d += wave_rows_mlp<double, 8, true>(c.rp, c.ci, c.val, p, c.q, nullptr, 0.0, r0, r1);
+            d = wave_rows_mlp<double, 8, true>(c.rp, c.ci, c.val, p, c.q, nullptr, 0.0, r0, r1);
     }
     if (!c.part1) return;   // same for the whole grid
     d = block_sum<BS>(d, red);
-    if (threadIdx.x == 0) c.part1[slot] = d;
+    if (threadIdx.x == 0) c.part1[g] = d;
 }
 
-// alpha = rr / p.q, x += alpha p, r -= alpha q, part2 = this workgroup's
-// r.r.  Two doubles per lane access, UNR accesses in flight.
+// alpha = rr / p.q, r -= alpha q, part2 = this workgroup's r.r; the first
+// workgroup stores alpha for the direction kernel.  Two doubles per lane
+// access, UNR accesses in flight; the first chunk's loads are issued before
+// p.q is assembled.
 template <int BS, int UNR>
-__global__ __launch_bounds__(BS) void k_cg_update(CgLaunch c)
+__global__ __launch_bounds__(BS) void k_cg_residual(CgLaunch c)
 {
     constexpr int64_t PER = (int64_t)BS * 2 * UNR;
     __shared__ double red[BS / kWave];
+    const int t = threadIdx.x;
+    const int64_t n = c.n;
+    const int64_t stride = (int64_t)gridDim.x * PER;
+    int64_t base = (int64_t)blockIdx.x * PER;
+    f64x2_t rv[UNR], qv[UNR];
+    auto load = [&](int64_t at) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int64_t i = at + ((int64_t)u * BS + t) * 2;
+            rv[u] = *(const f64x2_t *)(c.r + i);
+            qv[u] = __builtin_nontemporal_load((const f64x2_t *)(c.q + i));
+        }
+    };
+    bool full = base + PER <= n;
+    if (full) load(base);
     const double pq = sum_partials<BS>(c.part1, c.spmv_grid, red);
     const double rr = c.sc[c.slot];
     const double alpha = pq != 0.0 ? rr / pq : 0.0;
-    const int t = threadIdx.x;
-    const int64_t n = c.n;
+    if (blockIdx.x == 0 && t == 0) c.sc[kCgAlpha] = alpha;
     double acc[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) acc[u] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * PER;
-    for (int64_t base = (int64_t)blockIdx.x * PER; base < n; base += stride) {
-        if (base + PER <= n) {
-            f64x2_t xv[UNR], rv[UNR], pv[UNR], qv[UNR];
+    for (; base < n; base += stride) {
+        if (full) {
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 const int64_t i = base + ((int64_t)u * BS + t) * 2;
-                xv[u] = __builtin_nontemporal_load((const f64x2_t *)(c.x + i));
-                rv[u] = *(const f64x2_t *)(c.r + i);
-                pv[u] = *(const f64x2_t *)(c.p + i);
-                qv[u] = __builtin_nontemporal_load((const f64x2_t *)(c.q + i));
-            }
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int64_t i = base + ((int64_t)u * BS + t) * 2;
-                f64x2_t xn, rn;
-                xn[0] = fma_t(alpha, pv[u][0], xv[u][0]);
-                xn[1] = fma_t(alpha, pv[u][1], xv[u][1]);
+                f64x2_t rn;
                 rn[0] = fma_t(-alpha, qv[u][0], rv[u][0]);
                 rn[1] = fma_t(-alpha, qv[u][1], rv[u][1]);
                 acc[u] = fma_t(rn[0], rn[0], acc[u]);
                 acc[u] = fma_t(rn[1], rn[1], acc[u]);
-                __builtin_nontemporal_store(xn, (f64x2_t *)(c.x + i));
                 *(f64x2_t *)(c.r + i) = rn;
             }
         } else {
             for (int64_t i = base + t; i < n && i < base + PER; i += BS) {
-                c.x[i] = fma_t(alpha, c.p[i], c.x[i]);
                 const double rn = fma_t(-alpha, c.q[i], c.r[i]);
                 c.r[i] = rn;
                 acc[0] = fma_t(rn, rn, acc[0]);
             }
         }
+        full = base + stride + PER <= n;
+        if (full) load(base + stride);
     }
     double s = acc[0];
 #pragma unroll
@@ -131,43 +135,60 @@ __global__ __launch_bounds__(BS) void k_cg_update(CgLaunch c)
     if (t == 0) c.part2[blockIdx.x] = s;
 }
 
-// beta = rr' / rr with rr' the sum of part2, p = r + beta p; the first
-// workgroup records rr' (hist, and the other scalar slot).
+// beta = rr' / rr with rr' the sum of part2, then x += alpha p and
+// p = r + beta p (both from the same p); the first workgroup records rr'
+// (hist, and the other scalar slot).
 template <int BS, int UNR>
 __global__ __launch_bounds__(BS) void k_cg_direction(CgLaunch c)
 {
     constexpr int64_t PER = (int64_t)BS * 2 * UNR;
     __shared__ double red[BS / kWave];
+    const int t = threadIdx.x;
+    const int64_t n = c.n;
+    const int64_t stride = (int64_t)gridDim.x * PER;
+    int64_t base = (int64_t)blockIdx.x * PER;
+    f64x2_t xv[UNR], rv[UNR], pv[UNR];
+    auto load = [&](int64_t at) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int64_t i = at + ((int64_t)u * BS + t) * 2;
+            xv[u] = __builtin_nontemporal_load((const f64x2_t *)(c.x + i));
+            rv[u] = __builtin_nontemporal_load((const f64x2_t *)(c.r + i));
+            pv[u] = *(const f64x2_t *)(c.p + i);
+        }
+    };
+    bool full = base + PER <= n;
+    if (full) load(base);
     const double rr_new = sum_partials<BS>(c.part2, c.grid, red);
     const double rr = c.sc[c.slot];
     const double beta = rr != 0.0 ? rr_new / rr : 0.0;
-    const int t = threadIdx.x;
+    const double alpha = c.sc[kCgAlpha];
     if (blockIdx.x == 0 && t == 0) {
         c.sc[c.slot ^ 1] = rr_new;
         *c.hist = rr_new;
     }
-    const int64_t n = c.n;
-    const int64_t stride = (int64_t)gridDim.x * PER;
-    for (int64_t base = (int64_t)blockIdx.x * PER; base < n; base += stride) {
-        if (base + PER <= n) {
-            f64x2_t rv[UNR], pv[UNR];
+    for (; base < n; base += stride) {
+        if (full) {
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 const int64_t i = base + ((int64_t)u * BS + t) * 2;
-                rv[u] = __builtin_nontemporal_load((const f64x2_t *)(c.r + i));
-                pv[u] = *(const f64x2_t *)(c.p + i);
-            }
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int64_t i = base + ((int64_t)u * BS + t) * 2;
-                f64x2_t pn;
+                f64x2_t xn, pn;
+                xn[0] = fma_t(alpha, pv[u][0], xv[u][0]);
+                xn[1] = fma_t(alpha, pv[u][1], xv[u][1]);
                 pn[0] = fma_t(beta, pv[u][0], rv[u][0]);
                 pn[1] = fma_t(beta, pv[u][1], rv[u][1]);
+                __builtin_nontemporal_store(xn, (f64x2_t *)(c.x + i));
                 *(f64x2_t *)(c.p + i) = pn;
             }
         } else {
-            for (int64_t i = base + t; i < n && i < base + PER; i += BS) c.p[i] = fma_t(beta, c.p[i], c.r[i]);
+            for (int64_t i = base + t; i < n && i < base + PER; i += BS) {
+                const double pi = c.p[i];
+                c.x[i] = fma_t(alpha, pi, c.x[i]);
+                c.p[i] = fma_t(beta, pi, c.r[i]);
+            }
         }
+        full = base + stride + PER <= n;
+        if (full) load(base + stride);
     }
 }
 
@@ -242,9 +263,10 @@ hipError_t launch_cg_start(const CgLaunch &c, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_cg_update(const CgLaunch &c, hipStream_t s)
+hipError_t launch_cg_residual(const CgLaunch &c, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_cg_update<kCgVecBlock, kCgVecUnroll>), dim3((unsigned)c.grid), dim3(kCgVecBlock), 0, s, c);
+    hipLaunchKernelGGL((k_cg_residual<kCgVecBlock, kCgVecUnroll>), dim3((unsigned)c.grid), dim3(kCgVecBlock), 0, s,
+                       c);
     return hipGetLastError();
 }
 

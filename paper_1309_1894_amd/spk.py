@@ -112,6 +112,7 @@ _SIGS = {
     "spk_spmv_mat": (_S, [_P, _P, _P, _P, _P]),
     "spk_spmv_waxpy": (_S, [_P, _P, _D, _P, _P, _P, _P]),
     "spk_cg": (_S, [_P, _P, _P, _P, _I32, _P, _P]),
+    "spk_cg_tune": (_S, [_P, _P, _P, _I32, C.POINTER(spk_tune_opts), C.POINTER(spk_tune_report)]),
     "spk_run": (_S, [_P, C.POINTER(spk_problem), C.POINTER(spk_variant), _P]),
     "spk_variant_count": (_S, [_I32, _I32, C.POINTER(_I32)]),
     "spk_variant_get": (_S, [_I32, _I32, _I32, C.POINTER(spk_variant)]),
@@ -363,6 +364,18 @@ def spk_cg(A: Matrix, b, x, iters: int, hist=None, stream=None):
     _ok(_lib.spk_cg(A.handle.ptr, A.ptr, _dev(b, "b"), _dev(x, "x"), int(iters), _dev(hist, "hist"),
                     _stream(stream)), "spk_cg")
     return hist
+
+
+def spk_cg_tune(A: Matrix, b, iters: int, *, reps=10, warmup=2, tau=0.0, max_variants=0, record=True,
+                verbose=False) -> "spk_tune_report":
+    """Tunes the SpMV tile shape of spk_cg on A (validated against the
+    default shape's solve), recording the winner for A's class."""
+    o = spk_tune_opts()
+    o.reps, o.warmup, o.tau, o.max_variants = reps, warmup, tau, max_variants
+    o.record, o.verbose = int(record), int(verbose)
+    rep = spk_tune_report()
+    _ok(_lib.spk_cg_tune(A.handle.ptr, A.ptr, _dev(b, "b"), int(iters), C.byref(o), C.byref(rep)), "spk_cg_tune")
+    return rep
 
 
 # ------------------------------------------------------ variants, tuning --

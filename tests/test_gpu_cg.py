@@ -74,14 +74,14 @@ def test_cg_matches_oracle(spk, dev, name):
 
 def test_cg_every_tile_shape(spk, dev):
     """Each compiled (threads, entries per wavefront) shape, selected by the
-    plan recorded for the matrix's class."""
+    CG plan recorded for the matrix's class."""
     A = I.spd_zipf(2500, seed_struct=36, seed_val=37)
     b, x0 = _vecs(A, 8)
     xo, ho = O.cg(A, b, 8, x0)
     H = spk.Handle()
     try:
         M = spk.Matrix(A, handle=H)
-        key = spk.spk_class_key(spk.problem(spk.SPK_OP_SPMV, A=M), handle=H)
+        key = "cg:" + spk.spk_class_key(spk.problem(spk.SPK_OP_SPMV, A=M), handle=H)
         for bs in (128, 256, 512):
             for e in (256, 512, 1024):
                 say("cg tile shape", bs, e)
@@ -89,6 +89,34 @@ def test_cg_every_tile_shape(spk, dev):
                 spk.spk_plan_put(key, v, handle=H)
                 x, hist = _run(spk, M, b, x0, 8, dev)
                 _compare(x, hist, xo, ho)
+        M.release()
+    finally:
+        H.close()
+
+
+def test_cg_tune_records_a_validated_shape(spk, dev):
+    """spk_cg_tune times every shape that reproduces the default shape's
+    solve and files the winner under the CG class key; the tuned solve
+    still matches the oracle."""
+    A = I.lap3d(24)
+    b, x0 = _vecs(A, 13)
+    H = spk.Handle()
+    try:
+        M = spk.Matrix(A, handle=H)
+        bd = torch.from_numpy(b).to(dev)
+        say("cg tune lap3d 24")
+        rep = spk.spk_cg_tune(M, bd, 10, reps=3, warmup=1)
+        assert rep.tried == 9 and rep.rejected == 0
+        assert rep.best.format == spk.SPK_FMT_ADAPTIVE and rep.best_us > 0 and rep.plain_us > 0
+        key = "cg:" + spk.spk_class_key(spk.problem(spk.SPK_OP_SPMV, A=M), handle=H)
+        assert rep.class_key.decode() == key
+        got = spk.spk_plan_get(key, handle=H)
+        assert got is not None and (got.block, got.lds) == (rep.best.block, rep.best.lds)
+        xd = torch.from_numpy(x0).to(dev)
+        hist = spk.spk_cg(M, bd, xd, 30)
+        torch.cuda.synchronize()
+        xo, ho = O.cg(A, b, 30, x0)
+        _compare(xd.cpu().numpy(), hist.cpu().numpy(), xo, ho)
         M.release()
     finally:
         H.close()
