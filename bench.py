@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true", help="headline only")
+    ap.add_argument("--extras", default="all",
+                    help="comma list of extra legs (vector_sweep, spmv_large, krylov_step_lap2d, "
+                         "cg_lap3d_128, serving) or 'all'")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-instance baseline")
     ap.add_argument("--verbose", action="store_true", help="print every tuning candidate")
@@ -50,8 +53,15 @@ def parse():
     return ap.parse_args()
 
 
+EXTRA_LEGS = ("vector_sweep", "spmv_large", "krylov_step_lap2d", "cg_lap3d_128", "serving")
+
+
 def main():
     args = parse()
+    if args.extras != "all":
+        bad = [e for e in args.extras.split(",") if e.strip() and e.strip() not in EXTRA_LEGS]
+        if bad:
+            sys.exit(f"unknown extra leg(s) {bad}; known: {', '.join(EXTRA_LEGS)}")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -140,11 +150,14 @@ def main():
 
     if not args.no_extras:
         del d_y, d_w
-        out["vector_sweep"] = vector_sweep(spk, torch, I, dev)
-        out["spmv_large"] = spmv_large(spk, torch, I, dev)
-        out["krylov_step_lap2d"] = lap2d_step(spk, torch, I, dev)
-        out["cg_lap3d_128"] = cg_lap3d(spk, torch, I, dev)
-        out["serving"] = serving(spk, I, args.serve_requests)
+        legs = {"vector_sweep": lambda: vector_sweep(spk, torch, I, dev),
+                "spmv_large": lambda: spmv_large(spk, torch, I, dev),
+                "krylov_step_lap2d": lambda: lap2d_step(spk, torch, I, dev),
+                "cg_lap3d_128": lambda: cg_lap3d(spk, torch, I, dev),
+                "serving": lambda: serving(spk, I, args.serve_requests)}
+        want = list(legs) if args.extras == "all" else [e.strip() for e in args.extras.split(",") if e.strip()]
+        for name in want:
+            out[name] = legs[name]()
 
     cpu = None
     if not args.no_cpu:
