@@ -89,7 +89,7 @@ inline int batch_wave_entries(const BatchEntry &e) { return e.tile / (e.block / 
 // can read one while its first workgroup writes the other; sc[kCgAlpha]
 // carries alpha from the residual kernel to the direction kernel.
 constexpr int kCgAlpha = 2, kCgScalars = 3;
-constexpr int kCgVecBlock = 256, kCgVecUnroll = 2;
+constexpr int kCgVecBlock = 256, kCgVecUnroll = 4;
 constexpr int64_t kCgVecPer = (int64_t)kCgVecBlock * 2 * kCgVecUnroll;   // elements per workgroup pass
 
 struct CgLaunch {
