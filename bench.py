@@ -316,29 +316,54 @@ def spmv_large(spk, torch, I, dev):
         x = I.uniform(seed, 0, A.ncols)
         xd = torch.from_numpy(x).to(dev)
         y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+        # CSR formats only: the CSR byte count is the one these GB/s use
         rep = spk.spk_tune(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), reps=10, warmup=2, flush=True,
-                           record=True)
+                           record=True, formats=spk.CSR_FORMATS)
         nbytes = A.nnz * 12 + 4 * (A.nrows + 1) + 8 * A.ncols + 8 * A.nrows
         res[name] = {"tuned_gbs": round(nbytes / (rep.best_us * 1e-6) / 1e9, 1),
                      "plain_gbs": round(nbytes / (rep.plain_us * 1e-6) / 1e9, 1),
                      "tuned_us": round(rep.best_us, 2), "plain_us": round(rep.plain_us, 2),
                      "best": rep.best.as_dict(), "variants_timed": rep.tried, "pruned": rep.pruned,
                      "rejected": rep.rejected, "bytes": nbytes}
+        res[name]["structured"] = structured_spmv(spk, M, xd, y, rep.best_us)
         res[name]["best_us_per_format"] = per_format(spk, torch, M, xd, y)
         log(f"spmv {name}: {res[name]}")
         M.release()
     return res
 
 
+def structured_spmv(spk, M, xd, y, csr_tuned_us, op=None, w=None):
+    """The tuner restricted to the structured formats (DIA, matrix-free
+    stencil) when the matrix admits one; GB/s on that format's own
+    algorithmic bytes (fewer than CSR's), speed-up on time vs the tuned CSR
+    form.  Not recorded as the class plan."""
+    mask = M.formats() & ((1 << spk.SPK_FMT_DIA) | (1 << spk.SPK_FMT_STENCIL))
+    if not mask:
+        return None
+    op = spk.SPK_OP_SPMV if op is None else op
+    fused = op == spk.SPK_OP_SPMV_WAXPY
+    p = spk.problem(op, A=M, x=xd, y=y, w=w, alpha=0.5 if fused else 0.0)
+    rep = spk.spk_tune(p, reps=10, warmup=2, flush=not fused, record=False, formats=mask)
+    own = M.format_bytes(rep.best.format, fused)
+    names = {spk.SPK_FMT_DIA: "dia", spk.SPK_FMT_STENCIL: "stencil"}
+    return {"format": names[rep.best.format], "block": rep.best.block, "us": round(rep.best_us, 2),
+            "bytes": own, "gbs_own_bytes": round(own / (rep.best_us * 1e-6) / 1e9, 1),
+            "speedup_vs_csr_tuned": round(csr_tuned_us / rep.best_us, 2), "variants_timed": rep.tried}
+
+
 def per_format(spk, torch, M, xd, y, reps=5):
     """Best cold-cache time (us) of every compiled variant, per storage
     format (the tuner's search, reported format by format)."""
     names = {spk.SPK_FMT_SCALAR: "csr_scalar", spk.SPK_FMT_VECTOR: "csr_vector", spk.SPK_FMT_SELL: "sliced_ell",
-             spk.SPK_FMT_ADAPTIVE: "csr_lds_tiles"}
+             spk.SPK_FMT_ADAPTIVE: "csr_lds_tiles", spk.SPK_FMT_DIA: "dia", spk.SPK_FMT_STENCIL: "stencil"}
     stream = torch.cuda.current_stream()
     best = {}
     p = spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y)
-    for v in spk.variants(spk.SPK_OP_SPMV, M.dtype_code):
+    space = list(spk.variants(spk.SPK_OP_SPMV, M.dtype_code))
+    for fmt in (spk.SPK_FMT_DIA, spk.SPK_FMT_STENCIL):
+        if M.formats() & (1 << fmt):
+            space += [spk.make_variant(format=fmt, block=bs, group=1, unroll=1, streams=1) for bs in (128, 256, 512)]
+    for v in space:
         # the tuner's byte model: sliced ELL only when padding at most doubles the entries
         if v.format == spk.SPK_FMT_SELL and M.nnz and sell_padding(M, v.group) > 2.0:
             continue
@@ -377,10 +402,12 @@ def lap2d_step(spk, torch, I, dev):
     xd = torch.from_numpy(x).to(dev)
     y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
     w = torch.empty_like(y)
-    rep = spk.spk_tune(spk.problem(spk.SPK_OP_SPMV_WAXPY, A=M, x=xd, y=y, w=w, alpha=0.5), reps=20, warmup=3)
+    rep = spk.spk_tune(spk.problem(spk.SPK_OP_SPMV_WAXPY, A=M, x=xd, y=y, w=w, alpha=0.5), reps=20, warmup=3,
+                       formats=spk.CSR_FORMATS)
+    st = structured_spmv(spk, M, xd, y, rep.best_us, spk.SPK_OP_SPMV_WAXPY, w)
     M.release()
     return {"tuned_us": round(rep.best_us, 2), "plain_us": round(rep.plain_us, 2), "best": rep.best.as_dict(),
-            "variants_timed": rep.tried, "rejected": rep.rejected}
+            "variants_timed": rep.tried, "rejected": rep.rejected, "structured": st}
 
 
 def cg_lap3d(spk, torch, I, dev, iters=100):
@@ -392,7 +419,8 @@ def cg_lap3d(spk, torch, I, dev, iters=100):
     `iters` - solve of 0) / iters; bytes per iteration are the algorithmic
     traffic of the fused schedule: the matrix (12 nnz + 4 (n+1)), p read and
     q written by the SpMV (16 n), r and q read and r written (24 n), x, r, p
-    read and x, p written (40 n)."""
+    read and x, p written (40 n).  The matrix-free stencil form of the same
+    solve is reported separately (96 n bytes per iteration: no matrix)."""
     import numpy as np
     A = I.lap3d(128)
     n, nnz = A.nrows, A.nnz
@@ -400,8 +428,8 @@ def cg_lap3d(spk, torch, I, dev, iters=100):
     b = torch.from_numpy(I.uniform(61, 0, n)).to(dev)
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     hist = torch.empty(iters + 1, dtype=torch.float64, device=dev)
-    # Section 2's search over the SpMV tile shape of the solve (not timed)
-    tune = spk.spk_cg_tune(M, b, 10, reps=5, warmup=1)
+    # Section 2's search over the CSR tile shape of the solve (not timed)
+    tune = spk.spk_cg_tune(M, b, 10, reps=5, warmup=1, formats=1 << spk.SPK_FMT_ADAPTIVE)
 
     def solve(k):
         x.zero_()
@@ -449,6 +477,19 @@ def cg_lap3d(spk, torch, I, dev, iters=100):
     unfused(5)
     unfused_us, rr_unfused = min(unfused(50) for _ in range(2))
     fused_bytes = 12 * nnz + 4 * (n + 1) + 80 * n
+
+    # the matrix-free SpMV+dot (the matrix is a 7-point stencil): the tuner
+    # restricted to it, then the same timing; the matrix bytes drop out
+    st = None
+    if M.formats() & (1 << spk.SPK_FMT_STENCIL):
+        st_tune = spk.spk_cg_tune(M, b, 10, reps=5, warmup=1, formats=1 << spk.SPK_FMT_STENCIL)
+        solve(10)
+        st_us = (min(solve(iters) for _ in range(3)) - min(solve(0) for _ in range(3))) / iters
+        st_bytes = 96 * n
+        st = {"us_per_iter": round(st_us, 2), "bytes_per_iter": st_bytes,
+              "gbs_own_bytes": round(st_bytes / (st_us * 1e-6) / 1e9, 1),
+              "speedup_vs_csr_tiles": round(fused_us / st_us, 2), "block": st_tune.best.block,
+              "rr_ratio_end": float(hist.cpu().numpy()[-1] / hist.cpu().numpy()[0])}
     res = {"rows": n, "nnz": nnz, "iters": iters,
            "fused_us_per_iter": round(fused_us, 2), "unfused_us_per_iter": round(unfused_us, 2),
            "speedup": round(unfused_us / fused_us, 2),
@@ -458,7 +499,8 @@ def cg_lap3d(spk, torch, I, dev, iters=100):
            "rr_ratio_end": float(rr[-1] / rr[0]),
            "tuned_shape": {"block": tune.best.block, "entries": tune.best.lds},
            "tune_10_iters_us": {"tuned": round(tune.best_us, 1), "default_shape": round(tune.plain_us, 1),
-                                "shapes_timed": tune.tried, "rejected": tune.rejected}}
+                                "shapes_timed": tune.tried, "rejected": tune.rejected},
+           "matrix_free_stencil": st}
     log(f"cg lap3d_128: {res}")
     M.release()
     return res

@@ -78,7 +78,16 @@ typedef enum {
     SPK_FMT_SCALAR = 1,     /* CSR, one lane per row */
     SPK_FMT_VECTOR = 2,     /* CSR, `group` lanes per row (64 = one wavefront) */
     SPK_FMT_SELL = 3,       /* sliced ELL, `group` rows per slice, column-major slices */
-    SPK_FMT_ADAPTIVE = 4    /* CSR wavefront tiles staged through LDS (`lds` entries per wavefront) */
+    SPK_FMT_ADAPTIVE = 4,   /* CSR wavefront tiles staged through LDS (`lds` entries per wavefront) */
+    /* Structured formats (registered matrices whose structure qualifies,
+     * see spk_matrix_formats; not listed by spk_variant_get, searched by
+     * spk_tune when they apply).  They store less than CSR, so their
+     * algorithmic bytes differ from the CSR count (spk_matrix_format_bytes). */
+    SPK_FMT_DIA = 5,        /* diagonal storage: at most 16 diagonals, one value per
+                             * (diagonal, row) plus a 16-bit presence mask per row */
+    SPK_FMT_STENCIL = 6     /* matrix-free: a constant-coefficient 3-, 5- or 7-point
+                             * stencil on a 1-, 2- or 3-D grid with Dirichlet
+                             * truncation (only the coefficients are stored) */
 } spk_format;
 
 typedef void *spk_stream;                 /* hipStream_t */
@@ -197,6 +206,39 @@ spk_status spk_matrix_release(spk_handle h, spk_matrix A);
  * formats built so far). */
 spk_status spk_matrix_bytes(spk_handle h, spk_matrix A, int64_t *bytes);
 
+/* Formats that apply to A, as a bitmask of (1 << spk_format): SCALAR,
+ * VECTOR, SELL and ADAPTIVE always; DIA when every stored entry lies on at
+ * most 16 diagonals with no duplicate (row, column); STENCIL when A is
+ * exactly a constant-coefficient grid stencil: offsets {0, +-1} (1-D),
+ * {0, +-1, +-s} (2-D, s | n) or {0, +-1, +-s, +-t} (3-D, s | t, t | n),
+ * every neighbour inside the grid present, none outside, and one value per
+ * offset.  The structure is detected at registration (section 3 of the
+ * paper lists the storage format among the choices a tuner makes). */
+spk_status spk_matrix_formats(spk_handle h, spk_matrix A, uint32_t *mask);
+
+/* The structure spk_matrix_register detects, computed from host arrays
+ * alone (no GPU, no handle): `formats` as spk_matrix_formats reports it,
+ * the diagonal offsets when DIA applies, and the grid and coefficients
+ * (ascending offset order -N2*N3, -N3, -1, 0, +1, +N3, +N2*N3; absent
+ * slots 0) when STENCIL applies.  row_ptr, col_idx and val of `csr` are
+ * host pointers here. */
+typedef struct {
+    uint32_t formats;
+    int32_t ndiag;
+    int32_t offsets[16];
+    int32_t dim;             /* 0 (no stencil), 1, 2 or 3 */
+    int32_t n1, n2, n3;      /* grid, slowest to fastest axis */
+    double coef[7];
+} spk_structure;
+
+spk_status spk_csr_structure(const spk_csr *csr, spk_structure *out);
+
+/* Algorithmic bytes of one SpMV (fused: + the w stream) of A in `format`
+ * (SCALAR/VECTOR/ADAPTIVE: the CSR count; SELL: the CSR count; DIA:
+ * ndiag*m values + 2m mask bytes; STENCIL: none for the matrix) plus x and
+ * y.  SPK_ERR_ARG when the format does not apply to A. */
+spk_status spk_matrix_format_bytes(spk_handle h, spk_matrix A, int32_t format, int32_t fused, int64_t *bytes);
+
 /* y = A*x on a registered matrix, with the tuned variant of its shape class
  * (or the default when none is recorded). */
 spk_status spk_spmv_mat(spk_handle h, spk_matrix A, const void *x, void *y, spk_stream stream);
@@ -219,8 +261,10 @@ spk_status spk_spmv_waxpy(spk_handle h, spk_matrix A, double alpha, const void *
  * kernels Section 1 sets out to specialize.  Each iteration is three
  * launches with the scalars kept on the device (no host round trip): the
  * SpMV fused with p.q, the residual update fused with r.r, and the x and
- * direction updates in one pass over p.  The SpMV tile shape is the one
- * spk_cg_tune recorded for A's class, else a default.
+ * direction updates in one pass over p.  The SpMV+dot kernel is the one
+ * spk_cg_tune recorded for A's class (a CSR wavefront-tile shape, or the
+ * matrix-free form when A is a constant-coefficient grid stencil), else a
+ * default tile shape.
  *   b        device, n doubles (right-hand side), read only
  *   x        device, n doubles, 8-byte aligned: initial guess on entry, the
  *            iterate after `iters` iterations on return
@@ -278,6 +322,8 @@ typedef struct {
                               * NULL = computed on the device */
     int32_t record;          /* 1: store the winner in the handle's plan DB */
     int32_t verbose;         /* 1: print one line per variant to stderr */
+    uint32_t formats;        /* SpMV: bitmask (1 << spk_format) of the formats to
+                              * search; 0 = every format that applies to A */
 } spk_tune_opts;
 
 typedef struct {
@@ -306,12 +352,15 @@ spk_status spk_class_key(spk_handle h, const spk_problem *problem, char *out, in
 spk_status spk_plan_get(spk_handle h, const char *class_key, spk_variant *out);
 spk_status spk_plan_put(spk_handle h, const char *class_key, const spk_variant *v);
 
-/* Section 2's search applied to the solve.  The one knob is the
- * wavefront-tile shape of the SpMV+dot kernel (threads per workgroup and
- * row-stream entries per wavefront, reported as an SPK_FMT_ADAPTIVE variant
- * with `block` and `lds`): it sets the number of partial sums every
- * workgroup of the residual kernel adds, so the solve's best shape can
- * differ from a lone SpMV's.  Every compiled shape runs `iters` iterations
+/* Section 2's search applied to the solve.  The knob is the SpMV+dot
+ * kernel: a CSR wavefront-tile shape (threads per workgroup and row-stream
+ * entries per wavefront, reported as an SPK_FMT_ADAPTIVE variant with
+ * `block` and `lds`), which sets the number of partial sums every workgroup
+ * of the residual kernel adds, so the solve's best shape can differ from a
+ * lone SpMV's; or, when A is a grid stencil (spk_matrix_formats), the
+ * matrix-free kernel (SPK_FMT_STENCIL, `block` threads).  opts->formats
+ * limits the search (bits 1 << SPK_FMT_ADAPTIVE, 1 << SPK_FMT_STENCIL; 0 =
+ * all that apply).  Every candidate runs `iters` iterations
  * from x = 0 on b (device, n doubles); its r.r history and x must match
  * the default shape's run within tau (relative per entry of the history,
  * relative to max |x| for x; opts->tau, 0 -> 1e-10) or it is discarded

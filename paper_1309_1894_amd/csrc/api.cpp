@@ -85,6 +85,12 @@ spk_status check_variant(int op, int dtype, const spk_variant &v)
         return SPK_OK;
     }
     if (op == SPK_OP_SPMV || op == SPK_OP_SPMV_WAXPY) {
+        if (v.format == SPK_FMT_DIA || v.format == SPK_FMT_STENCIL) {
+            if (!find_struct_entry(v.format, v.block))
+                return fail(SPK_ERR_NOT_FOUND, "no compiled structured SpMV variant format=%d block=%d", v.format,
+                            v.block);
+            return SPK_OK;
+        }
         if (!find_spmv_entry(v))
             return fail(SPK_ERR_NOT_FOUND, "no compiled SpMV variant format=%d block=%d group=%d unroll=%d lds=%d",
                         v.format, v.block, v.group, v.unroll, v.lds);
@@ -184,8 +190,10 @@ std::string class_key(const spk_problem &p, const spk_csr *csr)
         const double mean = std::max(1.0, A->mean_len);
         const double ratio = (double)std::max<int64_t>(1, A->max_len) / mean;
         const int skew = ratio <= 2.0 ? 0 : ratio <= 16.0 ? 1 : 2;
-        snprintf(buf, sizeof buf, "%s:%s:m%d:l%d:s%d", nm, dtype_name(A->dtype),
-                 ilog2_ceil((double)std::max<int64_t>(1, A->nrows)), (int)std::lround(std::log2(mean)), skew);
+        // matrices that admit a structured format form classes of their own
+        const char *tag = A->st.stencil ? ":st" : A->st.dia ? ":dia" : "";
+        snprintf(buf, sizeof buf, "%s:%s:m%d:l%d:s%d%s", nm, dtype_name(A->dtype),
+                 ilog2_ceil((double)std::max<int64_t>(1, A->nrows)), (int)std::lround(std::log2(mean)), skew, tag);
         return buf;
     }
     const double mean = csr && csr->nrows > 0 ? std::max(1.0, (double)csr->nnz / (double)csr->nrows) : 1.0;
@@ -308,6 +316,7 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
     const int64_t m = p.mat ? p.mat->nrows : p.csr->nrows;
     const int dtype = p.mat ? p.mat->dtype : p.csr->dtype;
     if (m == 0) return SPK_OK;
+    if (v.format == SPK_FMT_DIA || v.format == SPK_FMT_STENCIL) return run_structured(h, p, v, s);
     const SpmvEntry *e = find_spmv_entry(v);
     if (!e) return fail(SPK_ERR_NOT_FOUND, "SpMV variant not compiled");
     if (!p.mat && (v.format == SPK_FMT_SELL || v.format == SPK_FMT_ADAPTIVE))
@@ -655,6 +664,8 @@ static void free_mat(spk_mat *A)
         (void)hipFree(kv.second.blk);
         (void)hipFree(kv.second.bk);
     }
+    if (A->dia.val) (void)hipFree(A->dia.val);
+    if (A->dia.mask) (void)hipFree(A->dia.mask);
     delete A;
 }
 
@@ -800,7 +811,9 @@ spk_status spk_spmv_csr(spk_handle h, const spk_csr *A, const void *x, void *y, 
     p.dtype = A->dtype;
     spk_variant v;
     SPK_TRY(resolve(h, p, A, &v));
-    if (v.format == SPK_FMT_SELL || v.format == SPK_FMT_ADAPTIVE) v = default_variant(h, p, A);
+    if (v.format == SPK_FMT_SELL || v.format == SPK_FMT_ADAPTIVE || v.format == SPK_FMT_DIA ||
+        v.format == SPK_FMT_STENCIL)
+        v = default_variant(h, p, A);
     SpmvProblem q;
     q.csr = A;
     q.x = x;
@@ -864,6 +877,19 @@ spk_status spk_matrix_register(spk_handle h, const spk_csr *A, int32_t where, in
         if (e != hipSuccess) return cleanup(hip_fail(e, "column check"));
         if (hbad) return cleanup(fail(SPK_ERR_CSR, "%llu column indices outside [0, %lld)", hbad, (long long)M->ncols));
     }
+    // structured formats (DIA, stencil) need the entries on the host once
+    if (M->nnz > 0) {
+        if (where == 0) {
+            detect_structure(M, A->col_idx, A->val);
+        } else {
+            std::vector<int32_t> ci_h((size_t)M->nnz);
+            std::vector<char> val_h((size_t)M->nnz * vs);
+            e = hipMemcpy(ci_h.data(), M->ci, sizeof(int32_t) * M->nnz, hipMemcpyDeviceToHost);
+            if (e == hipSuccess) e = hipMemcpy(val_h.data(), M->val, vs * M->nnz, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return cleanup(hip_fail(e, "structure detection copy"));
+            detect_structure(M, ci_h.data(), val_h.data());
+        }
+    }
     int64_t mx = 0;
     for (int64_t i = 0; i < M->nrows; ++i) mx = std::max<int64_t>(mx, M->rp_host[i + 1] - M->rp_host[i]);
     M->max_len = mx;
@@ -922,6 +948,8 @@ static spk_status spmv_mat_common(spk_handle h, spk_matrix A, bool fused, double
         SPK_TRY(check_variant(p.op, A->dtype, v));
     } else {
         SPK_TRY(resolve(h, p, nullptr, &v));
+        // a plan filed by hand may name a structured format A lacks
+        if (!format_applies(A, v.format)) v = default_variant(h, p, nullptr);
     }
     SpmvProblem q;
     q.mat = A;

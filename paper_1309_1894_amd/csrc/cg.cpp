@@ -7,12 +7,13 @@
 // scalars stay on the device, so nothing waits for the host and the whole
 // sequence can be captured into a graph by the caller.
 //
-// The one tunable is the wavefront-tile shape of the SpMV+dot kernel
-// (threads per workgroup, entries per wavefront): it sets the tile count,
-// hence the number of partials every workgroup of the residual kernel adds
-// up, so the best shape for the solve need not be the best for a lone SpMV.
-// spk_cg_tune applies Section 2's search to it and files the winner under
-// "cg:" + the matrix's SpMV class key.
+// The tunable is the SpMV+dot kernel: the wavefront-tile shape of the CSR
+// form (threads per workgroup, entries per wavefront), which sets the tile
+// count, hence the number of partials every workgroup of the residual
+// kernel adds up, so the best shape for the solve need not be the best for
+// a lone SpMV; or, for a matrix that is a constant-coefficient grid
+// stencil, the matrix-free form.  spk_cg_tune applies Section 2's search to
+// it and files the winner under "cg:" + the matrix's SpMV class key.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -29,13 +30,19 @@ namespace {
 constexpr int kCgDefaultBlock = 512;
 constexpr int kCgDefaultEntries = 512;
 
-const CgEntry *find_cg_entry(int block, int entries)
+const CgEntry *find_cg_entry(int format, int block, int entries)
 {
     int n = 0;
     const CgEntry *t = cg_table(&n);
     for (int i = 0; i < n; ++i)
-        if (t[i].block == block && t[i].entries == entries) return &t[i];
+        if (t[i].format == format && t[i].block == block && (format == SPK_FMT_STENCIL || t[i].entries == entries))
+            return &t[i];
     return nullptr;
+}
+
+const CgEntry *default_cg_entry()
+{
+    return find_cg_entry(SPK_FMT_ADAPTIVE, kCgDefaultBlock, kCgDefaultEntries);
 }
 
 std::string cg_key(spk_mat *A)
@@ -47,19 +54,19 @@ std::string cg_key(spk_mat *A)
     return "cg:" + class_key(p, nullptr);
 }
 
-// The tile shape recorded for A's class, else the default shape.
+// The SpMV+dot kernel recorded for A's class, else the default tile shape.
 const CgEntry *cg_entry_for(spk_handle h, spk_mat *A)
 {
     if (!h->plain) {
         const std::string key = cg_key(A);
         std::lock_guard<std::mutex> lk(h->mu);
         auto it = h->plans.find(key);
-        if (it != h->plans.end() && it->second.format == SPK_FMT_ADAPTIVE) {
-            const CgEntry *e = find_cg_entry(it->second.block, it->second.lds);
+        if (it != h->plans.end() && format_applies(A, it->second.format)) {
+            const CgEntry *e = find_cg_entry(it->second.format, it->second.block, it->second.lds);
             if (e) return e;
         }
     }
-    return find_cg_entry(kCgDefaultBlock, kCgDefaultEntries);
+    return default_cg_entry();
 }
 
 spk_status cg_scratch(spk_handle h, hipStream_t s, int64_t n, int64_t nparts, CgScratch **out)
@@ -96,28 +103,40 @@ spk_status run_cg(spk_handle h, spk_mat *A, const CgEntry *e, const double *b, d
                   double *hist, hipStream_t s)
 {
     const int64_t n = A->nrows;
-    BlockData *bd = nullptr;
-    SPK_TRY(get_blocks(h, A, e->entries, &bd));
-    const int nw = e->block / 64;
-    const int64_t ngroups = ((int64_t)bd->nblk + nw - 1) / nw;
     // the vector kernels make one pass with at most 8 workgroups per CU
     // (their partials are re-read by every workgroup of the consuming
-    // kernel); the SpMV runs one workgroup per tile group
+    // kernel); the tile SpMV runs one workgroup per tile group, the stencil
+    // SpMV a grid-stride loop on the same cap
     const int64_t cap = 8ll * h->num_cu;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((n + kCgVecPer - 1) / kCgVecPer, cap));
-    const int64_t spmv_grid = std::max<int64_t>(1, ngroups);
+    CgLaunch c;
+    memset(&c, 0, sizeof c);
+    int64_t spmv_grid = 1;
+    if (e->format == SPK_FMT_STENCIL) {
+        if (!format_applies(A, SPK_FMT_STENCIL)) return fail(SPK_ERR_ARG, "A is not a grid stencil");
+        spmv_grid = std::max<int64_t>(1, std::min<int64_t>((n + e->block - 1) / e->block, cap));
+        c.st.n = (int32_t)n;
+        c.st.N1 = A->st.N1;
+        c.st.N2 = A->st.N2;
+        c.st.N3 = A->st.N3;
+        c.st.dim = A->st.dim;
+        for (int q = 0; q < 7; ++q) c.st.coef[q] = A->st.coef[q];
+    } else {
+        BlockData *bd = nullptr;
+        SPK_TRY(get_blocks(h, A, e->entries, &bd));
+        const int nw = e->block / 64;
+        spmv_grid = std::max<int64_t>(1, ((int64_t)bd->nblk + nw - 1) / nw);
+        c.blocks = bd->blk;
+        c.block_k = bd->bk;
+        c.nblk = bd->nblk;
+    }
     CgScratch *cs = nullptr;
     SPK_TRY(cg_scratch(h, s, n, std::max(spmv_grid, grid), &cs));
 
-    CgLaunch c;
-    memset(&c, 0, sizeof c);
     c.n = n;
     c.rp = A->rp;
     c.ci = A->ci;
     c.val = (const double *)A->val;
-    c.blocks = bd->blk;
-    c.block_k = bd->bk;
-    c.nblk = bd->nblk;
     c.spmv_grid = (int32_t)spmv_grid;
     c.b = b;
     c.r = cs->vec;
@@ -267,7 +286,7 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
 
     // reference: the default shape, from x = 0 (Section 2: the unannotated
     // variant's outputs are what every candidate must reproduce)
-    const CgEntry *ref = find_cg_entry(kCgDefaultBlock, kCgDefaultEntries);
+    const CgEntry *ref = default_cg_entry();
     if (!ref) return fail(SPK_ERR_NOT_FOUND, "no CG SpMV kernel compiled");
     std::vector<double> x_ref(n), h_ref(iters + 1), x_try(n), h_try(iters + 1);
     SPK_TRY(solve(ref, xr.p, hr.p));
@@ -280,8 +299,10 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
     const int limit = limit_opt > 0 ? std::min(limit_opt, count) : count;
     double best_us = 1e300;
     const CgEntry *best = nullptr;
+    const uint32_t formats = opts ? opts->formats : 0u;
     for (int i = 0; i < limit; ++i) {
         const CgEntry *e = &table[i];
+        if (!format_applies(A, e->format) || (formats && !(formats & (1u << e->format)))) continue;
         SPK_TRY(solve(e, xt.p, ht.p));
         SPK_TRY(fetch(xt.p, ht.p, x_try, h_try));
         bool ok = true;
@@ -290,13 +311,17 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
         for (int64_t j = 0; j < n && ok; ++j) ok = std::fabs(x_try[j] - x_ref[j]) <= tau * xmax;
         if (!ok) {
             ++report->rejected;
-            if (verbose) fprintf(stderr, "spk_cg_tune: block %d entries %d rejected\n", e->block, e->entries);
+            if (verbose)
+                fprintf(stderr, "spk_cg_tune: format %d block %d entries %d rejected\n", e->format, e->block,
+                        e->entries);
             continue;
         }
         double us = 0.0;
         SPK_TRY(time_entry(e, &us));
         ++report->tried;
-        if (verbose) fprintf(stderr, "spk_cg_tune: block %d entries %d: %.2f us\n", e->block, e->entries, us);
+        if (verbose)
+            fprintf(stderr, "spk_cg_tune: format %d block %d entries %d: %.2f us\n", e->format, e->block, e->entries,
+                    us);
         if (e == ref) report->plain_us = us;
         if (us < best_us) {
             best_us = us;
@@ -305,7 +330,7 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
     }
     if (!best) return fail(SPK_ERR_VALIDATION, "no tile shape reproduced the reference solve");
     spk_variant v{};
-    v.format = SPK_FMT_ADAPTIVE;
+    v.format = best->format;
     v.block = best->block;
     v.group = 1;
     v.unroll = 1;

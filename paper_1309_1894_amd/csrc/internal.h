@@ -72,6 +72,21 @@ struct BlockData {
     int64_t bytes = 0;
 };
 
+// Structure found at registration (see spk_matrix_formats).
+struct StructInfo {
+    bool dia = false;               // at most kMaxDiag diagonals, no duplicates
+    std::vector<int32_t> off;       // ascending diagonal offsets
+    bool stencil = false;           // constant-coefficient grid stencil
+    int dim = 0, N1 = 1, N2 = 1, N3 = 1;
+    double coef[7] = {0, 0, 0, 0, 0, 0, 0};
+};
+
+struct DiaData {
+    void *val = nullptr;            // T[ndiag*m], diagonal-major
+    uint16_t *mask = nullptr;       // m
+    int64_t bytes = 0;
+};
+
 }  // namespace spk
 
 struct spk_mat {
@@ -87,6 +102,8 @@ struct spk_mat {
     int64_t bytes = 0;
     std::map<int, spk::SellData> sell;                       // by slice height
     std::map<std::pair<int, int>, spk::BlockData> blocks;    // by (0, wavefront entries)
+    spk::StructInfo st;
+    spk::DiaData dia;                                        // built on first use
 };
 
 namespace spk {
@@ -183,6 +200,15 @@ spk_variant plain_variant(int op, int which);
 
 // Shape-class key of a problem (plan DB key).
 std::string class_key(const spk_problem &p, const spk_csr *csr);
+
+// Structured formats (structured.cpp).  detect_structure fills A->st from
+// host copies of the CSR arrays; format_applies tells whether a variant's
+// format can run on A; run_structured runs a DIA or STENCIL variant.
+void detect_structure(spk_mat *A, const int32_t *ci_host, const void *val_host);
+bool format_applies(const spk_mat *A, int format);
+const StructEntry *find_struct_entry(int format, int block);
+spk_status run_structured(spk_handle h, const SpmvProblem &p, const spk_variant &v, hipStream_t s);
+int64_t format_bytes(const spk_mat *A, int format, bool fused);
 
 // Derived formats of a registered matrix (built on first use; synchronous).
 spk_status get_sell(spk_handle h, spk_mat *A, int C, SellData **out);

@@ -62,6 +62,48 @@ struct SpmvEntry {
 
 const SpmvEntry *spmv_table(int *count);
 
+// ------------------------------------------------ structured SpMV formats
+
+constexpr int kMaxDiag = 16;
+
+// Diagonal storage: entry (row i, column i + off[d]) at val[d*m + i], present
+// iff bit d of mask[i] is set.  Offsets ascend, so a row's products are
+// added in ascending column order.
+struct DiaArgs {
+    int32_t m, ncols, ndiag;
+    int32_t off[kMaxDiag];
+    const void *val;           // T[ndiag*m]
+    const uint16_t *mask;      // m
+    const void *x;
+    void *y, *w;               // w: fused step only
+    double alpha;
+};
+
+// Constant-coefficient grid stencil on N1 x N2 x N3 (row r = (i*N2 + j)*N3
+// + k; N1 = N2 = 1 in 1-D, N1 = 1 in 2-D).  coef[] holds the values of the
+// offsets -N2*N3, -N3, -1, 0, +1, +N3, +N2*N3 in that (ascending) order;
+// a neighbour outside the grid is absent.
+struct StencilArgs {
+    int32_t n, N1, N2, N3, dim;
+    double coef[7];
+    const void *x;
+    void *y, *w;
+    double alpha;
+};
+
+using StructFn = hipError_t (*)(const void *args, hipStream_t);
+
+struct StructEntry {
+    int format, block;
+    StructFn fn[2][2];         // [dtype][fused]
+};
+
+const StructEntry *struct_table(int *count);
+
+// val_dia[d*m + i] and mask[i] from CSR (val_dia zeroed by the caller).
+hipError_t launch_csr_to_dia(int dtype, int32_t m, const int32_t *rp, const int32_t *ci, const void *val,
+                             int32_t ndiag, const int32_t *off_host, void *val_dia, uint16_t *mask, hipStream_t s);
+
 // --------------------------------------------------------- batched kernels
 
 using BatchFn = hipError_t (*)(const void *args, dim3 grid, hipStream_t);
@@ -109,12 +151,16 @@ struct CgLaunch {
     double *hist;              // where this launch records r.r
     int32_t slot;              // iteration parity
     int64_t grid;              // workgroups of the vector kernels (slots of part2)
+    StencilArgs st;            // stencil form of the matrix (SpMV+dot of a STENCIL entry)
 };
 
 using CgFn = hipError_t (*)(const CgLaunch &, hipStream_t);
 
+// An SpMV+dot kernel of the solve: SPK_FMT_ADAPTIVE (CSR wavefront tiles of
+// `entries` entries, one workgroup per tile group) or SPK_FMT_STENCIL
+// (matrix-free, grid-stride rows, `entries` unused).
 struct CgEntry {
-    int block, entries;        // threads per workgroup, row-stream entries per wavefront
+    int format, block, entries;
     CgFn spmv_dot;
 };
 

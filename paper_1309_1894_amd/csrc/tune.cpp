@@ -112,15 +112,17 @@ spk_status time_variant(Ctx &c, const spk_variant &v, int warmup, int reps, bool
     return SPK_OK;
 }
 
-void candidate_space(const Ctx &c, std::vector<spk_variant> &out, int *pruned)
+void candidate_space(const Ctx &c, uint32_t formats, std::vector<spk_variant> &out, int *pruned)
 {
     int32_t n = 0;
     spk_variant_count(c.p.op, c.dtype, &n);
+    const bool spmv = c.p.op == SPK_OP_SPMV || c.p.op == SPK_OP_SPMV_WAXPY;
     for (int32_t i = 0; i < n; ++i) {
         spk_variant v{};
         spk_variant_get(c.p.op, c.dtype, i, &v);
-        if (c.p.op == SPK_OP_SPMV || c.p.op == SPK_OP_SPMV_WAXPY) {
+        if (spmv) {
             const spk_mat *A = c.p.A;
+            if (formats && !(formats & (1u << v.format))) continue;
             // byte model: sliced ELL is skipped when padding would more than
             // double the stored entries
             if (v.format == SPK_FMT_SELL && A->nnz > 0 && sell_padded_entries(A, v.group) > 2 * A->nnz) {
@@ -137,6 +139,27 @@ void candidate_space(const Ctx &c, std::vector<spk_variant> &out, int *pruned)
             ++*pruned;
             continue;
         }
+        out.push_back(v);
+    }
+    if (!spmv) return;
+    // structured formats, when the matrix admits them
+    const spk_mat *A = c.p.A;
+    int ns = 0;
+    const StructEntry *st = struct_table(&ns);
+    for (int i = 0; i < ns; ++i) {
+        if (formats && !(formats & (1u << st[i].format))) continue;
+        if (!format_applies(A, st[i].format)) continue;
+        // byte model: DIA is skipped when its stored slots exceed twice the entries
+        if (st[i].format == SPK_FMT_DIA && (int64_t)A->st.off.size() * A->nrows > 2 * A->nnz) {
+            ++*pruned;
+            continue;
+        }
+        spk_variant v{};
+        v.format = st[i].format;
+        v.block = st[i].block;
+        v.group = 1;
+        v.unroll = 1;
+        v.streams = 1;
         out.push_back(v);
     }
 }
@@ -245,7 +268,7 @@ extern "C" spk_status spk_tune(spk_handle h, const spk_problem *problem, const s
     // ----- search
     std::vector<spk_variant> space;
     int pruned = 0;
-    candidate_space(c, space, &pruned);
+    candidate_space(c, o.formats, space, &pruned);
     if (o.max_variants > 0 && (int)space.size() > o.max_variants) space.resize((size_t)o.max_variants);
     const bool flush = o.flush != 0;
     double best = 1e300, plain_best = 1e300;
@@ -279,7 +302,7 @@ extern "C" spk_status spk_tune(spk_handle h, const spk_problem *problem, const s
         return SPK_OK;
     };
     for (const spk_variant &v : space) SPK_TRY(consider(v));
-    if (spmv && tried > 0) {
+    if (spmv && tried > 0 && bestv.format != SPK_FMT_DIA && bestv.format != SPK_FMT_STENCIL) {
         // refinement: the winner split over 2 and 4 streams
         for (int s2 : {2, 4}) {
             spk_variant v = bestv;

@@ -27,6 +27,8 @@ SPK_OK = 0
 SPK_F32, SPK_F64 = 0, 1
 SPK_OP_SPMV, SPK_OP_WAXPY, SPK_OP_AXPY, SPK_OP_DOT, SPK_OP_SPMV_WAXPY = 0, 1, 2, 3, 4
 SPK_FMT_AUTO, SPK_FMT_SCALAR, SPK_FMT_VECTOR, SPK_FMT_SELL, SPK_FMT_ADAPTIVE = 0, 1, 2, 3, 4
+SPK_FMT_DIA, SPK_FMT_STENCIL = 5, 6
+CSR_FORMATS = (1 << SPK_FMT_SCALAR) | (1 << SPK_FMT_VECTOR) | (1 << SPK_FMT_SELL) | (1 << SPK_FMT_ADAPTIVE)
 STATUS = {0: "SPK_OK", 1: "SPK_ERR_NULL", 2: "SPK_ERR_SHAPE", 3: "SPK_ERR_DTYPE", 4: "SPK_ERR_ALIAS",
           5: "SPK_ERR_CSR", 6: "SPK_ERR_OOM", 7: "SPK_ERR_BUDGET", 8: "SPK_ERR_HIP", 9: "SPK_ERR_VALIDATION",
           10: "SPK_ERR_NOT_FOUND", 11: "SPK_ERR_ARG", 12: "SPK_ERR_STATE"}
@@ -59,7 +61,13 @@ class spk_problem(C.Structure):
 
 class spk_tune_opts(C.Structure):
     _fields_ = [("reps", _I32), ("warmup", _I32), ("flush", _I32), ("max_variants", _I32), ("tau", _D),
-                ("ref_host", _P), ("ref_scale", _P), ("record", _I32), ("verbose", _I32)]
+                ("ref_host", _P), ("ref_scale", _P), ("record", _I32), ("verbose", _I32),
+                ("formats", C.c_uint32)]
+
+
+class spk_structure(C.Structure):
+    _fields_ = [("formats", C.c_uint32), ("ndiag", _I32), ("offsets", _I32 * 16), ("dim", _I32), ("n1", _I32),
+                ("n2", _I32), ("n3", _I32), ("coef", _D * 7)]
 
 
 class spk_tune_report(C.Structure):
@@ -109,6 +117,9 @@ _SIGS = {
     "spk_matrix_register": (_S, [_P, C.POINTER(spk_csr), _I32, _I32, C.POINTER(_P)]),
     "spk_matrix_release": (_S, [_P, _P]),
     "spk_matrix_bytes": (_S, [_P, _P, C.POINTER(_I64)]),
+    "spk_matrix_formats": (_S, [_P, _P, C.POINTER(C.c_uint32)]),
+    "spk_matrix_format_bytes": (_S, [_P, _P, _I32, _I32, C.POINTER(_I64)]),
+    "spk_csr_structure": (_S, [C.POINTER(spk_csr), C.POINTER(spk_structure)]),
     "spk_spmv_mat": (_S, [_P, _P, _P, _P, _P]),
     "spk_spmv_waxpy": (_S, [_P, _P, _D, _P, _P, _P, _P]),
     "spk_cg": (_S, [_P, _P, _P, _P, _I32, _P, _P]),
@@ -296,6 +307,20 @@ def spk_spmv_csr(row_ptr, col_idx, val, x, y=None, nrows=None, ncols=None, handl
     return y
 
 
+def spk_csr_structure(csr) -> dict:
+    """Structure detection on a host CSR (numpy arrays; no GPU needed)."""
+    rp = np.ascontiguousarray(csr.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(csr.col_idx, dtype=np.int32)
+    val = np.ascontiguousarray(csr.val)
+    dt = SPK_F64 if val.dtype == np.float64 else SPK_F32
+    A = _csr_struct(csr.nrows, csr.ncols, ci.size, dt, rp.ctypes.data, ci.ctypes.data if ci.size else None,
+                    val.ctypes.data if val.size else None)
+    out = spk_structure()
+    _ok(_lib.spk_csr_structure(C.byref(A), C.byref(out)), "spk_csr_structure")
+    return {"formats": int(out.formats), "offsets": list(out.offsets[:out.ndiag]), "dim": int(out.dim),
+            "grid": (int(out.n1), int(out.n2), int(out.n3)), "coef": list(out.coef)}
+
+
 class Matrix:
     """A registered (library-owned, device-resident) CSR matrix."""
 
@@ -326,6 +351,19 @@ class Matrix:
     def bytes(self) -> int:
         b = _I64()
         _ok(_lib.spk_matrix_bytes(self.handle.ptr, self.ptr, C.byref(b)), "spk_matrix_bytes")
+        return int(b.value)
+
+    def formats(self) -> int:
+        """Bitmask (1 << format) of the SpMV formats that apply to this matrix."""
+        m = C.c_uint32()
+        _ok(_lib.spk_matrix_formats(self.handle.ptr, self.ptr, C.byref(m)), "spk_matrix_formats")
+        return int(m.value)
+
+    def format_bytes(self, fmt: int, fused: bool = False) -> int:
+        """Algorithmic bytes of one SpMV (or fused step) in format ``fmt``."""
+        b = _I64()
+        _ok(_lib.spk_matrix_format_bytes(self.handle.ptr, self.ptr, int(fmt), int(bool(fused)), C.byref(b)),
+            "spk_matrix_format_bytes")
         return int(b.value)
 
     def release(self):
@@ -367,11 +405,13 @@ def spk_cg(A: Matrix, b, x, iters: int, hist=None, stream=None):
 
 
 def spk_cg_tune(A: Matrix, b, iters: int, *, reps=10, warmup=2, tau=0.0, max_variants=0, record=True,
-                verbose=False) -> "spk_tune_report":
-    """Tunes the SpMV tile shape of spk_cg on A (validated against the
-    default shape's solve), recording the winner for A's class."""
+                verbose=False, formats=0) -> "spk_tune_report":
+    """Tunes the SpMV+dot kernel of spk_cg on A (tile shapes, and the
+    matrix-free form for grid stencils), each validated against the default
+    shape's solve; records the winner for A's class."""
     o = spk_tune_opts()
     o.reps, o.warmup, o.tau, o.max_variants = reps, warmup, tau, max_variants
+    o.formats = int(formats)
     o.record, o.verbose = int(record), int(verbose)
     rep = spk_tune_report()
     _ok(_lib.spk_cg_tune(A.handle.ptr, A.ptr, _dev(b, "b"), int(iters), C.byref(o), C.byref(rep)), "spk_cg_tune")
@@ -434,9 +474,10 @@ def make_variant(**kw) -> spk_variant:
 
 
 def spk_tune(p: spk_problem, *, reps=10, warmup=2, flush=False, max_variants=0, tau=0.0, ref=None, ref_scale=None,
-             record=True, verbose=False, handle=None) -> spk_tune_report:
+             record=True, verbose=False, formats=0, handle=None) -> spk_tune_report:
     o = spk_tune_opts()
     o.reps, o.warmup, o.flush, o.max_variants, o.tau = reps, warmup, int(flush), max_variants, tau
+    o.formats = int(formats)
     keep = []
     if ref is not None:
         r = np.ascontiguousarray(ref, dtype=np.float64)

@@ -106,8 +106,12 @@ def test_cg_tune_records_a_validated_shape(spk, dev):
         bd = torch.from_numpy(b).to(dev)
         say("cg tune lap3d 24")
         rep = spk.spk_cg_tune(M, bd, 10, reps=3, warmup=1)
-        assert rep.tried == 9 and rep.rejected == 0
-        assert rep.best.format == spk.SPK_FMT_ADAPTIVE and rep.best_us > 0 and rep.plain_us > 0
+        # nine tile shapes and two matrix-free stencil kernels
+        assert rep.tried == 11 and rep.rejected == 0
+        assert rep.best.format in (spk.SPK_FMT_ADAPTIVE, spk.SPK_FMT_STENCIL)
+        assert rep.best_us > 0 and rep.plain_us > 0
+        tiles = spk.spk_cg_tune(M, bd, 10, reps=2, warmup=1, record=False, formats=1 << spk.SPK_FMT_ADAPTIVE)
+        assert tiles.tried == 9 and tiles.best.format == spk.SPK_FMT_ADAPTIVE
         key = "cg:" + spk.spk_class_key(spk.problem(spk.SPK_OP_SPMV, A=M), handle=H)
         assert rep.class_key.decode() == key
         got = spk.spk_plan_get(key, handle=H)
@@ -118,6 +122,45 @@ def test_cg_tune_records_a_validated_shape(spk, dev):
         xo, ho = O.cg(A, b, 30, x0)
         _compare(xd.cpu().numpy(), hist.cpu().numpy(), xo, ho)
         M.release()
+    finally:
+        H.close()
+
+
+@pytest.mark.parametrize("name", ["lap3d_20", "lap2d_33"])
+def test_cg_matrix_free_stencil(spk, dev, name):
+    """The matrix-free SpMV+dot (a CG plan naming SPK_FMT_STENCIL) against
+    the oracle, both block sizes, and on a matrix that is not a stencil the
+    plan is ignored."""
+    A = I.lap3d(20) if name == "lap3d_20" else I.lap2d(33)
+    iters = 40
+    b, x0 = _vecs(A, 14)
+    xo, ho = O.cg(A, b, iters, x0)
+    H = spk.Handle()
+    try:
+        M = spk.Matrix(A, handle=H)
+        key = "cg:" + spk.spk_class_key(spk.problem(spk.SPK_OP_SPMV, A=M), handle=H)
+        for bs in (256, 512):
+            say("cg stencil", name, bs)
+            spk.spk_plan_put(key, spk.make_variant(format=spk.SPK_FMT_STENCIL, block=bs, group=1, unroll=1,
+                                                   streams=1), handle=H)
+            bd = torch.from_numpy(b).to(dev)
+            xd = torch.from_numpy(x0).to(dev)
+            hist = spk.spk_cg(M, bd, xd, iters)
+            torch.cuda.synchronize()
+            _compare(xd.cpu().numpy(), hist.cpu().numpy(), xo, ho)
+        M.release()
+        Z = I.spd_zipf(500, seed_struct=38, seed_val=39)
+        Mz = spk.Matrix(Z, handle=H)
+        kz = "cg:" + spk.spk_class_key(spk.problem(spk.SPK_OP_SPMV, A=Mz), handle=H)
+        spk.spk_plan_put(kz, spk.make_variant(format=spk.SPK_FMT_STENCIL, block=256, group=1, unroll=1, streams=1),
+                         handle=H)
+        bz, xz = _vecs(Z, 15)
+        xd = torch.from_numpy(xz).to(dev)
+        hist = spk.spk_cg(Mz, torch.from_numpy(bz).to(dev), xd, 6)
+        torch.cuda.synchronize()
+        xo, ho = O.cg(Z, bz, 6, xz)
+        _compare(xd.cpu().numpy(), hist.cpu().numpy(), xo, ho)
+        Mz.release()
     finally:
         H.close()
 
