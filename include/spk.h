@@ -84,10 +84,12 @@ typedef enum {
      * spk_tune when they apply).  They store less than CSR, so their
      * algorithmic bytes differ from the CSR count (spk_matrix_format_bytes). */
     SPK_FMT_DIA = 5,        /* diagonal storage: at most 16 diagonals, one value per
-                             * (diagonal, row) plus a 16-bit presence mask per row */
+                             * (diagonal, row) plus a 16-bit presence mask per row;
+                             * `block` threads, `unroll` rows per lane (1, 2) */
     SPK_FMT_STENCIL = 6     /* matrix-free: a constant-coefficient 3-, 5- or 7-point
                              * stencil on a 1-, 2- or 3-D grid with Dirichlet
-                             * truncation (only the coefficients are stored) */
+                             * truncation (only the coefficients are stored);
+                             * `block` threads, `unroll` rows per lane (1..8) */
 } spk_format;
 
 typedef void *spk_stream;                 /* hipStream_t */
@@ -358,7 +360,8 @@ spk_status spk_plan_put(spk_handle h, const char *class_key, const spk_variant *
  * `block` and `lds`), which sets the number of partial sums every workgroup
  * of the residual kernel adds, so the solve's best shape can differ from a
  * lone SpMV's; or, when A is a grid stencil (spk_matrix_formats), the
- * matrix-free kernel (SPK_FMT_STENCIL, `block` threads).  opts->formats
+ * matrix-free kernel (SPK_FMT_STENCIL, `block` threads, `unroll` rows per
+ * lane).  opts->formats
  * limits the search (bits 1 << SPK_FMT_ADAPTIVE, 1 << SPK_FMT_STENCIL; 0 =
  * all that apply).  Every candidate runs `iters` iterations
  * from x = 0 on b (device, n doubles); its r.r history and x must match
@@ -494,8 +497,9 @@ spk_status spk_serve_destroy(spk_server s);
 spk_status spk_stream_probe(spk_handle h, int32_t kind, int64_t n, const double *a, const double *b,
                             double *c, spk_stream stream);
 
-/* Writes a library-owned 512 MiB buffer so the next kernel starts with a
- * cold last-level cache. */
+/* Reads a library-owned 512 MiB buffer (twice the last-level cache) so the
+ * next kernel starts with cold caches holding only clean lines: it pays for
+ * its own misses and not for writing back someone else's dirty lines. */
 spk_status spk_flush_cache(spk_handle h, spk_stream stream);
 
 #ifdef __cplusplus

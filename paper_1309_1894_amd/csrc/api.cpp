@@ -86,9 +86,9 @@ spk_status check_variant(int op, int dtype, const spk_variant &v)
     }
     if (op == SPK_OP_SPMV || op == SPK_OP_SPMV_WAXPY) {
         if (v.format == SPK_FMT_DIA || v.format == SPK_FMT_STENCIL) {
-            if (!find_struct_entry(v.format, v.block))
-                return fail(SPK_ERR_NOT_FOUND, "no compiled structured SpMV variant format=%d block=%d", v.format,
-                            v.block);
+            if (!find_struct_entry(v.format, v.block, v.unroll))
+                return fail(SPK_ERR_NOT_FOUND, "no compiled structured SpMV variant format=%d block=%d unroll=%d",
+                            v.format, v.block, v.unroll);
             return SPK_OK;
         }
         if (!find_spmv_entry(v))
@@ -1140,12 +1140,14 @@ spk_status spk_flush_cache(spk_handle h, spk_stream stream)
     {
         std::lock_guard<std::mutex> lk(h->mu);
         if (!h->flush_buf) {
+            // 512 MiB to read (twice the last-level cache) + 16 bytes of sink
             h->flush_bytes = 512ll << 20;
-            SPK_HIP(hipMalloc(&h->flush_buf, (size_t)h->flush_bytes));
+            SPK_HIP(hipMalloc(&h->flush_buf, (size_t)h->flush_bytes + 256));
+            SPK_HIP(launch_fill(h->flush_buf, h->flush_bytes + 256, 0x5A5A5A5Au, h->work));
+            SPK_HIP(hipStreamSynchronize(h->work));
         }
     }
-    static std::atomic<uint32_t> pattern{1};
-    SPK_HIP(launch_fill(h->flush_buf, h->flush_bytes, pattern++, (hipStream_t)stream));
+    SPK_HIP(launch_evict(h->flush_buf, h->flush_bytes, (char *)h->flush_buf + h->flush_bytes, (hipStream_t)stream));
     return SPK_OK;
 }
 

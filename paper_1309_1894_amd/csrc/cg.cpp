@@ -35,8 +35,7 @@ const CgEntry *find_cg_entry(int format, int block, int entries)
     int n = 0;
     const CgEntry *t = cg_table(&n);
     for (int i = 0; i < n; ++i)
-        if (t[i].format == format && t[i].block == block && (format == SPK_FMT_STENCIL || t[i].entries == entries))
-            return &t[i];
+        if (t[i].format == format && t[i].block == block && t[i].entries == entries) return &t[i];
     return nullptr;
 }
 
@@ -62,7 +61,8 @@ const CgEntry *cg_entry_for(spk_handle h, spk_mat *A)
         std::lock_guard<std::mutex> lk(h->mu);
         auto it = h->plans.find(key);
         if (it != h->plans.end() && format_applies(A, it->second.format)) {
-            const CgEntry *e = find_cg_entry(it->second.format, it->second.block, it->second.lds);
+            const spk_variant &v = it->second;
+            const CgEntry *e = find_cg_entry(v.format, v.block, v.format == SPK_FMT_STENCIL ? v.unroll : v.lds);
             if (e) return e;
         }
     }
@@ -114,7 +114,8 @@ spk_status run_cg(spk_handle h, spk_mat *A, const CgEntry *e, const double *b, d
     int64_t spmv_grid = 1;
     if (e->format == SPK_FMT_STENCIL) {
         if (!format_applies(A, SPK_FMT_STENCIL)) return fail(SPK_ERR_ARG, "A is not a grid stencil");
-        spmv_grid = std::max<int64_t>(1, std::min<int64_t>((n + e->block - 1) / e->block, cap));
+        const int64_t per = (int64_t)e->block * e->entries;
+        spmv_grid = std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, cap));
         c.st.n = (int32_t)n;
         c.st.N1 = A->st.N1;
         c.st.N2 = A->st.N2;
@@ -333,9 +334,11 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
     v.format = best->format;
     v.block = best->block;
     v.group = 1;
-    v.unroll = 1;
     v.streams = 1;
-    v.lds = best->entries;
+    // tile shapes report their entries per wavefront as `lds`, the
+    // matrix-free kernel its rows per lane as `unroll`
+    v.unroll = best->format == SPK_FMT_STENCIL ? best->entries : 1;
+    v.lds = best->format == SPK_FMT_STENCIL ? 0 : best->entries;
     report->best = v;
     report->best_us = best_us;
     const std::string key = cg_key(A);

@@ -94,7 +94,7 @@ struct StencilArgs {
 using StructFn = hipError_t (*)(const void *args, hipStream_t);
 
 struct StructEntry {
-    int format, block;
+    int format, block, rows;   // rows per lane (a variant's `unroll`)
     StructFn fn[2][2];         // [dtype][fused]
 };
 
@@ -158,7 +158,7 @@ using CgFn = hipError_t (*)(const CgLaunch &, hipStream_t);
 
 // An SpMV+dot kernel of the solve: SPK_FMT_ADAPTIVE (CSR wavefront tiles of
 // `entries` entries, one workgroup per tile group) or SPK_FMT_STENCIL
-// (matrix-free, grid-stride rows, `entries` unused).
+// (matrix-free, grid-stride rows, `entries` rows per lane).
 struct CgEntry {
     int format, block, entries;
     CgFn spmv_dot;
@@ -196,6 +196,10 @@ hipError_t launch_dot_absum(int dtype, int64_t n, const void *x, const void *y, 
 
 // Fills n bytes (n a multiple of 16) with a pattern: evicts caches.
 hipError_t launch_fill(void *p, int64_t n, uint32_t pattern, hipStream_t s);
+
+// Reads n bytes (a multiple of 16) so the caches hold clean lines of p;
+// `sink` (16 bytes) is written only in a case that never occurs.
+hipError_t launch_evict(const void *p, int64_t n, void *sink, hipStream_t s);
 
 // STREAM copy (b = a) and triad (c = a + s*b) on doubles.
 hipError_t launch_copy(int64_t n, const double *a, double *b, hipStream_t s);

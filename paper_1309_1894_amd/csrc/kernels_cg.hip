@@ -24,6 +24,7 @@
 // than the whole SpMV at thousands of workgroups).  A step size whose
 // denominator is exactly zero is taken as zero.
 #include "device_rows.h"
+#include "device_stencil.h"
 #include "kernels.h"
 
 namespace spk {
@@ -75,46 +76,47 @@ __global__ __launch_bounds__(BS) void k_cg_spmv_dot(CgLaunch c)
     if (threadIdx.x == 0) c.part1[g] = d;
 }
 
-// q = A p for a constant-coefficient grid stencil (no matrix arrays), rows
-// in a grid-stride loop; each workgroup leaves its part of p.q.  The
-// neighbours are added in ascending offset order, as in k_spmv_stencil.
-template <int BS, int DIM>
+// q = A p for a constant-coefficient grid stencil (no matrix arrays): a
+// lane takes ROWS rows BS apart per pass of a grid-stride loop, all their
+// loads first (clamped addresses, absent neighbours dropped by a select),
+// neighbours added in ascending offset order as in k_spmv_stencil; each
+// workgroup leaves its part of p.q.  Workgroups are remapped so each XCD
+// sweeps contiguous rows.
+template <int BS, int DIM, int ROWS>
 __global__ __launch_bounds__(BS) void k_cg_stencil_dot(CgLaunch c)
 {
     __shared__ double red[BS / kWave];
     const StencilArgs &a = c.st;
     const double *p = c.spmv_x;
-    const uint32_t N3 = (uint32_t)a.N3, N2 = (uint32_t)a.N2;
-    const int plane = a.N2 * a.N3;
-    const int last = a.n - 1;
-    // all seven loads first (clamped addresses, absent neighbours dropped by
-    // a select); workgroups remapped so each XCD sweeps contiguous rows
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int stride = (int)gridDim.x * BS * ROWS;
     double d = 0.0;
-    for (int r = b * BS + (int)threadIdx.x; r < a.n; r += (int)gridDim.x * BS) {
-        const uint32_t ur = (uint32_t)r;
-        const uint32_t k = ur % N3;
-        const uint32_t pencil = ur / N3;
-        const uint32_t j = DIM >= 2 ? pencil % N2 : 0u;
-        const uint32_t i = DIM >= 3 ? pencil / N2 : 0u;
-        const bool has[7] = {DIM >= 3 && i > 0, DIM >= 2 && j > 0, k > 0, true, k + 1 < N3,
-                             DIM >= 2 && j + 1 < N2, DIM >= 3 && i + 1 < (uint32_t)a.N1};
-        const int at[7] = {max(r - plane, 0), max(r - a.N3, 0), max(r - 1, 0), r,
-                           min(r + 1, last), min(r + a.N3, last), min(r + plane, last)};
-        double pv[7];
+    for (int base = b * BS * ROWS + (int)threadIdx.x; base < a.n; base += stride) {
+        double pv[ROWS][7];
+        bool has[ROWS][7];
 #pragma unroll
-        for (int q = 0; q < 7; ++q)
-            if ((q == 0 || q == 6) ? DIM >= 3 : (q == 1 || q == 5) ? DIM >= 2 : true) pv[q] = p[at[q]];
-        double acc = 0.0;
+        for (int u = 0; u < ROWS; ++u) {
+            int at[7];
+            stencil_row<DIM>(a, min(base + u * BS, a.n - 1), at, has[u]);
 #pragma unroll
-        for (int q = 0; q < 7; ++q) {
-            if ((q == 0 || q == 6) ? DIM >= 3 : (q == 1 || q == 5) ? DIM >= 2 : true) {
-                const double t = fma_t(a.coef[q], pv[q], acc);
-                acc = has[q] ? t : acc;
-            }
+            for (int q = 0; q < 7; ++q)
+                if (stencil_slot<DIM>(q)) pv[u][q] = p[at[q]];
         }
-        __builtin_nontemporal_store(acc, c.q + r);
-        d = fma_t(pv[3], acc, d);
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) {
+            const int r = base + u * BS;
+            if (r >= a.n) break;
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                if (stencil_slot<DIM>(q)) {
+                    const double t = fma_t(a.coef[q], pv[u][q], acc);
+                    acc = has[u][q] ? t : acc;
+                }
+            }
+            __builtin_nontemporal_store(acc, c.q + r);
+            d = fma_t(pv[u][3], acc, d);
+        }
     }
     if (!c.part1) return;   // same for the whole grid
     d = block_sum<BS>(d, red);
@@ -289,16 +291,16 @@ hipError_t L_spmv_dot(const CgLaunch &c, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int BS>
+template <int BS, int ROWS>
 hipError_t L_stencil_dot(const CgLaunch &c, hipStream_t s)
 {
     const dim3 g((unsigned)c.spmv_grid);
     if (c.st.dim == 3)
-        hipLaunchKernelGGL((k_cg_stencil_dot<BS, 3>), g, dim3(BS), 0, s, c);
+        hipLaunchKernelGGL((k_cg_stencil_dot<BS, 3, ROWS>), g, dim3(BS), 0, s, c);
     else if (c.st.dim == 2)
-        hipLaunchKernelGGL((k_cg_stencil_dot<BS, 2>), g, dim3(BS), 0, s, c);
+        hipLaunchKernelGGL((k_cg_stencil_dot<BS, 2, ROWS>), g, dim3(BS), 0, s, c);
     else
-        hipLaunchKernelGGL((k_cg_stencil_dot<BS, 1>), g, dim3(BS), 0, s, c);
+        hipLaunchKernelGGL((k_cg_stencil_dot<BS, 1, ROWS>), g, dim3(BS), 0, s, c);
     return hipGetLastError();
 }
 
@@ -307,7 +309,9 @@ const CgEntry kCg[] = {
     TILES(128, 256), TILES(128, 512), TILES(128, 1024),
     TILES(256, 256), TILES(256, 512), TILES(256, 1024),
     TILES(512, 256), TILES(512, 512), TILES(512, 1024),
-    {6, 256, 0, L_stencil_dot<256>}, {6, 512, 0, L_stencil_dot<512>},
+    // matrix-free: `entries` = rows per lane
+    {6, 256, 1, L_stencil_dot<256, 1>}, {6, 256, 2, L_stencil_dot<256, 2>}, {6, 256, 4, L_stencil_dot<256, 4>},
+    {6, 512, 1, L_stencil_dot<512, 1>}, {6, 512, 2, L_stencil_dot<512, 2>}, {6, 512, 4, L_stencil_dot<512, 4>},
 };
 #undef TILES
 

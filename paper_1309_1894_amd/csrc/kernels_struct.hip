@@ -11,6 +11,7 @@
 // row with sorted columns, and skip absent entries (an absent entry is not
 // a stored zero: 0 * Inf would be NaN).
 #include "device_common.h"
+#include "device_stencil.h"
 #include "kernels.h"
 
 namespace spk {
@@ -18,76 +19,82 @@ namespace spk {
 // Both kernels issue all of a row's loads before any product: an absent
 // entry's load goes to a clamped in-bounds address and its product is
 // dropped by a select (never multiplied by zero, so Inf/NaN in x do not
-// leak), so no load waits behind a branch.  Row blocks are remapped so
-// each XCD walks a contiguous range of rows and neighbouring rows' x
-// entries meet in its L2.
+// leak), so no load waits behind a branch.  A lane takes ROWS rows (BS
+// apart, so every access stays coalesced) to keep enough bytes in flight:
+// with one row per lane the stencil moves only 16 bytes per lane and is
+// latency-bound.  Row blocks are remapped so each XCD walks a contiguous
+// range of rows and neighbouring rows' x entries meet in its L2.
 
-// One lane per row.  The offsets live in the kernel arguments; the loop over
-// the kMaxDiag slots is unrolled so they are indexed statically.
-template <typename T, int BS, bool FUSED>
+template <typename T, int BS, int ROWS, bool FUSED>
 __global__ __launch_bounds__(BS) void k_spmv_dia(DiaArgs a)
 {
-    const int i = xcd_remap((int)blockIdx.x, (int)gridDim.x) * BS + (int)threadIdx.x;
-    if (i >= a.m) return;
+    const int base = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (BS * ROWS) + (int)threadIdx.x;
     const T *val = (const T *)a.val;
     const T *x = (const T *)a.x;
-    const uint32_t msk = a.mask[i];
-    T v[kMaxDiag], xv[kMaxDiag];
+    uint32_t msk[ROWS];
+    T v[ROWS][kMaxDiag], xv[ROWS][kMaxDiag];
 #pragma unroll
-    for (int d = 0; d < kMaxDiag; ++d) {
-        if (d < a.ndiag) {
-            const int c = min(max(i + a.off[d], 0), a.ncols - 1);
-            v[d] = val[(int64_t)d * a.m + i];
-            xv[d] = x[c];
+    for (int u = 0; u < ROWS; ++u) {
+        const int i = min(base + u * BS, a.m - 1);
+        msk[u] = base + u * BS < a.m ? a.mask[i] : 0u;
+#pragma unroll
+        for (int d = 0; d < kMaxDiag; ++d) {
+            if (d < a.ndiag) {
+                const int c = min(max(i + a.off[d], 0), a.ncols - 1);
+                v[u][d] = val[(int64_t)d * a.m + i];
+                xv[u][d] = x[c];
+            }
         }
     }
-    double acc = 0.0;
 #pragma unroll
-    for (int d = 0; d < kMaxDiag; ++d) {
-        if (d < a.ndiag) {
-            const double t = fma_t((double)v[d], (double)xv[d], acc);
-            acc = ((msk >> d) & 1u) ? t : acc;
+    for (int u = 0; u < ROWS; ++u) {
+        const int i = base + u * BS;
+        if (i >= a.m) break;
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < kMaxDiag; ++d) {
+            if (d < a.ndiag) {
+                const double t = fma_t((double)v[u][d], (double)xv[u][d], acc);
+                acc = ((msk[u] >> d) & 1u) ? t : acc;
+            }
         }
+        const T yt = (T)acc;
+        ((T *)a.y)[i] = yt;
+        if constexpr (FUSED) ((T *)a.w)[i] = fma_t((T)a.alpha, yt, x[i]);
     }
-    const T yt = (T)acc;
-    ((T *)a.y)[i] = yt;
-    if constexpr (FUSED) ((T *)a.w)[i] = fma_t((T)a.alpha, yt, x[i]);
 }
 
-// One lane per row of the grid; the neighbours in ascending offset order.
-template <typename T, int BS, int DIM, bool FUSED>
+template <typename T, int BS, int DIM, int ROWS, bool FUSED>
 __global__ __launch_bounds__(BS) void k_spmv_stencil(StencilArgs a)
 {
-    const int r = xcd_remap((int)blockIdx.x, (int)gridDim.x) * BS + (int)threadIdx.x;
-    if (r >= a.n) return;
+    const int base = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (BS * ROWS) + (int)threadIdx.x;
     const T *x = (const T *)a.x;
-    const uint32_t ur = (uint32_t)r;
-    const uint32_t N3 = (uint32_t)a.N3, N2 = (uint32_t)a.N2;
-    const uint32_t k = ur % N3;
-    const uint32_t pencil = ur / N3;
-    const uint32_t j = DIM >= 2 ? pencil % N2 : 0u;
-    const uint32_t i = DIM >= 3 ? pencil / N2 : 0u;
-    const int plane = a.N2 * a.N3;
-    const int last = a.n - 1;
-    const bool has[7] = {DIM >= 3 && i > 0, DIM >= 2 && j > 0, k > 0, true, k + 1 < N3,
-                         DIM >= 2 && j + 1 < N2, DIM >= 3 && i + 1 < (uint32_t)a.N1};
-    const int at[7] = {max(r - plane, 0), max(r - a.N3, 0), max(r - 1, 0), r,
-                       min(r + 1, last), min(r + a.N3, last), min(r + plane, last)};
-    T xv[7];
+    T xv[ROWS][7];
+    bool has[ROWS][7];
 #pragma unroll
-    for (int q = 0; q < 7; ++q)
-        if ((q == 0 || q == 6) ? DIM >= 3 : (q == 1 || q == 5) ? DIM >= 2 : true) xv[q] = x[at[q]];
-    double acc = 0.0;
+    for (int u = 0; u < ROWS; ++u) {
+        int at[7];
+        stencil_row<DIM>(a, min(base + u * BS, a.n - 1), at, has[u]);
 #pragma unroll
-    for (int q = 0; q < 7; ++q) {
-        if ((q == 0 || q == 6) ? DIM >= 3 : (q == 1 || q == 5) ? DIM >= 2 : true) {
-            const double t = fma_t(a.coef[q], (double)xv[q], acc);
-            acc = has[q] ? t : acc;
-        }
+        for (int q = 0; q < 7; ++q)
+            if (stencil_slot<DIM>(q)) xv[u][q] = x[at[q]];
     }
-    const T yt = (T)acc;
-    ((T *)a.y)[r] = yt;
-    if constexpr (FUSED) ((T *)a.w)[r] = fma_t((T)a.alpha, yt, xv[3]);
+#pragma unroll
+    for (int u = 0; u < ROWS; ++u) {
+        const int r = base + u * BS;
+        if (r >= a.n) break;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            if (stencil_slot<DIM>(q)) {
+                const double t = fma_t(a.coef[q], (double)xv[u][q], acc);
+                acc = has[u][q] ? t : acc;
+            }
+        }
+        const T yt = (T)acc;
+        ((T *)a.y)[r] = yt;
+        if constexpr (FUSED) ((T *)a.w)[r] = fma_t((T)a.alpha, yt, xv[u][3]);
+    }
 }
 
 // CSR -> DIA, one lane per row.
@@ -130,35 +137,44 @@ hipError_t launch_csr_to_dia(int dtype, int32_t m, const int32_t *rp, const int3
 
 namespace {
 
-template <typename T, int BS, bool F>
+template <typename T, int BS, int ROWS, bool F>
 hipError_t L_dia(const void *p, hipStream_t s)
 {
     const DiaArgs &a = *(const DiaArgs *)p;
-    hipLaunchKernelGGL((k_spmv_dia<T, BS, F>), dim3((unsigned)((a.m + BS - 1) / BS)), dim3(BS), 0, s, a);
+    const int per = BS * ROWS;
+    hipLaunchKernelGGL((k_spmv_dia<T, BS, ROWS, F>), dim3((unsigned)((a.m + per - 1) / per)), dim3(BS), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int BS, bool F>
+template <typename T, int BS, int ROWS, bool F>
 hipError_t L_stencil(const void *p, hipStream_t s)
 {
     const StencilArgs &a = *(const StencilArgs *)p;
-    const dim3 g((unsigned)((a.n + BS - 1) / BS));
+    const int per = BS * ROWS;
+    const dim3 g((unsigned)((a.n + per - 1) / per));
     if (a.dim == 3)
-        hipLaunchKernelGGL((k_spmv_stencil<T, BS, 3, F>), g, dim3(BS), 0, s, a);
+        hipLaunchKernelGGL((k_spmv_stencil<T, BS, 3, ROWS, F>), g, dim3(BS), 0, s, a);
     else if (a.dim == 2)
-        hipLaunchKernelGGL((k_spmv_stencil<T, BS, 2, F>), g, dim3(BS), 0, s, a);
+        hipLaunchKernelGGL((k_spmv_stencil<T, BS, 2, ROWS, F>), g, dim3(BS), 0, s, a);
     else
-        hipLaunchKernelGGL((k_spmv_stencil<T, BS, 1, F>), g, dim3(BS), 0, s, a);
+        hipLaunchKernelGGL((k_spmv_stencil<T, BS, 1, ROWS, F>), g, dim3(BS), 0, s, a);
     return hipGetLastError();
 }
 
-#define SFN4(L, BS) {{L<float, BS, false>, L<float, BS, true>}, {L<double, BS, false>, L<double, BS, true>}}
+// format, block, rows per lane (the `unroll` knob)
+#define SFN4(L, BS, R) {{L<float, BS, R, false>, L<float, BS, R, true>}, {L<double, BS, R, false>, L<double, BS, R, true>}}
+#define DIA_E(BS, R) {5, BS, R, SFN4(L_dia, BS, R)}
+#define STN_E(BS, R) {6, BS, R, SFN4(L_stencil, BS, R)}
 
 const StructEntry kStruct[] = {
-    {5, 128, SFN4(L_dia, 128)},     {5, 256, SFN4(L_dia, 256)},     {5, 512, SFN4(L_dia, 512)},
-    {6, 128, SFN4(L_stencil, 128)}, {6, 256, SFN4(L_stencil, 256)}, {6, 512, SFN4(L_stencil, 512)},
+    DIA_E(128, 1), DIA_E(128, 2), DIA_E(256, 1), DIA_E(256, 2), DIA_E(512, 1), DIA_E(512, 2),
+    STN_E(128, 1), STN_E(128, 2), STN_E(128, 4), STN_E(128, 8),
+    STN_E(256, 1), STN_E(256, 2), STN_E(256, 4), STN_E(256, 8),
+    STN_E(512, 1), STN_E(512, 2), STN_E(512, 4),
 };
 
+#undef STN_E
+#undef DIA_E
 #undef SFN4
 
 }  // namespace

@@ -161,12 +161,12 @@ bool format_applies(const spk_mat *A, int format)
     return format >= SPK_FMT_SCALAR && format <= SPK_FMT_ADAPTIVE;
 }
 
-const StructEntry *find_struct_entry(int format, int block)
+const StructEntry *find_struct_entry(int format, int block, int rows)
 {
     int n = 0;
     const StructEntry *t = struct_table(&n);
     for (int i = 0; i < n; ++i)
-        if (t[i].format == format && t[i].block == block) return &t[i];
+        if (t[i].format == format && t[i].block == block && t[i].rows == rows) return &t[i];
     return nullptr;
 }
 
@@ -210,8 +210,10 @@ spk_status run_structured(spk_handle h, const SpmvProblem &p, const spk_variant 
     spk_mat *A = p.mat;
     if (!A) return fail(SPK_ERR_ARG, "format %d needs a registered matrix", v.format);
     if (!format_applies(A, v.format)) return fail(SPK_ERR_ARG, "format %d does not apply to this matrix", v.format);
-    const StructEntry *e = find_struct_entry(v.format, v.block);
-    if (!e) return fail(SPK_ERR_NOT_FOUND, "no compiled structured SpMV format=%d block=%d", v.format, v.block);
+    const StructEntry *e = find_struct_entry(v.format, v.block, v.unroll);
+    if (!e)
+        return fail(SPK_ERR_NOT_FOUND, "no compiled structured SpMV format=%d block=%d unroll=%d", v.format, v.block,
+                    v.unroll);
     const StructFn fn = e->fn[A->dtype][p.fused ? 1 : 0];
     if (v.format == SPK_FMT_DIA) {
         DiaData *d = nullptr;

@@ -158,7 +158,7 @@ void candidate_space(const Ctx &c, uint32_t formats, std::vector<spk_variant> &o
         v.format = st[i].format;
         v.block = st[i].block;
         v.group = 1;
-        v.unroll = 1;
+        v.unroll = st[i].rows;
         v.streams = 1;
         out.push_back(v);
     }

@@ -37,8 +37,13 @@ CASES = {
 }
 
 
+# compiled structured variants: (threads, rows per lane)
+SHAPES = {DIA: [(bs, r) for bs in (128, 256, 512) for r in (1, 2)],
+          STENCIL: [(bs, r) for bs in (128, 256) for r in (1, 2, 4, 8)] + [(512, r) for r in (1, 2, 4)]}
+
+
 def _variants(spk, fmt):
-    return [spk.make_variant(format=fmt, block=bs, group=1, unroll=1, streams=1) for bs in (128, 256, 512)]
+    return [spk.make_variant(format=fmt, block=bs, group=1, unroll=r, streams=1) for bs, r in SHAPES[fmt]]
 
 
 def _expect(A, x, dt):
@@ -63,10 +68,10 @@ def test_structured_formats_bit_exact(spk, dev, name, dt):
         wref = O.waxpy(0.5, yref, x)
         for fmt in sorted(fmts):
             for v in _variants(spk, fmt):
-                say(f"structured {name} dt={dt} format={fmt} block={v.block}")
+                say(f"structured {name} dt={dt} format={fmt} block={v.block} rows={v.unroll}")
                 y.fill_(float("nan"))
                 spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), v)
-                assert np.array_equal(y.cpu().numpy(), yref), (fmt, v.block)
+                assert np.array_equal(y.cpu().numpy(), yref), (fmt, v.block, v.unroll)
                 y.fill_(float("nan"))
                 w.fill_(float("nan"))
                 spk.spk_run(spk.problem(spk.SPK_OP_SPMV_WAXPY, A=M, x=xd, y=y, w=w, alpha=0.5), v)
@@ -147,10 +152,11 @@ def test_tuner_searches_structured_formats(spk, dev):
         rep2 = spk.spk_tune(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), reps=3, warmup=1, record=False,
                             formats=spk.CSR_FORMATS, handle=H)
         assert rep2.best.format not in (DIA, STENCIL)
-        # six structured variants more (three DIA, three stencil); the stream
-        # refinement (two more timed runs) follows a CSR winner only
+        # every structured variant more; the stream refinement (two more
+        # timed runs) follows a CSR winner only
+        ns = len(SHAPES[DIA]) + len(SHAPES[STENCIL])
         structured_won = rep.best.format in (DIA, STENCIL)
-        assert rep.tried - rep2.tried == (4 if structured_won else 6)
+        assert rep.tried - rep2.tried == (ns - 2 if structured_won else ns)
         M.release()
     finally:
         H.close()
@@ -166,7 +172,8 @@ def test_full_size_lap3d_128(spk, dev):
         ref, _ = O.spmv(A, x)
         for fmt in (DIA, STENCIL):
             say(f"full-size lap3d 128 format {fmt}")
-            spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), _variants(spk, fmt)[1])
-            assert np.array_equal(y.cpu().numpy(), ref)
+            for v in _variants(spk, fmt):
+                spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), v)
+                assert np.array_equal(y.cpu().numpy(), ref), (fmt, v.block, v.unroll)
     finally:
         M.release()
