@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="headline only")
     ap.add_argument("--extras", default="all",
                     help="comma list of extra legs (vector_sweep, spmv_large, krylov_step_lap2d, "
-                         "cg_lap3d_128, serving) or 'all'")
+                         "cg_lap3d_128, serving, host_simd) or 'all'")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-instance baseline")
     ap.add_argument("--verbose", action="store_true", help="print every tuning candidate")
@@ -53,7 +53,7 @@ def parse():
     return ap.parse_args()
 
 
-EXTRA_LEGS = ("vector_sweep", "spmv_large", "krylov_step_lap2d", "cg_lap3d_128", "serving")
+EXTRA_LEGS = ("vector_sweep", "spmv_large", "krylov_step_lap2d", "cg_lap3d_128", "serving", "host_simd")
 
 
 def main():
@@ -154,7 +154,8 @@ def main():
                 "spmv_large": lambda: spmv_large(spk, torch, I, dev),
                 "krylov_step_lap2d": lambda: lap2d_step(spk, torch, I, dev),
                 "cg_lap3d_128": lambda: cg_lap3d(spk, torch, I, dev),
-                "serving": lambda: serving(spk, I, args.serve_requests)}
+                "serving": lambda: serving(spk, I, args.serve_requests),
+                "host_simd": lambda: host_simd()}
         want = list(legs) if args.extras == "all" else [e.strip() for e in args.extras.split(",") if e.strip()]
         for name in want:
             out[name] = legs[name]()
@@ -504,6 +505,24 @@ def cg_lap3d(spk, torch, I, dev, iters=100):
     log(f"cg lap3d_128: {res}")
     M.release()
     return res
+
+
+def host_simd():
+    """The paper's own experiment (Figure 1) on this machine's host CPU: the
+    annotated vector update expanded into compiler-specific SIMD pragma
+    variants (gcc and clang; SSE4.2, AVX2, AVX-512 as the CPU allows;
+    unroll, restrict), validated against and timed with the pragma-free
+    -O3 baseline, one thread, FP64, a = 1.5."""
+    from paper_1309_1894_amd import host_simd as H
+    t0 = time.time()
+    rep = H.tune(sizes=(10**4, 10**5, 10**6, 10**7), reps=3, target_s=0.005, confirm=5, log=log)
+    rep["seconds"] = round(time.time() - t0, 1)
+    for v in rep["sizes"].values():
+        for k in ("baseline_s", "best_s"):
+            v[k] = float(f"{v[k]:.4g}")
+        for k in ("speedup", "time_saved_pct", "best_gbs", "baseline_gbs"):
+            v[k] = round(v[k], 2)
+    return rep
 
 
 def serving(spk, I, nreq):
