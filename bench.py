@@ -421,7 +421,7 @@ def cg_lap3d(spk, torch, I, dev, iters=100):
     traffic of the fused schedule: the matrix (12 nnz + 4 (n+1)), p read and
     q written by the SpMV (16 n), r and q read and r written (24 n), x, r, p
     read and x, p written (40 n).  The matrix-free stencil form of the same
-    solve is reported separately (96 n bytes per iteration: no matrix)."""
+    solve is reported separately (80 n bytes per iteration: no matrix)."""
     import numpy as np
     A = I.lap3d(128)
     n, nnz = A.nrows, A.nnz
@@ -486,7 +486,7 @@ def cg_lap3d(spk, torch, I, dev, iters=100):
         st_tune = spk.spk_cg_tune(M, b, 10, reps=5, warmup=1, formats=1 << spk.SPK_FMT_STENCIL)
         solve(10)
         st_us = (min(solve(iters) for _ in range(3)) - min(solve(0) for _ in range(3))) / iters
-        st_bytes = 96 * n
+        st_bytes = 80 * n   # p read, q written (16 n) + the residual (24 n) and direction (40 n) passes
         st = {"us_per_iter": round(st_us, 2), "bytes_per_iter": st_bytes,
               "gbs_own_bytes": round(st_bytes / (st_us * 1e-6) / 1e9, 1),
               "speedup_vs_csr_tiles": round(fused_us / st_us, 2), "block": st_tune.best.block,
@@ -617,7 +617,8 @@ def cpu_baseline(B, x, alpha, step_bytes):
 
 # Sources of the batched kernel: the committed counter figures apply only
 # while these are unchanged.
-TILE_KERNEL_SOURCES = ["kernels_batch.hip", "device_rows.h", "device_common.h", "batch_types.h", "kernels.h"]
+# the files whose contents define the batched tile kernel's device code
+TILE_KERNEL_SOURCES = ["kernels_batch.hip", "device_rows.h", "device_common.h", "batch_types.h"]
 
 
 def tile_kernel_hash() -> str:
