@@ -20,23 +20,51 @@ __device__ __forceinline__ void wave_lds_sync()
 
 constexpr int kWaveTileRows = 2 * kWave;   // rows of one wavefront's row stream
 
+typedef int int4v __attribute__((ext_vector_type(4)));
+
 // Products of a wavefront tile's entries, written to its LDS slice
 // (sp[k - k0] for entry k).  Lane l takes entries k0 + l + 64j: coalesced
-// 8-byte value and 4-byte column loads.
+// 8-byte value loads and x gathers in entry order.  The column indices
+// arrive in 16-byte groups instead (a quarter of the load instructions):
+// groups of four aligned on their address, each loaded only when it holds
+// an entry of the tile (so the 16-byte block lies in the same page as a
+// valid entry), staged through the not-yet-used product slice and read back
+// in entry order.
 template <typename T, int ITEMS>
 __device__ __forceinline__ void wave_products(const int32_t *ci, const T *val, const T *x, int k0, int nk, double *sp)
 {
+    constexpr int STEPS = (ITEMS * kWave + 3 + 4 * kWave - 1) / (4 * kWave);
     const int l = threadIdx.x & (kWave - 1);
     T v[ITEMS];
-    int c[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int k = l + j * kWave;
         // matrix entries are read exactly once: non-temporal, so the cache
         // keeps the x entries that neighbouring rows share
         v[j] = k < nk ? __builtin_nontemporal_load(val + k0 + k) : T(0);
-        c[j] = k < nk ? __builtin_nontemporal_load(ci + k0 + k) : -1;
     }
+    const int off = (int)(((uintptr_t)(ci + k0) >> 2) & 3u);   // entries before k0 in the first group
+    const int32_t *cg = ci + k0 - off;
+    int *sci = reinterpret_cast<int *>(sp);                    // 2*64*ITEMS ints of room
+    int4v g[STEPS];
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) {
+        const int e0 = 4 * (l + kWave * s);
+        if (nk > 0 && e0 < off + nk) g[s] = __builtin_nontemporal_load((const int4v *)(cg + e0));
+    }
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) {
+        const int e0 = 4 * (l + kWave * s);
+        if (nk > 0 && e0 < off + nk) *(int4v *)(sci + e0) = g[s];
+    }
+    wave_lds_sync();
+    int c[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int k = l + j * kWave;
+        c[j] = k < nk ? sci[k + off] : -1;
+    }
+    wave_lds_sync();   // the staged indices are read before products overwrite them
     T xv[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) xv[j] = c[j] >= 0 ? x[c[j]] : T(0);
