@@ -396,11 +396,12 @@ typedef struct {
 typedef struct {
     int32_t persistent;      /* launch kind: 1 (default) one persistent launch
                               * pulling tiles from per-XCD queues; 0 one
-                              * workgroup per tile; 2 one workgroup per run of
-                              * 4 tiles, software-pipelined */
+                              * workgroup per group of wavefront tiles; other
+                              * values are rejected (SPK_ERR_ARG) */
     int32_t use_graph;       /* 1 (default): replay a captured hipGraph */
     int32_t block;           /* threads per workgroup (0 -> 256) */
-    int32_t tile_nnz;        /* target entries per tile (0 -> 2048) */
+    int32_t tile_nnz;        /* target entries per tile of the lane-group
+                              * modes (0 -> 1024) */
     int32_t waves_per_cu;    /* persistent residency (0 -> from occupancy) */
 } spk_batch_opts;
 

@@ -257,6 +257,9 @@ spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *d, const spk_batch
     }
     if (o.block == 0) o.block = 256;
     if (o.tile_nnz == 0) o.tile_nnz = 1024;
+    if (o.persistent != kBatchGrid && o.persistent != kBatchPersistent)
+        return fail(SPK_ERR_ARG, "persistent must be 0 or 1 (got %d)", o.persistent);
+    if (o.tile_nnz < 0 || o.waves_per_cu < 0) return fail(SPK_ERR_ARG, "negative tile_nnz or waves_per_cu");
     const BatchEntry *e = batch_entry(o.block, 2048);
     if (!e) return fail(SPK_ERR_ARG, "no batched kernel with block %d", o.block);
 

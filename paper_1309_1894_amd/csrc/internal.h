@@ -238,8 +238,8 @@ const BatchEntry *batch_entry(int block, int tile);
 // k1 and mode; the caller sets the matrix pointers and vector offset.
 void cut_rows(const int32_t *rp, int64_t m, int mode, int entries, int64_t target, std::vector<BatchTile> &out);
 
-// One launch of the tile kernel of launch kind `kind` (kBatchGrid,
-// kBatchPersistent with queue counters `ctr`, or kBatchPipe).
+// One launch of the tile kernel of launch kind `kind` (kBatchGrid, or
+// kBatchPersistent with queue counters `ctr`).
 spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchTile *d_tiles, int64_t ntiles, double alpha,
                         const void *x, void *y, void *w, int kind, uint32_t *ctr, int64_t persistent_grid,
                         hipStream_t s);

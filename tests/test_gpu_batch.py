@@ -139,6 +139,14 @@ def test_batch_spmv_only_and_empty(spk, dev):
     e.free()
 
 
+def test_batch_rejects_bad_options(spk, dev):
+    B = mixed_batch()
+    arrays = _dev_batch(B, dev)
+    for kw in ({"persistent": 2}, {"persistent": -1}, {"block": 96}, {"tile_nnz": -5}):
+        with pytest.raises(spk.SpkError, match="SPK_ERR_ARG"):
+            spk.Batch(B, arrays, **kw)
+
+
 def test_full_batched_workload_sampled(spk, dev):
     """The full 4096-instance batch: sampled instances against the oracle."""
     B = I.batch_banded(4096)
