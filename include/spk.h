@@ -272,7 +272,8 @@ spk_status spk_spmv_waxpy(spk_handle h, spk_matrix A, double alpha, const void *
  *            iterate after `iters` iterations on return
  *   d_rr_hist device, iters + 1 doubles: r_k.r_k for k = 0..iters
  * Asynchronous on `stream`; the solve's working vectors are owned by the
- * handle (one set per stream, grown on demand).  Errors: SPK_ERR_DTYPE for
+ * handle (one set per stream, grown on demand), so solves on one stream run
+ * one after another and must not be issued from several threads at once.  Errors: SPK_ERR_DTYPE for
  * FP32 matrices, SPK_ERR_SHAPE for a non-square matrix or iters < 0,
  * SPK_ERR_ALIAS when x overlaps b or the history. */
 spk_status spk_cg(spk_handle h, spk_matrix A, const void *b, void *x, int32_t iters, double *d_rr_hist,
