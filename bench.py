@@ -347,7 +347,8 @@ def structured_spmv(spk, M, xd, y, csr_tuned_us, op=None, w=None):
     rep = spk.spk_tune(p, reps=10, warmup=2, flush=not fused, record=False, formats=mask)
     own = M.format_bytes(rep.best.format, fused)
     names = {spk.SPK_FMT_DIA: "dia", spk.SPK_FMT_STENCIL: "stencil"}
-    return {"format": names[rep.best.format], "block": rep.best.block, "us": round(rep.best_us, 2),
+    return {"format": names[rep.best.format], "block": rep.best.block, "rows_per_lane": rep.best.unroll,
+            "lds_staged": bool(rep.best.format == spk.SPK_FMT_STENCIL and rep.best.lds), "us": round(rep.best_us, 2),
             "bytes": own, "gbs_own_bytes": round(own / (rep.best_us * 1e-6) / 1e9, 1),
             "speedup_vs_csr_tuned": round(csr_tuned_us / rep.best_us, 2), "variants_timed": rep.tried}
 
@@ -363,7 +364,11 @@ def per_format(spk, torch, M, xd, y, reps=5):
     space = list(spk.variants(spk.SPK_OP_SPMV, M.dtype_code))
     for fmt in (spk.SPK_FMT_DIA, spk.SPK_FMT_STENCIL):
         if M.formats() & (1 << fmt):
-            space += [spk.make_variant(format=fmt, block=bs, group=1, unroll=1, streams=1) for bs in (128, 256, 512)]
+            space += [spk.make_variant(format=fmt, block=bs, group=1, unroll=r, streams=1) for bs in (128, 256, 512)
+                      for r in (1, 2)]
+    if M.formats() & (1 << spk.SPK_FMT_STENCIL):
+        space += [spk.make_variant(format=spk.SPK_FMT_STENCIL, block=bs, group=1, unroll=r, streams=1, lds=1)
+                  for bs in (256, 512) for r in (2, 4)]
     for v in space:
         # the tuner's byte model: sliced ELL only when padding at most doubles the entries
         if v.format == spk.SPK_FMT_SELL and M.nnz and sell_padding(M, v.group) > 2.0:
@@ -379,7 +384,7 @@ def per_format(spk, torch, M, xd, y, reps=5):
             ev.append((a, b))
         torch.cuda.synchronize()
         t = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)[reps // 2]
-        k = names[v.format]
+        k = names[v.format] + ("_lds" if v.format == spk.SPK_FMT_STENCIL and v.lds else "")
         if k not in best or t < best[k]:
             best[k] = round(t, 2)
     return best
@@ -490,6 +495,7 @@ def cg_lap3d(spk, torch, I, dev, iters=100):
         st = {"us_per_iter": round(st_us, 2), "bytes_per_iter": st_bytes,
               "gbs_own_bytes": round(st_bytes / (st_us * 1e-6) / 1e9, 1),
               "speedup_vs_csr_tiles": round(fused_us / st_us, 2), "block": st_tune.best.block,
+              "rows_per_lane": st_tune.best.unroll, "lds_staged": bool(st_tune.best.lds),
               "rr_ratio_end": float(hist.cpu().numpy()[-1] / hist.cpu().numpy()[0])}
     res = {"rows": n, "nnz": nnz, "iters": iters,
            "fused_us_per_iter": round(fused_us, 2), "unfused_us_per_iter": round(unfused_us, 2),

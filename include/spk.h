@@ -89,7 +89,8 @@ typedef enum {
     SPK_FMT_STENCIL = 6     /* matrix-free: a constant-coefficient 3-, 5- or 7-point
                              * stencil on a 1-, 2- or 3-D grid with Dirichlet
                              * truncation (only the coefficients are stored);
-                             * `block` threads, `unroll` rows per lane (1..8) */
+                             * `block` threads, `unroll` rows per lane (1..8),
+                             * `lds` 1 = x staged through LDS */
 } spk_format;
 
 typedef void *spk_stream;                 /* hipStream_t */
@@ -124,7 +125,9 @@ typedef struct {
  *   streams SpMV: split rows over this many streams (1, 2 or 4)
  *   lds     SpMV VECTOR: 1 = stage row_ptr in LDS; ADAPTIVE: LDS row-stream
  *           capacity in entries per wavefront (the "L1 size" knob; gfx950
- *           has no L1/LDS split, so the staged tile size takes its place) */
+ *           has no L1/LDS split, so the staged tile size takes its place);
+ *           STENCIL: 1 = stage each workgroup's x values and one grid line
+ *           of halo in LDS (applies while they fit 64 KiB) */
 typedef struct {
     int32_t format, block, group, unroll, vec, grid, streams, lds;
 } spk_variant;
@@ -362,7 +365,7 @@ spk_status spk_plan_put(spk_handle h, const char *class_key, const spk_variant *
  * of the residual kernel adds, so the solve's best shape can differ from a
  * lone SpMV's; or, when A is a grid stencil (spk_matrix_formats), the
  * matrix-free kernel (SPK_FMT_STENCIL, `block` threads, `unroll` rows per
- * lane).  opts->formats
+ * lane, `lds` 1 = p staged through LDS).  opts->formats
  * limits the search (bits 1 << SPK_FMT_ADAPTIVE, 1 << SPK_FMT_STENCIL; 0 =
  * all that apply).  Every candidate runs `iters` iterations
  * from x = 0 on b (device, n doubles); its r.r history and x must match

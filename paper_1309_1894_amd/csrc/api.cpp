@@ -86,9 +86,10 @@ spk_status check_variant(int op, int dtype, const spk_variant &v)
     }
     if (op == SPK_OP_SPMV || op == SPK_OP_SPMV_WAXPY) {
         if (v.format == SPK_FMT_DIA || v.format == SPK_FMT_STENCIL) {
-            if (!find_struct_entry(v.format, v.block, v.unroll))
-                return fail(SPK_ERR_NOT_FOUND, "no compiled structured SpMV variant format=%d block=%d unroll=%d",
-                            v.format, v.block, v.unroll);
+            if (!find_struct_entry(v.format, v.block, v.unroll, v.lds))
+                return fail(SPK_ERR_NOT_FOUND,
+                            "no compiled structured SpMV variant format=%d block=%d unroll=%d lds=%d", v.format,
+                            v.block, v.unroll, v.lds);
             return SPK_OK;
         }
         if (!find_spmv_entry(v))

@@ -30,18 +30,29 @@ namespace {
 constexpr int kCgDefaultBlock = 512;
 constexpr int kCgDefaultEntries = 512;
 
-const CgEntry *find_cg_entry(int format, int block, int entries)
+const CgEntry *find_cg_entry(int format, int block, int entries, int lds)
 {
     int n = 0;
     const CgEntry *t = cg_table(&n);
     for (int i = 0; i < n; ++i)
-        if (t[i].format == format && t[i].block == block && t[i].entries == entries) return &t[i];
+        if (t[i].format == format && t[i].block == block && t[i].entries == entries && t[i].lds == lds)
+            return &t[i];
     return nullptr;
 }
 
 const CgEntry *default_cg_entry()
 {
-    return find_cg_entry(SPK_FMT_ADAPTIVE, kCgDefaultBlock, kCgDefaultEntries);
+    return find_cg_entry(SPK_FMT_ADAPTIVE, kCgDefaultBlock, kCgDefaultEntries, 0);
+}
+
+// Whether entry e can run on A: its format applies, and an LDS-staged
+// stencil's halo fits the budget.
+bool cg_entry_fits(const spk_mat *A, const CgEntry &e)
+{
+    if (!format_applies(A, e.format)) return false;
+    if (e.format == SPK_FMT_STENCIL && e.lds)
+        return stencil_lds_bytes(e.block, e.entries, A->st.dim, A->st.N3, 8) <= kStencilLdsMaxBytes;
+    return true;
 }
 
 std::string cg_key(spk_mat *A)
@@ -60,10 +71,11 @@ const CgEntry *cg_entry_for(spk_handle h, spk_mat *A)
         const std::string key = cg_key(A);
         std::lock_guard<std::mutex> lk(h->mu);
         auto it = h->plans.find(key);
-        if (it != h->plans.end() && format_applies(A, it->second.format)) {
+        if (it != h->plans.end()) {
             const spk_variant &v = it->second;
-            const CgEntry *e = find_cg_entry(v.format, v.block, v.format == SPK_FMT_STENCIL ? v.unroll : v.lds);
-            if (e) return e;
+            const bool st = v.format == SPK_FMT_STENCIL;
+            const CgEntry *e = find_cg_entry(v.format, v.block, st ? v.unroll : v.lds, st ? v.lds : 0);
+            if (e && cg_entry_fits(A, *e)) return e;
         }
     }
     return default_cg_entry();
@@ -113,7 +125,7 @@ spk_status run_cg(spk_handle h, spk_mat *A, const CgEntry *e, const double *b, d
     memset(&c, 0, sizeof c);
     int64_t spmv_grid = 1;
     if (e->format == SPK_FMT_STENCIL) {
-        if (!format_applies(A, SPK_FMT_STENCIL)) return fail(SPK_ERR_ARG, "A is not a grid stencil");
+        if (!cg_entry_fits(A, *e)) return fail(SPK_ERR_ARG, "A is not a grid stencil this kernel can run");
         const int64_t per = (int64_t)e->block * e->entries;
         spmv_grid = std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, cap));
         c.st.n = (int32_t)n;
@@ -303,7 +315,7 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
     const uint32_t formats = opts ? opts->formats : 0u;
     for (int i = 0; i < limit; ++i) {
         const CgEntry *e = &table[i];
-        if (!format_applies(A, e->format) || (formats && !(formats & (1u << e->format)))) continue;
+        if (!cg_entry_fits(A, *e) || (formats && !(formats & (1u << e->format)))) continue;
         SPK_TRY(solve(e, xt.p, ht.p));
         SPK_TRY(fetch(xt.p, ht.p, x_try, h_try));
         bool ok = true;
@@ -321,8 +333,8 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
         SPK_TRY(time_entry(e, &us));
         ++report->tried;
         if (verbose)
-            fprintf(stderr, "spk_cg_tune: format %d block %d entries %d: %.2f us\n", e->format, e->block, e->entries,
-                    us);
+            fprintf(stderr, "spk_cg_tune: format %d block %d entries %d lds %d: %.2f us\n", e->format, e->block,
+                    e->entries, e->lds, us);
         if (e == ref) report->plain_us = us;
         if (us < best_us) {
             best_us = us;
@@ -338,7 +350,7 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
     // tile shapes report their entries per wavefront as `lds`, the
     // matrix-free kernel its rows per lane as `unroll`
     v.unroll = best->format == SPK_FMT_STENCIL ? best->entries : 1;
-    v.lds = best->format == SPK_FMT_STENCIL ? 0 : best->entries;
+    v.lds = best->format == SPK_FMT_STENCIL ? best->lds : best->entries;
     report->best = v;
     report->best_us = best_us;
     const std::string key = cg_key(A);

@@ -206,7 +206,8 @@ std::string class_key(const spk_problem &p, const spk_csr *csr);
 // format can run on A; run_structured runs a DIA or STENCIL variant.
 void detect_structure(spk_mat *A, const int32_t *ci_host, const void *val_host);
 bool format_applies(const spk_mat *A, int format);
-const StructEntry *find_struct_entry(int format, int block, int rows);
+const StructEntry *find_struct_entry(int format, int block, int rows, int lds);
+bool struct_entry_fits(const spk_mat *A, const StructEntry &e);
 spk_status run_structured(spk_handle h, const SpmvProblem &p, const spk_variant &v, hipStream_t s);
 int64_t format_bytes(const spk_mat *A, int format, bool fused);
 

@@ -95,8 +95,19 @@ using StructFn = hipError_t (*)(const void *args, hipStream_t);
 
 struct StructEntry {
     int format, block, rows;   // rows per lane (a variant's `unroll`)
+    int lds;                   // stencil: 1 = x staged through LDS (a variant's `lds`)
     StructFn fn[2][2];         // [dtype][fused]
 };
+
+// LDS-staged stencil kernels keep a workgroup's rows plus one grid line of
+// halo on each side (block*rows + 2*N3 values, 2 in 1-D) in LDS; they apply
+// while that fits this budget.
+constexpr int64_t kStencilLdsMaxBytes = 64 * 1024;
+inline int64_t stencil_lds_bytes(int block, int rows, int dim, int N3, int elem)
+{
+    const int64_t halo = dim >= 2 ? N3 : 1;
+    return ((int64_t)block * rows + 2 * halo) * elem;
+}
 
 const StructEntry *struct_table(int *count);
 
@@ -161,6 +172,7 @@ using CgFn = hipError_t (*)(const CgLaunch &, hipStream_t);
 // (matrix-free, grid-stride rows, `entries` rows per lane).
 struct CgEntry {
     int format, block, entries;
+    int lds;                   // matrix-free: 1 = p staged through LDS
     CgFn spmv_dot;
 };
 

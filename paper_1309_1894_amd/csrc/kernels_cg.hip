@@ -123,6 +123,80 @@ __global__ __launch_bounds__(BS) void k_cg_stencil_dot(CgLaunch c)
     if (threadIdx.x == 0) c.part1[blockIdx.x] = d;
 }
 
+// The same with p staged through LDS (as k_spmv_stencil_lds): per pass a
+// workgroup copies p of its BS*ROWS rows and one grid line of halo on each
+// side into LDS (dynamic shared memory, stencil_lds_bytes), so only the
+// plane neighbours come from global memory.  Same products, same order.
+template <int BS, int DIM, int ROWS>
+__global__ __launch_bounds__(BS) void k_cg_stencil_lds(CgLaunch c)
+{
+    extern __shared__ double ps[];
+    __shared__ double red[BS / kWave];
+    constexpr int SPAN = BS * ROWS;
+    const StencilArgs &a = c.st;
+    const double *p = c.spmv_x;
+    const int halo = DIM >= 2 ? a.N3 : 1;
+    const int cnt = SPAN + 2 * halo;
+    const int last = a.n - 1;
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int stride = (int)gridDim.x * SPAN;
+    double d = 0.0;
+    for (int R0 = b * SPAN; R0 < a.n; R0 += stride) {
+        const int lo = R0 - halo;
+        __syncthreads();   // the previous pass has finished reading ps
+        for (int t = (int)threadIdx.x; t < cnt; t += BS) {
+            const int g = lo + t;
+            ps[t] = (g >= 0 && g < a.n) ? p[g] : 0.0;
+        }
+        double pp[ROWS][2];
+        bool has[ROWS][7];
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) {
+            int at[7];
+            stencil_row<DIM>(a, min(R0 + u * BS + (int)threadIdx.x, last), at, has[u]);
+            if constexpr (DIM >= 3) {
+                pp[u][0] = p[at[0]];
+                pp[u][1] = p[at[6]];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) {
+            const int r = R0 + u * BS + (int)threadIdx.x;
+            if (r >= a.n) break;
+            const int o = r - lo;
+            double acc = 0.0, t;
+            if constexpr (DIM >= 3) {
+                t = fma_t(a.coef[0], pp[u][0], acc);
+                acc = has[u][0] ? t : acc;
+            }
+            if constexpr (DIM >= 2) {
+                t = fma_t(a.coef[1], ps[o - a.N3], acc);
+                acc = has[u][1] ? t : acc;
+            }
+            t = fma_t(a.coef[2], ps[o - 1], acc);
+            acc = has[u][2] ? t : acc;
+            const double pr = ps[o];
+            acc = fma_t(a.coef[3], pr, acc);
+            t = fma_t(a.coef[4], ps[o + 1], acc);
+            acc = has[u][4] ? t : acc;
+            if constexpr (DIM >= 2) {
+                t = fma_t(a.coef[5], ps[o + a.N3], acc);
+                acc = has[u][5] ? t : acc;
+            }
+            if constexpr (DIM >= 3) {
+                t = fma_t(a.coef[6], pp[u][1], acc);
+                acc = has[u][6] ? t : acc;
+            }
+            __builtin_nontemporal_store(acc, c.q + r);
+            d = fma_t(pr, acc, d);
+        }
+    }
+    if (!c.part1) return;   // same for the whole grid
+    d = block_sum<BS>(d, red);
+    if (threadIdx.x == 0) c.part1[blockIdx.x] = d;
+}
+
 // alpha = rr / p.q, r -= alpha q, part2 = this workgroup's r.r; the first
 // workgroup stores alpha for the direction kernel.  Two doubles per lane
 // access, UNR accesses in flight; the first chunk's loads are issued before
@@ -304,14 +378,31 @@ hipError_t L_stencil_dot(const CgLaunch &c, hipStream_t s)
     return hipGetLastError();
 }
 
-#define TILES(BS, E) {4, BS, E, L_spmv_dot<BS, E>}
+template <int BS, int ROWS>
+hipError_t L_stencil_lds(const CgLaunch &c, hipStream_t s)
+{
+    const dim3 g((unsigned)c.spmv_grid);
+    const size_t sh = (size_t)stencil_lds_bytes(BS, ROWS, c.st.dim, c.st.N3, 8);
+    if (c.st.dim == 3)
+        hipLaunchKernelGGL((k_cg_stencil_lds<BS, 3, ROWS>), g, dim3(BS), sh, s, c);
+    else if (c.st.dim == 2)
+        hipLaunchKernelGGL((k_cg_stencil_lds<BS, 2, ROWS>), g, dim3(BS), sh, s, c);
+    else
+        hipLaunchKernelGGL((k_cg_stencil_lds<BS, 1, ROWS>), g, dim3(BS), sh, s, c);
+    return hipGetLastError();
+}
+
+#define TILES(BS, E) {4, BS, E, 0, L_spmv_dot<BS, E>}
 const CgEntry kCg[] = {
     TILES(128, 256), TILES(128, 512), TILES(128, 1024),
     TILES(256, 256), TILES(256, 512), TILES(256, 1024),
     TILES(512, 256), TILES(512, 512), TILES(512, 1024),
-    // matrix-free: `entries` = rows per lane
-    {6, 256, 1, L_stencil_dot<256, 1>}, {6, 256, 2, L_stencil_dot<256, 2>}, {6, 256, 4, L_stencil_dot<256, 4>},
-    {6, 512, 1, L_stencil_dot<512, 1>}, {6, 512, 2, L_stencil_dot<512, 2>}, {6, 512, 4, L_stencil_dot<512, 4>},
+    // matrix-free: `entries` = rows per lane; lds = p staged through LDS
+    {6, 256, 1, 0, L_stencil_dot<256, 1>}, {6, 256, 2, 0, L_stencil_dot<256, 2>},
+    {6, 256, 4, 0, L_stencil_dot<256, 4>}, {6, 512, 1, 0, L_stencil_dot<512, 1>},
+    {6, 512, 2, 0, L_stencil_dot<512, 2>}, {6, 512, 4, 0, L_stencil_dot<512, 4>},
+    {6, 256, 2, 1, L_stencil_lds<256, 2>}, {6, 256, 4, 1, L_stencil_lds<256, 4>},
+    {6, 512, 2, 1, L_stencil_lds<512, 2>}, {6, 512, 4, 1, L_stencil_lds<512, 4>},
 };
 #undef TILES
 

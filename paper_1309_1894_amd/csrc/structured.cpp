@@ -161,13 +161,19 @@ bool format_applies(const spk_mat *A, int format)
     return format >= SPK_FMT_SCALAR && format <= SPK_FMT_ADAPTIVE;
 }
 
-const StructEntry *find_struct_entry(int format, int block, int rows)
+const StructEntry *find_struct_entry(int format, int block, int rows, int lds)
 {
     int n = 0;
     const StructEntry *t = struct_table(&n);
     for (int i = 0; i < n; ++i)
-        if (t[i].format == format && t[i].block == block && t[i].rows == rows) return &t[i];
+        if (t[i].format == format && t[i].block == block && t[i].rows == rows && t[i].lds == lds) return &t[i];
     return nullptr;
+}
+
+bool struct_entry_fits(const spk_mat *A, const StructEntry &e)
+{
+    if (!e.lds) return true;
+    return stencil_lds_bytes(e.block, e.rows, A->st.dim, A->st.N3, (int)dtype_size(A->dtype)) <= kStencilLdsMaxBytes;
 }
 
 int64_t format_bytes(const spk_mat *A, int format, bool fused)
@@ -210,10 +216,12 @@ spk_status run_structured(spk_handle h, const SpmvProblem &p, const spk_variant 
     spk_mat *A = p.mat;
     if (!A) return fail(SPK_ERR_ARG, "format %d needs a registered matrix", v.format);
     if (!format_applies(A, v.format)) return fail(SPK_ERR_ARG, "format %d does not apply to this matrix", v.format);
-    const StructEntry *e = find_struct_entry(v.format, v.block, v.unroll);
+    const StructEntry *e = find_struct_entry(v.format, v.block, v.unroll, v.lds);
     if (!e)
-        return fail(SPK_ERR_NOT_FOUND, "no compiled structured SpMV format=%d block=%d unroll=%d", v.format, v.block,
-                    v.unroll);
+        return fail(SPK_ERR_NOT_FOUND, "no compiled structured SpMV format=%d block=%d unroll=%d lds=%d", v.format,
+                    v.block, v.unroll, v.lds);
+    if (!struct_entry_fits(A, *e))
+        return fail(SPK_ERR_ARG, "the stencil's grid lines are too long to stage through LDS");
     const StructFn fn = e->fn[A->dtype][p.fused ? 1 : 0];
     if (v.format == SPK_FMT_DIA) {
         DiaData *d = nullptr;

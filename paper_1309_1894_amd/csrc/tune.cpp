@@ -148,7 +148,7 @@ void candidate_space(const Ctx &c, uint32_t formats, std::vector<spk_variant> &o
     const StructEntry *st = struct_table(&ns);
     for (int i = 0; i < ns; ++i) {
         if (formats && !(formats & (1u << st[i].format))) continue;
-        if (!format_applies(A, st[i].format)) continue;
+        if (!format_applies(A, st[i].format) || !struct_entry_fits(A, st[i])) continue;
         // byte model: DIA is skipped when its stored slots exceed twice the entries
         if (st[i].format == SPK_FMT_DIA && (int64_t)A->st.off.size() * A->nrows > 2 * A->nnz) {
             ++*pruned;
@@ -159,6 +159,7 @@ void candidate_space(const Ctx &c, uint32_t formats, std::vector<spk_variant> &o
         v.block = st[i].block;
         v.group = 1;
         v.unroll = st[i].rows;
+        v.lds = st[i].lds;
         v.streams = 1;
         out.push_back(v);
     }

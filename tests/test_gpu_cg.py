@@ -106,8 +106,9 @@ def test_cg_tune_records_a_validated_shape(spk, dev):
         bd = torch.from_numpy(b).to(dev)
         say("cg tune lap3d 24")
         rep = spk.spk_cg_tune(M, bd, 10, reps=3, warmup=1)
-        # nine tile shapes and six matrix-free stencil kernels
-        assert rep.tried == 15 and rep.rejected == 0
+        # nine tile shapes and ten matrix-free stencil kernels (four of them
+        # staging p through LDS)
+        assert rep.tried == 19 and rep.rejected == 0
         assert rep.best.format in (spk.SPK_FMT_ADAPTIVE, spk.SPK_FMT_STENCIL)
         assert rep.best_us > 0 and rep.plain_us > 0
         tiles = spk.spk_cg_tune(M, bd, 10, reps=2, warmup=1, record=False, formats=1 << spk.SPK_FMT_ADAPTIVE)
@@ -139,10 +140,12 @@ def test_cg_matrix_free_stencil(spk, dev, name):
     try:
         M = spk.Matrix(A, handle=H)
         key = "cg:" + spk.spk_class_key(spk.problem(spk.SPK_OP_SPMV, A=M), handle=H)
-        for bs, rows in [(bs, r) for bs in (256, 512) for r in (1, 2, 4)]:
-            say("cg stencil", name, bs, rows)
+        shapes = [(bs, r, 0) for bs in (256, 512) for r in (1, 2, 4)] + [(bs, r, 1) for bs in (256, 512)
+                                                                         for r in (2, 4)]
+        for bs, rows, lds in shapes:
+            say("cg stencil", name, bs, rows, lds)
             spk.spk_plan_put(key, spk.make_variant(format=spk.SPK_FMT_STENCIL, block=bs, group=1, unroll=rows,
-                                                   streams=1), handle=H)
+                                                   streams=1, lds=lds), handle=H)
             bd = torch.from_numpy(b).to(dev)
             xd = torch.from_numpy(x0).to(dev)
             hist = spk.spk_cg(M, bd, xd, iters)

@@ -37,13 +37,14 @@ CASES = {
 }
 
 
-# compiled structured variants: (threads, rows per lane)
-SHAPES = {DIA: [(bs, r) for bs in (128, 256, 512) for r in (1, 2)],
-          STENCIL: [(bs, r) for bs in (128, 256) for r in (1, 2, 4, 8)] + [(512, r) for r in (1, 2, 4)]}
+# compiled structured variants: (threads, rows per lane, x staged in LDS)
+SHAPES = {DIA: [(bs, r, 0) for bs in (128, 256, 512) for r in (1, 2)],
+          STENCIL: [(bs, r, 0) for bs in (128, 256) for r in (1, 2, 4, 8)] + [(512, r, 0) for r in (1, 2, 4)]
+          + [(bs, r, 1) for bs in (256, 512) for r in (2, 4)]}
 
 
 def _variants(spk, fmt):
-    return [spk.make_variant(format=fmt, block=bs, group=1, unroll=r, streams=1) for bs, r in SHAPES[fmt]]
+    return [spk.make_variant(format=fmt, block=bs, group=1, unroll=r, streams=1, lds=l) for bs, r, l in SHAPES[fmt]]
 
 
 def _expect(A, x, dt):
@@ -68,10 +69,10 @@ def test_structured_formats_bit_exact(spk, dev, name, dt):
         wref = O.waxpy(0.5, yref, x)
         for fmt in sorted(fmts):
             for v in _variants(spk, fmt):
-                say(f"structured {name} dt={dt} format={fmt} block={v.block} rows={v.unroll}")
+                say(f"structured {name} dt={dt} format={fmt} block={v.block} rows={v.unroll} lds={v.lds}")
                 y.fill_(float("nan"))
                 spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), v)
-                assert np.array_equal(y.cpu().numpy(), yref), (fmt, v.block, v.unroll)
+                assert np.array_equal(y.cpu().numpy(), yref), (fmt, v.block, v.unroll, v.lds)
                 y.fill_(float("nan"))
                 w.fill_(float("nan"))
                 spk.spk_run(spk.problem(spk.SPK_OP_SPMV_WAXPY, A=M, x=xd, y=y, w=w, alpha=0.5), v)
@@ -117,6 +118,44 @@ def test_format_not_applicable_is_an_error(spk, dev):
                 spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), _variants(spk, fmt)[0])
             with pytest.raises(spk.SpkError, match="SPK_ERR_ARG"):
                 M.format_bytes(fmt)
+    finally:
+        M.release()
+
+
+def test_staged_stencil_needs_short_grid_lines(spk, dev):
+    """A 2-D stencil whose grid lines are too long for the LDS budget
+    (64 KiB: block*rows + 2*N3 values) rejects the staged variants and the
+    tuner leaves them out; the unstaged ones still run."""
+    N = 6000   # 2*6000*8 bytes of halo + the rows exceed 64 KiB
+    rows, cols, vals = [], [], []
+    # a 2-D Laplacian on a 3 x N grid (N3 = N)
+    n = 3 * N
+    r = np.arange(n)
+    k, j = r % N, r // N
+    for off, ok, v in ((-N, j > 0, -1.0), (-1, k > 0, -1.0), (0, np.ones(n, bool), 4.0), (1, k < N - 1, -1.0),
+                       (N, j < 2, -1.0)):
+        rows.append(r[ok]); cols.append(r[ok] + off); vals.append(np.full(ok.sum(), v))
+    rows, cols, vals = (np.concatenate(t) for t in (rows, cols, vals))
+    order = np.lexsort((cols, rows))
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, rows + 1, 1)
+    A = I.CSR(n, n, np.cumsum(rp).astype(np.int32), cols[order].astype(np.int32), vals[order])
+    M = spk.Matrix(A)
+    try:
+        assert M.formats() & (1 << STENCIL)
+        x = I.uniform(45, 0, n)
+        xd = torch.from_numpy(x).to(dev)
+        y = torch.empty(n, dtype=torch.float64, device=dev)
+        ref, _ = O.spmv(A, x)
+        staged = spk.make_variant(format=STENCIL, block=512, group=1, unroll=4, streams=1, lds=1)
+        with pytest.raises(spk.SpkError, match="SPK_ERR_ARG"):
+            spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), staged)
+        plain = spk.make_variant(format=STENCIL, block=256, group=1, unroll=2, streams=1)
+        spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), plain)
+        assert np.array_equal(y.cpu().numpy(), ref)
+        rep = spk.spk_tune(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), reps=2, warmup=1, record=False,
+                           formats=1 << STENCIL)
+        assert rep.tried == len([s for s in SHAPES[STENCIL] if s[2] == 0]) and rep.best.lds == 0
     finally:
         M.release()
 
@@ -174,6 +213,6 @@ def test_full_size_lap3d_128(spk, dev):
             say(f"full-size lap3d 128 format {fmt}")
             for v in _variants(spk, fmt):
                 spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), v)
-                assert np.array_equal(y.cpu().numpy(), ref), (fmt, v.block, v.unroll)
+                assert np.array_equal(y.cpu().numpy(), ref), (fmt, v.block, v.unroll, v.lds)
     finally:
         M.release()
