@@ -22,86 +22,103 @@ constexpr int kWaveTileRows = 2 * kWave;   // rows of one wavefront's row stream
 
 typedef int int4v __attribute__((ext_vector_type(4)));
 
-// Products of a wavefront tile's entries, written to its LDS slice
-// (sp[k - k0] for entry k).  Lane l takes entries k0 + l + 64j: coalesced
-// 8-byte value loads and x gathers in entry order.  The column indices
-// arrive in 16-byte groups instead (a quarter of the load instructions):
-// groups of four aligned on their address, each loaded only when it holds
-// an entry of the tile (so the 16-byte block lies in the same page as a
-// valid entry), staged through the not-yet-used product slice and read back
-// in entry order.
-template <typename T, int ITEMS>
-__device__ __forceinline__ void wave_products(const int32_t *ci, const T *val, const T *x, int k0, int nk, double *sp)
-{
-    constexpr int STEPS = (ITEMS * kWave + 3 + 4 * kWave - 1) / (4 * kWave);
-    const int l = threadIdx.x & (kWave - 1);
-    T v[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int k = l + j * kWave;
-        // matrix entries are read exactly once: non-temporal, so the cache
-        // keeps the x entries that neighbouring rows share
-        v[j] = k < nk ? __builtin_nontemporal_load(val + k0 + k) : T(0);
-    }
-    const int off = (int)(((uintptr_t)(ci + k0) >> 2) & 3u);   // entries before k0 in the first group
-    const int32_t *cg = ci + k0 - off;
-    int *sci = reinterpret_cast<int *>(sp);                    // 2*64*ITEMS ints of room
-    int4v g[STEPS];
-#pragma unroll
-    for (int s = 0; s < STEPS; ++s) {
-        const int e0 = 4 * (l + kWave * s);
-        if (nk > 0 && e0 < off + nk) g[s] = __builtin_nontemporal_load((const int4v *)(cg + e0));
-    }
-#pragma unroll
-    for (int s = 0; s < STEPS; ++s) {
-        const int e0 = 4 * (l + kWave * s);
-        if (nk > 0 && e0 < off + nk) *(int4v *)(sci + e0) = g[s];
-    }
-    wave_lds_sync();
-    int c[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int k = l + j * kWave;
-        c[j] = k < nk ? sci[k + off] : -1;
-    }
-    wave_lds_sync();   // the staged indices are read before products overwrite them
-    T xv[ITEMS];
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) xv[j] = c[j] >= 0 ? x[c[j]] : T(0);
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int k = l + j * kWave;
-        if (k < nk) sp[k] = (double)v[j] * (double)xv[j];
-    }
-}
+// Global-address-space views.  Arrays reached through an argument block
+// held in memory (a tile record, say) reach the kernel as generic
+// pointers, and loads through them compile to flat accesses, which the
+// compiler can only wait for all together (vmcnt and lgkmcnt both to
+// zero).  Loads through these views are global accesses counted by vmcnt
+// alone, so a wait covers just the loads issued before the one needed.
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+template <typename T>
+using gptr_mut = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T *p) { return (gptr<T>)p; }
+template <typename T>
+__device__ __forceinline__ gptr_mut<T> as_global_mut(T *p) { return (gptr_mut<T>)p; }
 
 // One wavefront streams a run of short rows [r0, r1) with entries [k0, k1)
-// (k1 - k0 <= 64*ITEMS, r1 - r0 <= 128) through its private LDS slice:
-// all value/column/row-offset/own-x loads at once, then the x gather,
-// products to LDS, one lane per row sums from LDS (four interleaved
-// partial sums).  No workgroup barrier:
-// every wavefront of a CU is an independent stream.
+// (k1 - k0 <= 64*ITEMS, 1 <= r1 - r0 <= 128) through its private LDS slice
+// sp (64*ITEMS doubles).  No workgroup barrier: every wavefront of a CU is
+// an independent stream.
+//
+// Loads are issued in the order their data is needed and without
+// branches: the column indices first, in 16-byte groups aligned on their
+// address (a quarter of the load instructions), then the values (lane l
+// takes entries k0 + l + 64j: coalesced 8-byte loads), then the row offsets
+// and the rows' own x entries.  Only the index loads are waited for before
+// they are staged through the not-yet-used product slice and read back in
+// entry order, so the x gathers go out while the values are still
+// arriving.  Lanes past the tile's end load the tile's last entry or group
+// again (an address in the same page as a valid entry, already cached) and
+// drop it.  Then products to LDS and one lane per row sums them (four
+// interleaved partial sums).
 // With DOT, also returns the lane's part of sum_i x_i*y_i over the tile's
 // rows (square matrices: x_i is the row's own entry of x).
 template <typename T, int ITEMS, bool DOT = false>
-__device__ __forceinline__ double wave_stream(const int32_t *rp, const int32_t *ci, const T *val, const T *x, T *y,
-                                              T *w, T alpha, int r0, int r1, int k0, int k1, double *sp, int *srp)
+__device__ __forceinline__ double wave_stream(const int32_t *rp_, const int32_t *ci_, const T *val_, const T *x_,
+                                              T *y_, T *w_, T alpha, int r0, int r1, int k0, int k1, double *sp,
+                                              int *srp)
 {
+    constexpr int STEPS = (ITEMS * kWave + 3 + 4 * kWave - 1) / (4 * kWave);
+    static_assert(STEPS * 4 * kWave <= 2 * kWave * ITEMS, "staged index groups must fit the product slice");
+    const gptr<int32_t> rp = as_global(rp_);
+    const gptr<int32_t> ci = as_global(ci_);
+    const gptr<T> val = as_global(val_);
+    const gptr<T> x = as_global(x_);
+    const gptr_mut<T> y = as_global_mut(y_);
+    const gptr_mut<T> w = w_ ? as_global_mut(w_) : nullptr;
     const int l = threadIdx.x & (kWave - 1);
     const int nr = r1 - r0;
     const int nk = k1 - k0;
+    if (nr <= 0) return 0.0;
+    int *sci = reinterpret_cast<int *>(sp);   // 2*64*ITEMS ints of room
+    const int off = (int)(((uintptr_t)(ci_ + k0) >> 2) & 3u);   // entries before k0 in the first group
+    const int klast = nk > 0 ? nk - 1 : 0;
+    int4v g[STEPS];
+    T v[ITEMS];
+    if (nk > 0) {
+        const gptr<int32_t> cg = ci + k0 - off;
+        const int glast = (off + klast) & ~3;   // start of the last group holding an entry
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s)
+            g[s] = __builtin_nontemporal_load((gptr<int4v>)(cg + min(4 * (l + kWave * s), glast)));
+        // matrix entries are read exactly once: non-temporal, so the cache
+        // keeps the x entries that neighbouring rows share
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) v[j] = __builtin_nontemporal_load(val + k0 + min(l + j * kWave, klast));
+    }
     int rpv[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) rpv[q] = (l + q * kWave <= nr) ? rp[r0 + l + q * kWave] - k0 : 0;
-    T xo[2];
+    for (int q = 0; q < 3; ++q) rpv[q] = rp[r0 + min(l + q * kWave, nr)] - k0;
+    T xo[2] = {T(0), T(0)};
+    if (DOT || w) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) xo[q] = ((DOT || w) && l + q * kWave < nr) ? x[r0 + l + q * kWave] : T(0);
-    wave_products<T, ITEMS>(ci, val, x, k0, nk, sp);
-    double dot = 0.0;
+        for (int q = 0; q < 2; ++q) xo[q] = x[r0 + min(l + q * kWave, nr - 1)];
+    }
+    if (nk > 0) {
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) *(int4v *)(sci + 4 * (l + kWave * s)) = g[s];
+        wave_lds_sync();
+        int c[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) c[j] = sci[min(l + j * kWave, klast) + off];
+        wave_lds_sync();   // the staged indices are read before products overwrite them
+        T xv[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) xv[j] = x[c[j]];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int k = l + j * kWave;
+            if (k < nk) sp[k] = (double)v[j] * (double)xv[j];
+        }
+    }
 #pragma unroll
     for (int q = 0; q < 3; ++q)
         if (l + q * kWave <= nr) srp[l + q * kWave] = rpv[q];
     wave_lds_sync();
+    double dot = 0.0;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int i = l + q * kWave;

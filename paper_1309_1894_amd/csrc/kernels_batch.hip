@@ -21,6 +21,11 @@ namespace spk {
 // Tiles are wavefront-sized: every wavefront of a workgroup runs its own
 // tile, with its own slice of the workgroup's LDS (TILE/(BS/64) products and
 // 129 row offsets), and no workgroup barrier.
+// Tiles per run when tile groups are dealt to the XCDs (measured on the
+// 4096-instance banded batch: runs of 32 to 128 tiles stream 5% faster than
+// contiguous eighths, and 2-3% faster than dealing single groups).
+constexpr int kXcdRunTiles = 64;
+
 template <typename T, int BS, int TILE>
 struct WaveTiles {
     static constexpr int NW = BS / kWave;        // wavefronts per workgroup
@@ -62,7 +67,8 @@ __global__ __launch_bounds__(BS) void k_batch_grid(BatchArgs<T> a)
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int ngroups = (a.ntiles + WT::NW - 1) / WT::NW;
     const int b = (int)blockIdx.x;
-    const int tile = xcd_remap(b, ngroups) * WT::NW + wv;   // XCD-contiguous tile groups
+    // runs of kXcdRunTiles tiles dealt to the XCDs in turn
+    const int tile = xcd_chunk(b, ngroups, kXcdRunTiles / WT::NW) * WT::NW + wv;
     if (tile < a.ntiles)
         run_wave_tile<T, BS, TILE>(a, tile, sp + wv * WT::ENTRIES, srp + wv * (kWaveTileRows + 1));
 }

@@ -46,9 +46,9 @@ __device__ __forceinline__ double sum_partials(const double *part, int64_t n, do
 }  // namespace
 
 // q = A p over wavefront tiles: wavefront w of workgroup b runs tile w of
-// tile group xcd_remap(b) (each XCD sweeps a contiguous range of groups, so
-// the groups in flight on an XCD share their x entries in its L2), and the
-// workgroup leaves its part of p.q at that group's index.
+// tile group xcd_remap(b) (runs of neighbouring groups per XCD, so groups in
+// flight on an XCD share their x entries in its L2), and the workgroup
+// leaves its part of p.q at that group's index.
 template <int BS, int E>
 __global__ __launch_bounds__(BS) void k_cg_spmv_dot(CgLaunch c)
 {
