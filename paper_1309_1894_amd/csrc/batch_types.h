@@ -8,10 +8,10 @@ namespace spk {
 
 // A tile is rows [r0, r1) (entries [k0, k1)) of one CSR matrix, processed
 // with kernel `mode`: 0 = LDS-staged row stream summed one lane per row,
-// 100 + G (G in {2,4,8,16}) = the same stream summed by G lanes per row,
-// G in {2..64} = G lanes per row straight from memory.  The tile carries its matrix's arrays and the offset of the matrix's
-// vectors inside the launch's x / y / w, so a workgroup needs one 64-byte
-// descriptor load before it can start streaming.
+// G in {2, 4, ..., 64} = G lanes per row straight from memory.  The tile
+// carries its matrix's arrays and the offset of the matrix's vectors inside
+// the launch's x / y / w, so a wavefront needs one 64-byte descriptor load
+// before it can start streaming.
 struct BatchTile {
     const int32_t *rp;
     const int32_t *ci;
