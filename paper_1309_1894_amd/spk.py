@@ -198,6 +198,13 @@ def _dev(t, name: str):
     return t.data_ptr()
 
 
+def _need(t, n: int, name: str):
+    """The C entry points take bare pointers: a tensor shorter than the call
+    reads or writes is caught here, before the pointer is passed on."""
+    if t is not None and t.numel() < n:
+        raise ValueError(f"{name} holds {t.numel()} elements; the call uses {n}")
+
+
 def _stream(stream=None):
     if stream is not None:
         return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
@@ -301,6 +308,9 @@ def spk_spmv_csr(row_ptr, col_idx, val, x, y=None, nrows=None, ncols=None, handl
     ncols = x.numel() if ncols is None else ncols
     if y is None:
         y = torch.empty(nrows, dtype=val.dtype, device=val.device)
+    _need(row_ptr, nrows + 1, "row_ptr")
+    _need(x, ncols, "x")
+    _need(y, nrows, "y")
     A = _csr_struct(nrows, ncols, col_idx.numel(), _dtype_code(val), _dev(row_ptr, "row_ptr"),
                     _dev(col_idx, "col_idx"), _dev(val, "val"))
     _ok(_lib.spk_spmv_csr(_h(handle), C.byref(A), _dev(x, "x"), _dev(y, "y"), _stream(stream)), "spk_spmv_csr")
@@ -376,6 +386,8 @@ def spk_spmv_mat(A: Matrix, x, y=None, stream=None):
     torch = _torch()
     if y is None:
         y = torch.empty(A.nrows, dtype=A.torch_dtype, device=x.device)
+    _need(x, A.ncols, "x")
+    _need(y, A.nrows, "y")
     _ok(_lib.spk_spmv_mat(A.handle.ptr, A.ptr, _dev(x, "x"), _dev(y, "y"), _stream(stream)), "spk_spmv_mat")
     return y
 
@@ -387,6 +399,9 @@ def spk_spmv_waxpy(A: Matrix, alpha: float, x, y=None, w=None, stream=None):
         y = torch.empty(A.nrows, dtype=A.torch_dtype, device=x.device)
     if w is None:
         w = torch.empty(A.nrows, dtype=A.torch_dtype, device=x.device)
+    _need(x, A.ncols, "x")
+    _need(y, A.nrows, "y")
+    _need(w, A.nrows, "w")
     _ok(_lib.spk_spmv_waxpy(A.handle.ptr, A.ptr, float(alpha), _dev(x, "x"), _dev(y, "y"), _dev(w, "w"),
                             _stream(stream)), "spk_spmv_waxpy")
     return y, w
@@ -399,6 +414,9 @@ def spk_cg(A: Matrix, b, x, iters: int, hist=None, stream=None):
     torch = _torch()
     if hist is None:
         hist = torch.empty(int(iters) + 1, dtype=torch.float64, device=x.device)
+    _need(b, A.nrows, "b")
+    _need(x, A.nrows, "x")
+    _need(hist, int(iters) + 1, "hist")
     _ok(_lib.spk_cg(A.handle.ptr, A.ptr, _dev(b, "b"), _dev(x, "x"), int(iters), _dev(hist, "hist"),
                     _stream(stream)), "spk_cg")
     return hist
@@ -414,6 +432,7 @@ def spk_cg_tune(A: Matrix, b, iters: int, *, reps=10, warmup=2, tau=0.0, max_var
     o.formats = int(formats)
     o.record, o.verbose = int(record), int(verbose)
     rep = spk_tune_report()
+    _need(b, A.nrows, "b")
     _ok(_lib.spk_cg_tune(A.handle.ptr, A.ptr, _dev(b, "b"), int(iters), C.byref(o), C.byref(rep)), "spk_cg_tune")
     return rep
 
@@ -431,6 +450,14 @@ def problem(op, *, A: Matrix | None = None, x=None, y=None, w=None, d_result=Non
     if dtype is not None:
         p.dtype = dtype
     p.n = int(n if n is not None else (x.numel() if x is not None else 0))
+    if A is not None:
+        _need(x, A.ncols, "x")
+        _need(y, A.nrows, "y")
+        _need(w, A.nrows, "w")
+    else:
+        for t, name in ((x, "x"), (y, "y"), (w, "w")):
+            _need(t, p.n, name)
+    _need(d_result, 1, "d_result")
     p.alpha = float(alpha)
     p.x = _dev(x, "x")
     p.y = _dev(y, "y")
@@ -534,11 +561,18 @@ class Batch:
         self.ptr = b.value
         self._dev = device_arrays  # keep the borrowed arrays alive
 
+    def _check(self, x, y, w):
+        rows = int(self._host[0].sum())
+        for t, name in ((x, "x"), (y, "y"), (w, "w")):
+            _need(t, rows, name)
+
     def run(self, alpha, x, y, w=None, stream=None):
+        self._check(x, y, w)
         _ok(_lib.spk_batch_run(self.handle.ptr, self.ptr, float(alpha), _dev(x, "x"), _dev(y, "y"), _dev(w, "w"),
                                _stream(stream)), "spk_batch_run")
 
     def tune(self, alpha, x, y, w=None, reps=10, warmup=2, flush=False, record=True, verbose=False):
+        self._check(x, y, w)
         o = spk_tune_opts()
         o.reps, o.warmup, o.flush, o.record, o.verbose = reps, warmup, int(flush), int(record), int(verbose)
         rep = spk_tune_report()

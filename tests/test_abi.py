@@ -110,3 +110,23 @@ def test_header_is_plain_c99(tmp_path):
     r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-pedantic", "-fsyntax-only",
                         "-I", os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_binding_rejects_short_tensors():
+    """The C entry points take bare pointers; the binding refuses a tensor
+    shorter than the call would read or write before passing its pointer."""
+    import torch
+
+    from paper_1309_1894_amd import spk
+    x, short = torch.zeros(10, dtype=torch.float64), torch.zeros(9, dtype=torch.float64)
+    with pytest.raises(ValueError, match="y holds 9"):
+        spk.problem(spk.SPK_OP_WAXPY, x=x, y=short, w=x, alpha=1.0)
+    with pytest.raises(ValueError, match="w holds 9"):
+        spk.problem(spk.SPK_OP_WAXPY, x=x, y=x, w=short, alpha=1.0)
+    with pytest.raises(ValueError, match="d_result holds 0"):
+        spk.problem(spk.SPK_OP_DOT, x=x, y=x, d_result=torch.zeros(0, dtype=torch.float64))
+    ci, val = torch.zeros(0, dtype=torch.int32), torch.zeros(0, dtype=torch.float64)
+    with pytest.raises(ValueError, match="y holds 9"):
+        spk.spk_spmv_csr(torch.zeros(11, dtype=torch.int32), ci, val, x, y=short, nrows=10)
+    with pytest.raises(ValueError, match="row_ptr holds 5"):
+        spk.spk_spmv_csr(torch.zeros(5, dtype=torch.int32), ci, val, x, y=x, nrows=10)

@@ -51,7 +51,7 @@ def test_graph_replays_match_eager(spk, dev):
         wx = torch.empty_like(xd)
         d = torch.empty(1, dtype=torch.float64, device=dev)
         xc = torch.zeros_like(xd)
-        hist = torch.empty(10, dtype=torch.float64, device=dev)
+        hist = torch.empty(11, dtype=torch.float64, device=dev)   # r.r for k = 0..10
 
         def calls():
             for k, v in vs.items():
