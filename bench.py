@@ -140,6 +140,8 @@ def main():
         plain["gbs_of_tuned_bytes"] = round(step_bytes / (plain["ms"] * 1e-3) / 1e9, 1)
     log(f"batched plain: {plain}")
     out["batched"] = {"tuned_gbs": round(value, 1), "tuned_ms": round(ms_per_step, 4), "launch": cfg,
+                      "kernel_ms_p10_p50_p90": [round(float(np.percentile(per_launch_ms, q)), 4)
+                                                for q in (10, 50, 90)],
                       "plain": plain,
                       "speedup_vs_plain": round(plain["ms"] / ms_per_step, 2) if plain["ms"] else None,
                       "instances": B.count, "rows": nv, "nnz": int(B.nnz.sum()), "bytes_per_step": step_bytes,
