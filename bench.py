@@ -166,6 +166,7 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(B, x, alpha, step_bytes)
         out["cpu_oracle_single_thread"] = cpu_single_thread(B, x, alpha, step_bytes)
+        out["cpu_oracle_beside_legs"] = cpu_beside_legs(I, [k for k in out if k in EXTRA_LEGS])
 
     traffic = load_traffic(kname, step_bytes)
     result = {
@@ -661,6 +662,50 @@ def cpu_baseline(B, x, alpha, step_bytes):
     return {"value": round(step_bytes / sec / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": f"the whole batched step ({B.count} instances), median of {len(t)} runs "
                       f"({t_total:.1f} s), {sec * 1e3:.1f} ms per step"}
+
+
+def cpu_beside_legs(I, legs):
+    """The CPU-baseline leg beside the other results: the oracle as it
+    stands, on all host cores, on the same seeded inputs as each GPU leg
+    that ran (algorithmic bytes as there; median of a few runs)."""
+    import numpy as np
+
+    import oracle as O
+
+    def median_s(fn, reps):
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            t.append(time.perf_counter() - t0)
+        return float(np.median(t))
+
+    res = {"threads": O.num_threads()}
+    if "spmv_large" in legs:
+        for name, A, seed in (("lap3d_128", I.lap3d(128), 31), ("zipf_1M", I.zipf(1000000), 34)):
+            xh = I.uniform(seed, 0, A.ncols)
+            sec = median_s(lambda: O.spmv(A, xh, with_absum=False), 3)
+            nbytes = A.nnz * 12 + 4 * (A.nrows + 1) + 8 * A.ncols + 8 * A.nrows
+            res[f"spmv_{name}"] = {"ms": round(sec * 1e3, 2), "gbs": round(nbytes / sec / 1e9, 2)}
+    if "vector_sweep" in legs:
+        n = 1 << 27
+        xh, yh = I.uniform(21, 0, n), I.uniform(22, 0, n)
+        for nm, fn, nbytes in (("waxpy", lambda: O.waxpy(1.5, xh, yh), 24 * n), ("dot", lambda: O.dot(xh, yh), 16 * n)):
+            sec = median_s(fn, 3)
+            res[f"{nm}_f64_n2^27"] = {"ms": round(sec * 1e3, 2), "gbs": round(nbytes / sec / 1e9, 2)}
+        del xh, yh
+    if "krylov_step_lap2d" in legs:
+        A = I.lap2d(256)
+        xh = I.uniform(11, 0, A.nrows)
+        sec = median_s(lambda: O.spmv_waxpy(A, xh, 0.5), 20)
+        res["krylov_step_lap2d"] = {"us": round(sec * 1e6, 1)}
+    if "cg_lap3d_128" in legs:
+        A = I.lap3d(128)
+        bh = I.uniform(61, 0, A.nrows)
+        it = 20
+        sec = median_s(lambda: O.cg(A, bh, it), 1)
+        res["cg_lap3d_128"] = {"us_per_iter": round(sec * 1e6 / it, 1), "iters": it}
+    return res
 
 
 def cpu_single_thread(B, x, alpha, step_bytes, steps=3):
