@@ -63,7 +63,7 @@ def main():
         if bad:
             sys.exit(f"unknown extra leg(s) {bad}; known: {', '.join(EXTRA_LEGS)}")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
     lib = os.path.join(ROOT, "paper_1309_1894_amd", "libspk.so")
