@@ -427,7 +427,7 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
     SPK_HIP(hipStreamSynchronize(s));
 
     std::vector<hipEvent_t> ev(2 * (size_t)reps);
-    for (auto &e : ev) SPK_HIP(hipEventCreate(&e));
+    for (auto &e : ev) SPK_HIP(timing_event(&e));
     struct EvFree {
         std::vector<hipEvent_t> &e;
         ~EvFree() { for (auto x : e) (void)hipEventDestroy(x); }

@@ -267,8 +267,8 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
     SPK_HIP(hipMalloc(&hr.p, hb));
     SPK_HIP(hipMalloc(&ht.p, hb));
     EventPair ev;
-    SPK_HIP(hipEventCreate(&ev.a));
-    SPK_HIP(hipEventCreate(&ev.b));
+    SPK_HIP(timing_event(&ev.a));
+    SPK_HIP(timing_event(&ev.b));
 
     auto solve = [&](const CgEntry *e, void *xd, void *hd) -> spk_status {
         SPK_HIP(hipMemsetAsync(xd, 0, nb, s));
@@ -287,7 +287,7 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
             SPK_HIP(hipEventRecord(ev.a, s));
             SPK_TRY(run_cg(h, A, e, (const double *)b, (double *)xt.p, iters, (double *)ht.p, s));
             SPK_HIP(hipEventRecord(ev.b, s));
-            SPK_HIP(hipEventSynchronize(ev.b));
+            SPK_HIP(hipStreamSynchronize(s));
             float ms = 0.f;
             SPK_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
             if (r >= warmup) t.push_back(ms * 1e3);

@@ -127,6 +127,16 @@ struct CgScratch {
 
 }  // namespace spk
 
+namespace spk {
+
+// Events used only to time work between them (the elapsed time is read
+// after a stream synchronisation): created without the system-scope
+// release/acquire an event record otherwise performs, so that a short
+// kernel's time does not include an L2 write-back and invalidate.
+inline hipError_t timing_event(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableSystemFence); }
+
+}  // namespace spk
+
 struct spk_ctx {
     int device = 0;
     int num_cu = 0;

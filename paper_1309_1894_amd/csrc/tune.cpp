@@ -79,7 +79,7 @@ spk_status time_variant(Ctx &c, const spk_variant &v, int warmup, int reps, bool
 {
     for (int i = 0; i < warmup; ++i) SPK_TRY(run_variant(c, v));
     std::vector<hipEvent_t> ev(2 * (size_t)reps);
-    for (auto &e : ev) SPK_HIP(hipEventCreate(&e));
+    for (auto &e : ev) SPK_HIP(timing_event(&e));
     spk_status st = SPK_OK;
     for (int r = 0; r < reps && st == SPK_OK; ++r) {
         if (c.p.op == SPK_OP_AXPY) {
