@@ -358,50 +358,23 @@ def structured_spmv(spk, M, xd, y, csr_tuned_us, op=None, w=None):
 
 
 def per_format(spk, torch, M, xd, y, reps=5):
-    """Best cold-cache time (us) of every compiled variant, per storage
-    format (the tuner's search, reported format by format)."""
+    """Best cold-cache time (us) per storage format: the tuner's search
+    (validation, then timing) restricted to one format at a time."""
     names = {spk.SPK_FMT_SCALAR: "csr_scalar", spk.SPK_FMT_VECTOR: "csr_vector", spk.SPK_FMT_SELL: "sliced_ell",
              spk.SPK_FMT_ADAPTIVE: "csr_lds_tiles", spk.SPK_FMT_DIA: "dia", spk.SPK_FMT_STENCIL: "stencil"}
-    stream = torch.cuda.current_stream()
     best = {}
     p = spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y)
-    space = list(spk.variants(spk.SPK_OP_SPMV, M.dtype_code))
-    for fmt in (spk.SPK_FMT_DIA, spk.SPK_FMT_STENCIL):
-        if M.formats() & (1 << fmt):
-            space += [spk.make_variant(format=fmt, block=bs, group=1, unroll=r, streams=1) for bs in (128, 256, 512)
-                      for r in (1, 2)]
-    if M.formats() & (1 << spk.SPK_FMT_STENCIL):
-        space += [spk.make_variant(format=spk.SPK_FMT_STENCIL, block=bs, group=1, unroll=r, streams=1, lds=1)
-                  for bs in (256, 512) for r in (2, 4)]
-    for v in space:
-        # the tuner's byte model: sliced ELL only when padding at most doubles the entries
-        if v.format == spk.SPK_FMT_SELL and M.nnz and sell_padding(M, v.group) > 2.0:
+    for fmt, name in names.items():
+        if fmt in (spk.SPK_FMT_DIA, spk.SPK_FMT_STENCIL) and not M.formats() & (1 << fmt):
             continue
-        spk.spk_run(p, v)
-        ev = []
-        for _ in range(reps):
-            spk.spk_flush_cache()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            spk.spk_run(p, v)
-            b.record(stream)
-            ev.append((a, b))
-        torch.cuda.synchronize()
-        t = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)[reps // 2]
-        k = names[v.format] + ("_lds" if v.format == spk.SPK_FMT_STENCIL and v.lds else "")
-        if k not in best or t < best[k]:
-            best[k] = round(t, 2)
+        try:
+            rep = spk.spk_tune(p, reps=reps, warmup=1, flush=True, record=False, formats=1 << fmt)
+        except spk.SpkError:
+            continue   # every variant of the format pruned (sliced ELL whose padding would exceed 2x)
+        best[name] = round(rep.best_us, 2)
+        if fmt == spk.SPK_FMT_STENCIL:
+            best["stencil_lds_staged"] = bool(rep.best.lds)
     return best
-
-
-def sell_padding(M, C):
-    """Stored entries of sliced ELL with slices of C rows, over nnz."""
-    import numpy as np
-    lens = np.diff(M.row_ptr_host.astype(np.int64))
-    pad = len(lens) % C
-    if pad:
-        lens = np.concatenate([lens, np.zeros(C - pad, np.int64)])
-    return float(lens.reshape(-1, C).max(axis=1).sum() * C) / max(1, M.nnz)
 
 
 def lap2d_step(spk, torch, I, dev):
