@@ -100,3 +100,38 @@ def test_serve_rejects_oversized_matrix(spk, dev):
         assert e.value.name == "SPK_ERR_BUDGET"
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_serve_large_vectors_chunked_copies(spk, dev, mode):
+    """Requests whose vectors exceed the inline-copy threshold: the host
+    copies to and from the pinned staging block are cut into chunks shared by
+    the copy threads (a ragged last chunk included); every result still
+    matches the oracle and the same request served alone."""
+    pool = [I.banded(150001, 5, 0.6, seed_struct=64, seed_val=65),                   # x: 1.2 MB of FP64
+            I.zipf(90001, kmax=4096, seed_struct=66, seed_val=67, dtype=np.float32)]  # x: 360 KB of FP32
+    nreq = 24
+    mats = [i % 2 for i in range(nreq)]
+    xs = [I.uniform(73, i, pool[m].ncols, pool[m].val.dtype) for i, m in enumerate(mats)]
+    ys = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
+    ws = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
+    say(f"serve large vectors mode={mode}")
+    srv = spk.Server(streams=4, max_inflight=16, max_batch=8, mode=mode, alpha=0.5)
+    try:
+        ids = [srv.add_matrix(A) for A in pool]
+        srv.replay(I.poisson_arrivals(nreq, 5000.0, seed=74), [ids[m] for m in mats], xs, ys, ws)
+        assert srv.stats()["completed"] == nreq
+    finally:
+        srv.close()
+    for i in range(nreq):
+        _check(pool[mats[i]], xs[i], ys[i], ws[i])
+    solo = spk.Server(streams=1, max_inflight=1, max_batch=1, mode=mode, alpha=0.5)
+    try:
+        ids = [solo.add_matrix(A) for A in pool]
+        for i in (0, 1, nreq - 1):
+            y1, w1 = np.empty_like(ys[i]), np.empty_like(ws[i])
+            solo.submit(ids[mats[i]], xs[i], y1, w1)
+            solo.drain()
+            assert np.array_equal(y1, ys[i]) and np.array_equal(w1, ws[i]), i
+    finally:
+        solo.close()
