@@ -546,7 +546,7 @@ def serving(spk, I, nreq):
     """Open-loop Poisson serving of SpMV+WAXPY requests over a pool of banded
     and Zipf matrices (1e3..1e5 rows here, 70% FP64 / 30% FP32): continuous
     batching vs a FIFO server that runs one request at a time with the plain
-    unbatched kernels, both on the same arrival traces at two offered loads
+    unbatched kernels, both on the same arrival traces at four offered loads
     (70% of the FIFO server's and 50/70/90% of the batching server's
     closed-loop saturation rate)."""
     import numpy as np
