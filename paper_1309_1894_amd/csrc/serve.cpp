@@ -171,6 +171,7 @@ struct PoolMat {
     void *d_val = nullptr;
     int64_t dev_bytes = 0;
     bool resident = false;
+    bool upload_done = false;   // its upload event has been seen complete
     int refs = 0;
     double last_use = 0.0;
     hipEvent_t uploaded = nullptr;
@@ -263,6 +264,7 @@ spk_status make_resident(Server *S, PoolMat &M)
     if (!M.uploaded) SPK_HIP(hipEventCreateWithFlags(&M.uploaded, hipEventDisableTiming));
     SPK_HIP(hipEventRecord(M.uploaded, S->upload));
     M.resident = true;
+    M.upload_done = false;
     S->used_mat += M.dev_bytes;
     ++S->uploads;
     return SPK_OK;
@@ -356,7 +358,16 @@ spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &gro
     S->copies.copy(cp);
     hipStream_t s = S->streams[S->next_stream];
     S->next_stream = (S->next_stream + 1) % (int)S->streams.size();
-    for (const auto &g : group) SPK_HIP(hipStreamWaitEvent(s, S->mats[g.second.mat].uploaded, 0));
+    // order the launch after uploads still in flight (each matrix once)
+    for (const auto &g : group) {
+        PoolMat &M = S->mats[g.second.mat];
+        if (M.upload_done) continue;
+        if (hipEventQuery(M.uploaded) == hipSuccess) {
+            M.upload_done = true;
+            continue;
+        }
+        SPK_HIP(hipStreamWaitEvent(s, M.uploaded, 0));
+    }
     char *dev = (char *)F.dev;
     SPK_HIP(hipMemcpyAsync(dev, pin, in_b, hipMemcpyHostToDevice, s));
     const void *x = dev + tile_b;
