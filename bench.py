@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-instance baseline")
     ap.add_argument("--verbose", action="store_true", help="print every tuning candidate")
     ap.add_argument("--instances", type=int, default=4096)
-    ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--serve-requests", type=int, default=6000)
     return ap.parse_args()
 
 
@@ -579,7 +579,7 @@ def serving(spk, I, nreq):
 
     def saturation(mode):
         srv, ids = make(mode)
-        k = min(nreq, 600)
+        k = min(nreq, 1500)
         t0 = time.perf_counter()
         for i in range(k):
             srv.submit(ids[mats[i]], xs[i], np.empty(pool[mats[i]].nrows, pool[mats[i]].val.dtype))
