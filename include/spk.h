@@ -468,7 +468,10 @@ typedef struct {
     double bytes_moved;       /* algorithmic bytes of completed requests */
 } spk_serve_stats;
 
-/* Starts a serving loop on the handle's device (a scheduler thread). */
+/* Starts a serving loop on the handle's device: a scheduler thread, which
+ * owns the GPU side, and three threads that share its host copies between
+ * the callers' buffers and pinned staging memory.  spk_serve_destroy joins
+ * them all. */
 spk_status spk_serve_create(spk_handle h, const spk_serve_opts *opts, spk_server *out);
 
 /* Adds a matrix to the server's pool.  A's arrays are host memory and are
