@@ -471,8 +471,10 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
     };
 
     // launch configuration: workgroup size / LDS tile and persistence,
-    // timed on the whole batch with the current per-class kernels
-    {
+    // timed on the whole batch with the current per-class kernels; run
+    // before the per-class search and once more after it (the shape that
+    // wins with the default kernels need not win with the tuned ones)
+    auto pick_launch = [&]() -> spk_status {
         int n = 0;
         const BatchEntry *tab = batch_table(&n);
         const BatchEntry *best_e = b->entry;
@@ -500,9 +502,12 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
         b->opts.persistent = best_p;
         SPK_TRY(occupancy(b));
         SPK_TRY(replan(b));
-    }
+        return SPK_OK;
+    };
+    SPK_TRY(pick_launch());
 
     std::map<int, std::vector<int64_t>> by_class;
+    std::map<int, double> class_best;
     for (int64_t i = 0; i < b->count; ++i) by_class[b->cls[i]].push_back(i);
     for (auto &kv : by_class) {
         const int c = kv.first;
@@ -525,21 +530,25 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
             }
         }
         b->mode[c] = best_mode;
+        class_best[c] = best;
         total_best += best;
         total_plain += plain_time > 0 ? plain_time : best;
-        if (o.record) {
-            spk_variant v{};
-            v.format = is_stream_mode(best_mode) ? SPK_FMT_ADAPTIVE : SPK_FMT_VECTOR;
-            v.block = b->entry->block;
-            v.group = best_mode;
-            v.lds = b->entry->tile;
-            v.streams = 1;
-            const std::string key = batch_key(b->dtype, c);
-            spk_plan_put(h, key.c_str(), &v);
-            db_append(h, key, v, best);
-        }
     }
     SPK_TRY(replan(b));
+    SPK_TRY(pick_launch());
+    if (o.record) {
+        for (const auto &kv : class_best) {
+            spk_variant v{};
+            v.format = is_stream_mode(b->mode[kv.first]) ? SPK_FMT_ADAPTIVE : SPK_FMT_VECTOR;
+            v.block = b->entry->block;
+            v.group = b->mode[kv.first];
+            v.lds = b->entry->tile;
+            v.streams = 1;
+            const std::string key = batch_key(b->dtype, kv.first);
+            spk_plan_put(h, key.c_str(), &v);
+            db_append(h, key, v, kv.second);
+        }
+    }
     // leave a full-batch result in the caller's buffers
     SPK_TRY(launch(b, (int64_t)b->tiles.size(), alpha, x, y, w, s));
     SPK_HIP(hipStreamSynchronize(s));
