@@ -145,7 +145,8 @@ struct CopyPool {
         size_t total = 0;
         for (const Chunk &c : items) total += c.n;
         if (thr.empty() || total < kCopyInline) {
-            for (const Chunk &c : items) memcpy(c.dst, c.src, c.n);
+            for (const Chunk &c : items)
+                if (c.n) memcpy(c.dst, c.src, c.n);
             return;
         }
         std::unique_lock<std::mutex> lk(mu);
