@@ -126,9 +126,10 @@ void cut_rows(const int32_t *rp, int64_t m, int mode, int entries, int64_t targe
 
 spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchTile *d_tiles, int64_t ntiles, double alpha,
                         const void *x, void *y, void *w, int kind, uint32_t *ctr, int64_t persistent_grid,
-                        hipStream_t s)
+                        hipStream_t s, const BatchReq *reqs, const uint16_t *req_of_tile)
 {
     if (ntiles == 0) return SPK_OK;
+    if (reqs && kind != kBatchGrid) return fail(SPK_ERR_ARG, "request tables need the grid launch");
     union {
         BatchArgs<float> f;
         BatchArgs<double> d;
@@ -145,6 +146,8 @@ spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchTile *d_tiles
         q.alpha = (T)alpha;
         q.next = ctr;                              // 8 queue heads, 256 bytes apart
         q.done = ctr ? ctr + 8 * 64 : nullptr;     // then the completion count
+        q.reqs = reqs;
+        q.req_of_tile = reqs ? req_of_tile : nullptr;
     };
     if (dtype == SPK_F64) fill(a.d); else fill(a.f);
     const int64_t nw = e->block / 64;

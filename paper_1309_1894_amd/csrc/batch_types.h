@@ -23,4 +23,16 @@ struct BatchTile {
 
 static_assert(sizeof(BatchTile) == 64, "tile descriptor is one 64-byte line");
 
+// Serving launches: each request's matrix keeps its tiles on the device
+// (vector offsets 0), and a launch over several requests names them through
+// this table instead of copying tiles: launch tile t is tile
+// t - first of request req_of_tile[t], its vectors at vec_off in x / y / w.
+struct BatchReq {
+    const BatchTile *tiles;
+    int64_t vec_off;
+    int32_t first, pad;
+};
+
+static_assert(sizeof(BatchReq) == 24, "request record");
+
 }  // namespace spk

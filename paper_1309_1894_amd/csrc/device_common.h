@@ -183,6 +183,8 @@ struct BatchArgs {
     T alpha;
     uint32_t *next;    // tile queue head (persistent launch), zero between launches
     uint32_t *done;    // finished workgroups (persistent launch), zero between launches
+    const BatchReq *reqs;            // serving (grid launch): tiles named per request, or null
+    const uint16_t *req_of_tile;     // request of each launch tile (with reqs)
 };
 
 }  // namespace spk

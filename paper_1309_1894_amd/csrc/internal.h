@@ -250,9 +250,11 @@ const BatchEntry *batch_entry(int block, int tile);
 void cut_rows(const int32_t *rp, int64_t m, int mode, int entries, int64_t target, std::vector<BatchTile> &out);
 
 // One launch of the tile kernel of launch kind `kind` (kBatchGrid, or
-// kBatchPersistent with queue counters `ctr`).
+// kBatchPersistent with queue counters `ctr`).  With `reqs` (grid launches
+// only) the ntiles launch tiles are named through the request table and
+// `req_of_tile` instead of `d_tiles`.
 spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchTile *d_tiles, int64_t ntiles, double alpha,
                         const void *x, void *y, void *w, int kind, uint32_t *ctr, int64_t persistent_grid,
-                        hipStream_t s);
+                        hipStream_t s, const BatchReq *reqs = nullptr, const uint16_t *req_of_tile = nullptr);
 
 }  // namespace spk

@@ -35,9 +35,8 @@ struct WaveTiles {
 };
 
 template <typename T, int BS, int TILE>
-__device__ __forceinline__ void run_wave_tile(const BatchArgs<T> &a, int tile, double *sp, int *srp)
+__device__ __forceinline__ void run_wave_tile(const BatchArgs<T> &a, const BatchTile &td, double *sp, int *srp)
 {
-    const BatchTile td = a.tiles[tile];
     const int32_t *rp = td.rp;
     const int32_t *ci = td.ci;
     const T *val = (const T *)td.val;
@@ -69,8 +68,31 @@ __global__ __launch_bounds__(BS) void k_batch_grid(BatchArgs<T> a)
     const int b = (int)blockIdx.x;
     // runs of kXcdRunTiles tiles dealt to the XCDs in turn
     const int tile = xcd_chunk(b, ngroups, kXcdRunTiles / WT::NW) * WT::NW + wv;
-    if (tile < a.ntiles)
-        run_wave_tile<T, BS, TILE>(a, tile, sp + wv * WT::ENTRIES, srp + wv * (kWaveTileRows + 1));
+    if (tile >= a.ntiles) return;
+    // the tile record stays wavefront-uniform: the 16-bit map entry arrives
+    // through a vector load and is made uniform again
+    const BatchTile *tp = a.tiles + tile;
+    int64_t voff = -1;
+    if (a.req_of_tile) {
+        const int r = __builtin_amdgcn_readfirstlane((int)a.req_of_tile[tile]);
+        const BatchReq *q = a.reqs + r;
+        tp = q->tiles + (tile - q->first);
+        voff = q->vec_off;
+    }
+    // the address made uniform and read through the constant address space:
+    // scalar loads, as for a tile array passed in the arguments
+    const uint64_t ta = (uint64_t)tp;
+    const uint64_t tu = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(ta >> 32)) << 32) |
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)ta);
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const __attribute__((address_space(4))) u32x4 *src = (const __attribute__((address_space(4))) u32x4 *)tu;
+    u32x4 parts[sizeof(BatchTile) / sizeof(u32x4)];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(BatchTile) / sizeof(u32x4)); ++i) parts[i] = src[i];
+    BatchTile td;
+    __builtin_memcpy(&td, parts, sizeof td);
+    if (voff >= 0) td.vec_off = voff;
+    run_wave_tile<T, BS, TILE>(a, td, sp + wv * WT::ENTRIES, srp + wv * (kWaveTileRows + 1));
 }
 
 // Persistent form: a grid sized to fill the GPU whose wavefronts pull tiles
@@ -103,7 +125,7 @@ __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs<T> a)
         if (c0 >= hi) break;
         if (l == 0) claim = (int)atomicAdd(head, (uint32_t)kChunk);
         const int c1 = min(c0 + kChunk, hi);
-        for (int tile = c0; tile < c1; ++tile) run_wave_tile<T, BS, TILE>(a, tile, my_sp, my_srp);
+        for (int tile = c0; tile < c1; ++tile) run_wave_tile<T, BS, TILE>(a, a.tiles[tile], my_sp, my_srp);
     }
     // Every wavefront has drawn past the end of its queue before it counts
     // itself done, so the last one may reset all counters.  Only atomics

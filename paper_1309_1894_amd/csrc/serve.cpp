@@ -170,13 +170,14 @@ struct PoolMat {
     bool h_pinned = false;
     int32_t *d_rp = nullptr, *d_ci = nullptr;
     void *d_val = nullptr;
+    BatchTile *d_tiles = nullptr;   // its tiles, on the device while resident (vector offsets 0)
     int64_t dev_bytes = 0;
     bool resident = false;
     bool upload_done = false;   // its upload event has been seen complete
     int refs = 0;
     double last_use = 0.0;
     hipEvent_t uploaded = nullptr;
-    std::vector<BatchTile> tiles;   // row ranges of this matrix (pointers set at launch)
+    std::vector<BatchTile> tiles;   // row ranges of this matrix (pointers set when made resident)
 };
 
 struct Request {
@@ -262,6 +263,18 @@ spk_status make_resident(Server *S, PoolMat &M)
         SPK_HIP(hipMemcpyAsync(M.d_ci, M.h_ci, sizeof(int32_t) * M.nnz, hipMemcpyHostToDevice, S->upload));
         SPK_HIP(hipMemcpyAsync(M.d_val, M.h_val, vs * M.nnz, hipMemcpyHostToDevice, S->upload));
     }
+    if (!M.tiles.empty()) {
+        for (BatchTile &t : M.tiles) {
+            t.rp = M.d_rp;
+            t.ci = M.d_ci;
+            t.val = M.d_val;
+            t.vec_off = 0;
+        }
+        SPK_HIP(hipMalloc(&M.d_tiles, sizeof(BatchTile) * M.tiles.size()));
+        // pageable source: the call returns once the tiles are staged
+        SPK_HIP(hipMemcpyAsync(M.d_tiles, M.tiles.data(), sizeof(BatchTile) * M.tiles.size(), hipMemcpyHostToDevice,
+                               S->upload));
+    }
     if (!M.uploaded) SPK_HIP(hipEventCreateWithFlags(&M.uploaded, hipEventDisableTiming));
     SPK_HIP(hipEventRecord(M.uploaded, S->upload));
     M.resident = true;
@@ -278,8 +291,10 @@ void evict(Server *S, PoolMat &M)
     (void)hipFree(M.d_rp);
     (void)hipFree(M.d_ci);
     (void)hipFree(M.d_val);
+    if (M.d_tiles) (void)hipFree(M.d_tiles);
     M.d_rp = M.d_ci = nullptr;
     M.d_val = nullptr;
+    M.d_tiles = nullptr;
     M.resident = false;
     S->used_mat -= M.dev_bytes;
     ++S->evictions;
@@ -324,37 +339,43 @@ spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &gro
     Flight F;
     F.dtype = dtype;
     F.reqs = group;
-    std::vector<BatchTile> tiles;
-    int64_t total = 0;
+    const bool batched = S->opts.mode != 1;
+    // batched launches name each request's resident tiles through a table
+    // [request records | request of each launch tile] staged before x
+    std::vector<BatchReq> rq;
+    int64_t ntiles = 0, total = 0;
     for (size_t k = 0; k < group.size(); ++k) {
         const PoolMat &M = S->mats[group[k].second.mat];
         F.off.push_back(total);
-        for (BatchTile t : M.tiles) {
-            t.rp = M.d_rp;
-            t.ci = M.d_ci;
-            t.val = M.d_val;
-            t.vec_off = total;
-            tiles.push_back(t);
-        }
+        if (batched) rq.push_back({M.d_tiles, total, (int32_t)ntiles, 0});
+        ntiles += (int64_t)M.tiles.size();
         total += M.m;
     }
-    // one staging block: [tiles | x | y | w], 256-byte aligned parts
+    // one staging block: [requests | tile map | x | y | w], 256-byte aligned parts
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    const size_t tile_b = al(sizeof(BatchTile) * std::max<size_t>(1, tiles.size()));
+    const size_t req_b = batched ? al(sizeof(BatchReq) * std::max<size_t>(1, rq.size())) : 0;
+    const size_t map_b = batched ? al(sizeof(uint16_t) * (size_t)std::max<int64_t>(1, ntiles)) : 0;
+    const size_t head_b = req_b + map_b;
     const size_t vec_b = al(vs * (size_t)std::max<int64_t>(1, total));
-    const size_t in_b = tile_b + vec_b;
+    const size_t in_b = head_b + vec_b;
     F.y_off = in_b;
     F.w_off = in_b + vec_b;
     const size_t all_b = in_b + 2 * vec_b;
     SPK_HIP(S->dpool.get(all_b, &F.dev));
     SPK_HIP(S->hpool.get(all_b, &F.pin));
     char *pin = (char *)F.pin;
+    if (batched) {
+        memcpy(pin, rq.data(), sizeof(BatchReq) * rq.size());
+        uint16_t *map = (uint16_t *)(pin + req_b);
+        for (size_t k = 0; k < rq.size(); ++k)
+            std::fill(map + rq[k].first, map + rq[k].first + (int64_t)S->mats[group[k].second.mat].tiles.size(),
+                      (uint16_t)k);
+    }
     std::vector<CopyPool::Chunk> cp;
-    cp.push_back({pin, tiles.data(), sizeof(BatchTile) * tiles.size()});
     for (size_t k = 0; k < group.size(); ++k) {
         const Request &R = group[k].second;
         const PoolMat &M = S->mats[R.mat];
-        cp.push_back({pin + tile_b + vs * F.off[k], R.x, vs * (size_t)M.n});
+        cp.push_back({pin + head_b + vs * F.off[k], R.x, vs * (size_t)M.n});
     }
     S->copies.copy(cp);
     hipStream_t s = S->streams[S->next_stream];
@@ -371,7 +392,7 @@ spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &gro
     }
     char *dev = (char *)F.dev;
     SPK_HIP(hipMemcpyAsync(dev, pin, in_b, hipMemcpyHostToDevice, s));
-    const void *x = dev + tile_b;
+    const void *x = dev + head_b;
     void *y = dev + F.y_off;
     void *w = dev + F.w_off;
     if (S->opts.mode == 1) {
@@ -386,8 +407,8 @@ spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &gro
         SPK_TRY(run_spmv(S->h, q, pv, s));
         SPK_TRY(run_waxpy(S->h, M.dtype, M.m, S->opts.alpha, y, x, w, plain_variant(SPK_OP_WAXPY, 0), s));
     } else {
-        SPK_TRY(launch_tiles(S->entry, dtype, (const BatchTile *)dev, (int64_t)tiles.size(), S->opts.alpha, x, y,
-                             w, kBatchGrid, nullptr, 0, s));
+        SPK_TRY(launch_tiles(S->entry, dtype, nullptr, ntiles, S->opts.alpha, x, y, w, kBatchGrid, nullptr, 0, s,
+                             (const BatchReq *)dev, (const uint16_t *)(dev + req_b)));
     }
     SPK_HIP(hipMemcpyAsync(pin + F.y_off, y, 2 * vec_b, hipMemcpyDeviceToHost, s));
     F.done = take_event(S);
@@ -558,6 +579,7 @@ spk_status spk_serve_create(spk_handle h, const spk_serve_opts *opts, spk_server
     if (o.streams <= 0) o.streams = 4;
     if (o.max_inflight <= 0) o.max_inflight = 256;
     if (o.max_batch <= 0) o.max_batch = 64;
+    if (o.max_batch > 4096) return fail(SPK_ERR_ARG, "max_batch above 4096");
     if (o.hbm_budget <= 0) o.hbm_budget = 200ll * 1000 * 1000 * 1000;
     if (o.mode != 0 && o.mode != 1) return fail(SPK_ERR_ARG, "mode must be 0 or 1");
     if (o.streams > 16) return fail(SPK_ERR_ARG, "at most 16 streams");
@@ -630,6 +652,7 @@ spk_status spk_serve_add_matrix(spk_server S, const spk_csr *A, int32_t *id)
     spk_variant v{};
     if (spk_plan_get(S->h, batch_key(M.dtype, cls).c_str(), &v) == SPK_OK) mode = v.group;
     cut_rows(M.h_rp, M.m, mode, batch_wave_entries(*S->entry), 1024, M.tiles);
+    M.dev_bytes += (int64_t)(sizeof(BatchTile) * M.tiles.size());
     std::lock_guard<std::mutex> lk(S->mats_mu);
     if (M.dev_bytes + vec_bytes_of(M) > S->opts.hbm_budget) {
         if (M.h_pinned) {
@@ -791,6 +814,7 @@ spk_status spk_serve_destroy(spk_server S)
             (void)hipFree(M.d_rp);
             (void)hipFree(M.d_ci);
             (void)hipFree(M.d_val);
+            if (M.d_tiles) (void)hipFree(M.d_tiles);
         }
         if (M.uploaded) (void)hipEventDestroy(M.uploaded);
         if (M.h_pinned) {
