@@ -11,9 +11,11 @@
 //   3. launches the admitted group as one batched tile kernel on the next of
 //      its streams, so groups admitted while others run overlap on the GPU.
 // The tile kernel is the batched one, with each matrix cut into tiles by the
-// kernel of its shape class, so a request's result does not depend on what
-// it was batched with.  Mode 1 is the baseline: one request at a time with
-// the plain unbatched kernels (SpMV, then WAXPY).
+// kernel of its shape class (the tiles live on the device with the matrix;
+// a launch names them through a small request table), so a request's
+// result does not depend on what it was batched with.  Mode 1 is the
+// baseline: one request at a time with the plain unbatched kernels (SpMV,
+// then WAXPY).
 #include <algorithm>
 #include <atomic>
 #include <chrono>
