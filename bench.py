@@ -708,12 +708,18 @@ TILE_KERNEL_SOURCES = ["kernels_batch.hip", "device_rows.h", "device_common.h", 
 
 
 def tile_kernel_hash() -> str:
+    """Hash of the code (comments and whitespace removed) of the files that
+    define the batched tile kernel."""
     import hashlib
+    import re
     h = hashlib.sha1()
     for f in TILE_KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1309_1894_amd", "csrc", f), "rb") as fh:
-            h.update(f.encode())
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1309_1894_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(f.encode())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:12]
 
 

@@ -3,8 +3,9 @@
 // The host planner cuts every instance into tiles (row ranges) and gives
 // each tile the kernel chosen for the instance's shape class: an LDS-staged
 // row stream (mode 0) or G lanes per row (mode G).  The kernel either runs
-// one workgroup per tile, or is persistent: a grid sized to fill the GPU
-// pulls tiles from a queue head in device memory until the queue is empty.
+// one workgroup per group of tiles (one tile per wavefront), or is
+// persistent: a grid sized to fill the GPU pulls tiles from queue heads in
+// device memory until the queues are empty.
 // The queue head and a completion counter are left at zero by the last
 // workgroup to finish, so the launch can be captured in a hipGraph and
 // replayed without a reset node.
@@ -18,14 +19,14 @@
 
 namespace spk {
 
-// Tiles are wavefront-sized: every wavefront of a workgroup runs its own
-// tile, with its own slice of the workgroup's LDS (TILE/(BS/64) products and
-// 129 row offsets), and no workgroup barrier.
 // Tiles per run when tile groups are dealt to the XCDs (measured on the
 // 4096-instance banded batch: runs of 32 to 128 tiles stream 5% faster than
 // contiguous eighths, and 2-3% faster than dealing single groups).
 constexpr int kXcdRunTiles = 64;
 
+// Tiles are wavefront-sized: every wavefront of a workgroup runs its own
+// tile, with its own slice of the workgroup's LDS (TILE/(BS/64) products and
+// 129 row offsets), and no workgroup barrier.
 template <typename T, int BS, int TILE>
 struct WaveTiles {
     static constexpr int NW = BS / kWave;        // wavefronts per workgroup
