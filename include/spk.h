@@ -128,7 +128,8 @@ typedef struct {
  *   unroll  independent loads in flight per lane (1, 2, 4 or 8)
  *   vec     vector ops: elements per lane load (1, 2 or 4; at most 16 bytes)
  *   grid    vector ops: 0 = one pass, else workgroups per compute unit of a
- *           grid-stride launch
+ *           grid-stride launch (either way at most 2^30 work-items: past
+ *           that the kernels loop over the grid, so any n is covered)
  *   streams SpMV: split rows over this many streams (1, 2 or 4)
  *   lds     SpMV VECTOR: 1 = stage row_ptr in LDS; ADAPTIVE: LDS row-stream
  *           capacity in entries per wavefront (the "L1 size" knob; gfx950

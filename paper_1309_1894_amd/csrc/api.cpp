@@ -221,10 +221,7 @@ spk_status run_waxpy(spk_handle h, int dtype, int64_t n, double alpha, const voi
     L.x = x;
     L.y = y;
     L.w = w;
-    const int64_t per = vec_per_block(*e);
-    int64_t g = (n + per - 1) / per;
-    if (vv.grid > 0) g = std::min<int64_t>(g, (int64_t)vv.grid * h->num_cu);
-    L.grid = std::max<int64_t>(1, g);
+    L.grid = vec_grid(*e, n, vv.grid, h->num_cu);
     SPK_HIP(e->fn[dtype](L, s));
     return SPK_OK;
 }
@@ -260,10 +257,7 @@ spk_status run_dot(spk_handle h, int dtype, int64_t n, const void *x, const void
     if (vv.vec > 1 && (((uintptr_t)x | (uintptr_t)y) % bytes) != 0) vv.vec = 1;
     const VecEntry *e = find_vec_entry(SPK_OP_DOT, dtype, vv);
     if (!e) return fail(SPK_ERR_NOT_FOUND, "dot variant not compiled");
-    const int64_t per = vec_per_block(*e);
-    int64_t g = (n + per - 1) / per;
-    if (vv.grid > 0) g = std::min<int64_t>(g, (int64_t)vv.grid * h->num_cu);
-    g = std::max<int64_t>(1, g);
+    const int64_t g = vec_grid(*e, n, vv.grid, h->num_cu);
     DotScratch *d = nullptr;
     SPK_TRY(dot_scratch(h, s, g, &d));
     VecLaunch L{};
