@@ -420,7 +420,9 @@ typedef struct {
 /* Plans the batch: instances -> shape classes -> tiles, each class served by
  * the variant recorded for it (see spk_batch_tune), tiles ordered largest
  * first.  The descriptor arrays are copied; the device arrays are borrowed
- * for the batch's lifetime. */
+ * for the batch's lifetime.  A batch runs as one launch of at most 2^24
+ * wavefront tiles (a dispatch counts its work-items in 32 bits); one that
+ * needs more is rejected with SPK_ERR_SHAPE and should be split. */
 spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *desc, const spk_batch_opts *opts,
                           spk_batch *out);
 
@@ -477,7 +479,10 @@ spk_status spk_serve_create(spk_handle h, const spk_serve_opts *opts, spk_server
 
 /* Adds a matrix to the server's pool.  A's arrays are host memory and are
  * copied; the matrix is uploaded (made resident) when a request needs it
- * and evicted, least recently used first, only while idle. */
+ * and evicted, least recently used first, only while idle.  SPK_ERR_SHAPE
+ * for a non-square matrix, nnz >= 2^31, nrows >= 2^30 or more than 2^24
+ * wavefront tiles (the most one launch takes; a launch's requests together
+ * stay within it). */
 spk_status spk_serve_add_matrix(spk_server s, const spk_csr *A, int32_t *id);
 
 /* Submits one request: y = A_id*x, w = alpha*y + x.  x is host memory of

@@ -336,9 +336,14 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
         cut = split_rows(p.mat, m, parts, v.format == SPK_FMT_SELL ? v.group : 1);
     }
 
-    auto launch_piece = [&](int i, hipStream_t st) -> spk_status {
-        const int64_t lo = cut[i], hi = cut[i + 1];
-        if (hi <= lo) return SPK_OK;
+    // Rows (or ADAPTIVE row blocks) covered by one workgroup.  A range whose
+    // launch would exceed kMaxLaunchItems work-items (e.g. a wavefront per
+    // row over more than 2^24 rows) is run as consecutive launches.
+    const int64_t unit = v.format == SPK_FMT_ADAPTIVE ? v.block / 64
+                         : v.format == SPK_FMT_VECTOR ? v.block / v.group : v.block;
+    const int64_t span = kMaxLaunchItems / v.block * unit;
+
+    auto launch_range = [&](int64_t lo, int64_t hi, hipStream_t st) -> spk_status {
         union {
             SpmvArgs<float> f;
             SpmvArgs<double> d;
@@ -353,15 +358,10 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
                 a.blocks = bd->blk;
                 a.block_k = bd->bk;
                 a.blk0 = (int32_t)lo;
-                a.nblk = (int32_t)(hi - lo);
-                const int64_t nw = v.block / 64;   // one wavefront tile per wavefront
-                grid = dim3((unsigned)((hi - lo + nw - 1) / nw));
+                a.nblk = (int32_t)(hi - lo);   // one wavefront tile per wavefront
             } else {
                 a.row0 = (int32_t)lo;
                 a.m = (int32_t)(hi - lo);
-                int64_t rows_per_block = v.block;
-                if (v.format == SPK_FMT_VECTOR) rows_per_block = v.block / v.group;
-                grid = dim3((unsigned)((hi - lo + rows_per_block - 1) / rows_per_block));
                 if (sd) {
                     a.sell_ptr = sd->ptr;
                     a.sell_len = sd->len;
@@ -371,7 +371,13 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
             }
         };
         if (dtype == SPK_F64) setup(args.d); else setup(args.f);
+        grid = dim3((unsigned)((hi - lo + unit - 1) / unit));
         SPK_HIP(fn(dtype == SPK_F64 ? (const void *)&args.d : (const void *)&args.f, grid, st));
+        return SPK_OK;
+    };
+    auto launch_piece = [&](int i, hipStream_t st) -> spk_status {
+        for (int64_t lo = cut[i]; lo < cut[i + 1]; lo += span)
+            SPK_TRY(launch_range(lo, std::min(cut[i + 1], lo + span), st));
         return SPK_OK;
     };
 

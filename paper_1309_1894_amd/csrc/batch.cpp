@@ -129,6 +129,9 @@ spk_status launch_tiles(const BatchEntry *e, int dtype, const BatchTile *d_tiles
                         hipStream_t s, const BatchReq *reqs, const uint16_t *req_of_tile)
 {
     if (ntiles == 0) return SPK_OK;
+    if (ntiles > kMaxLaunchTiles)
+        return fail(SPK_ERR_SHAPE, "%lld tiles are more than one launch takes (%lld)", (long long)ntiles,
+                    (long long)kMaxLaunchTiles);
     if (reqs && kind != kBatchGrid) return fail(SPK_ERR_ARG, "request tables need the grid launch");
     union {
         BatchArgs<float> f;
@@ -208,6 +211,9 @@ spk_status replan(spk_batch b)
     b->tiles.clear();
     for (int64_t i = 0; i < b->count; ++i) cut_instance(b, i, b->mode[b->cls[i]], b->tiles);
     invalidate_graph(b);
+    if ((int64_t)b->tiles.size() > kMaxLaunchTiles)
+        return fail(SPK_ERR_SHAPE, "the batch needs %lld tiles, more than one launch takes (%lld): split it",
+                    (long long)b->tiles.size(), (long long)kMaxLaunchTiles);
     return upload_tiles(b, b->tiles);
 }
 

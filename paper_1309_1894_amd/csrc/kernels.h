@@ -50,16 +50,23 @@ constexpr int64_t kDotTicketMaxGrid = 16;
 // Elements covered by one workgroup in one pass.
 inline int64_t vec_per_block(const VecEntry &e) { return (int64_t)e.block * e.vec * e.unroll; }
 
+// Most work-items in one launch: a dispatch's size in work-items is a
+// 32-bit quantity, so larger problems loop in the kernel (vector ops) or are
+// split over several launches (SpMV row ranges).
+constexpr int64_t kMaxLaunchItems = (int64_t)1 << 30;
+// Most wavefront tiles in one batched launch (one wavefront per tile).
+constexpr int64_t kMaxLaunchTiles = kMaxLaunchItems / 64;
+
 // Workgroups of a vector-op launch over n elements: one pass (a workgroup
 // per vec_per_block elements) or at most `per_cu` per compute unit, and in
-// any case at most 2^30 work-items, the launch's size in work-items being a
-// 32-bit quantity; the kernels loop over the grid, so every n is covered.
+// any case at most kMaxLaunchItems work-items; the kernels loop over the
+// grid, so every n is covered.
 inline int64_t vec_grid(const VecEntry &e, int64_t n, int per_cu, int num_cu)
 {
     const int64_t per = vec_per_block(e);
     int64_t g = (n + per - 1) / per;
     if (per_cu > 0) g = g < (int64_t)per_cu * num_cu ? g : (int64_t)per_cu * num_cu;
-    const int64_t cap = ((int64_t)1 << 30) / e.block;
+    const int64_t cap = kMaxLaunchItems / e.block;
     if (g > cap) g = cap;
     return g > 1 ? g : 1;
 }

@@ -395,13 +395,14 @@ bool admit(Server *S)
     std::vector<std::pair<int64_t, Request>> group;
     std::vector<int32_t> keep;
     int group_dtype = -1;
-    int64_t group_vec = 0;
+    int64_t group_vec = 0, group_tiles = 0;
     const int64_t max_group = S->opts.mode == 1 ? 1 : S->opts.max_batch;
     while (!S->pending.empty() && (int64_t)group.size() < max_group &&
            S->inflight + (int64_t)group.size() < S->opts.max_inflight) {
         const Request &R = S->pending.front().second;
         PoolMat &M = S->mats[R.mat];
         if (group_dtype >= 0 && M.dtype != group_dtype) break;
+        if (!group.empty() && group_tiles + (int64_t)M.tiles.size() > kMaxLaunchTiles) break;
         const int64_t need = group_vec + vec_bytes_of(M) + (M.resident ? 0 : M.dev_bytes);
         keep.push_back(R.mat);
         if (!make_room(S, need, keep)) {
@@ -419,6 +420,7 @@ bool admit(Server *S)
         M.last_use = now_seconds();
         group_dtype = M.dtype;
         group_vec += vec_bytes_of(M);
+        group_tiles += (int64_t)M.tiles.size();
         group.push_back(S->pending.front());
         S->pending.pop_front();
     }
@@ -539,6 +541,15 @@ spk_status spk_serve_add_matrix(spk_server S, const spk_csr *A, int32_t *id)
     for (int64_t k = 0; k < A->nnz; ++k)
         if (A->col_idx[k] < 0 || A->col_idx[k] >= A->ncols) return fail(SPK_ERR_CSR, "column index out of range");
     PoolMat M;
+    // tiles by the plan of the matrix's shape class
+    const int cls = batch_class(A->nrows, A->nnz);
+    int mode = batch_default_mode(cls, batch_wave_entries(*S->entry));
+    spk_variant v{};
+    if (spk_plan_get(S->h, batch_key(A->dtype, cls).c_str(), &v) == SPK_OK) mode = v.group;
+    cut_rows(rp, A->nrows, mode, batch_wave_entries(*S->entry), 1024, M.tiles);
+    if ((int64_t)M.tiles.size() > kMaxLaunchTiles)
+        return fail(SPK_ERR_SHAPE, "the matrix needs %lld tiles, more than one launch takes",
+                    (long long)M.tiles.size());
     M.dtype = A->dtype;
     M.m = A->nrows;
     M.n = A->ncols;
@@ -557,7 +568,12 @@ spk_status spk_serve_add_matrix(spk_server S, const spk_csr *A, int32_t *id)
         M.h_rp = (int32_t *)malloc(brp);
         M.h_ci = (int32_t *)malloc(bci);
         M.h_val = malloc(bv);
-        if (!M.h_rp || !M.h_ci || !M.h_val) return fail(SPK_ERR_OOM, "host copy of the matrix");
+        if (!M.h_rp || !M.h_ci || !M.h_val) {
+            free(M.h_rp);
+            free(M.h_ci);
+            free(M.h_val);
+            return fail(SPK_ERR_OOM, "host copy of the matrix");
+        }
     }
     memcpy(M.h_rp, A->row_ptr, brp);
     if (M.nnz) {
@@ -565,12 +581,6 @@ spk_status spk_serve_add_matrix(spk_server S, const spk_csr *A, int32_t *id)
         memcpy(M.h_val, A->val, vs * M.nnz);
     }
     M.dev_bytes = (int64_t)(brp + bci + bv);
-    // tiles by the plan of the matrix's shape class
-    const int cls = batch_class(M.m, M.nnz);
-    int mode = batch_default_mode(cls, batch_wave_entries(*S->entry));
-    spk_variant v{};
-    if (spk_plan_get(S->h, batch_key(M.dtype, cls).c_str(), &v) == SPK_OK) mode = v.group;
-    cut_rows(M.h_rp, M.m, mode, batch_wave_entries(*S->entry), 1024, M.tiles);
     M.dev_bytes += (int64_t)(sizeof(BatchTile) * M.tiles.size());
     std::lock_guard<std::mutex> lk(S->mats_mu);
     if (M.dev_bytes + vec_bytes_of(M) > S->opts.hbm_budget) {
