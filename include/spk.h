@@ -420,7 +420,10 @@ typedef struct {
 /* Plans the batch: instances -> shape classes -> tiles, each class served by
  * the variant recorded for it (see spk_batch_tune), tiles ordered largest
  * first.  The descriptor arrays are copied; the device arrays are borrowed
- * for the batch's lifetime.  A batch runs as one launch of at most 2^24
+ * for the batch's lifetime.  Each instance's row_ptr is checked (starts at
+ * 0, never decreases, ends at nnz: SPK_ERR_CSR otherwise); column indices
+ * are not (as in spk_spmv_csr, one outside [0, m_i) reads outside the
+ * instance's x).  A batch runs as one launch of at most 2^24
  * wavefront tiles (a dispatch counts its work-items in 32 bits); one that
  * needs more is rejected with SPK_ERR_SHAPE and should be split. */
 spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *desc, const spk_batch_opts *opts,

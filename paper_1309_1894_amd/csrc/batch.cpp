@@ -167,6 +167,10 @@ namespace {
 
 void invalidate_graph(spk_batch b)
 {
+    // a replay may still be queued on any of the caller's streams: let it
+    // finish before its executable graph goes (rare: a change of x, y, w,
+    // alpha or of the plan)
+    if (b->exec) (void)hipDeviceSynchronize();
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
@@ -311,6 +315,10 @@ spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *d, const spk_batch
         const int32_t *rp = b->rp_host.data() + b->rp_off[i];
         if (rp[0] != 0 || rp[b->m[i]] != b->nnz[i])
             return bail(fail(SPK_ERR_CSR, "instance %lld: row_ptr does not span [0, nnz]", (long long)i));
+        for (int64_t r = 0; r < b->m[i]; ++r)
+            if (rp[r + 1] < rp[r])
+                return bail(fail(SPK_ERR_CSR, "instance %lld: row_ptr decreases at row %lld", (long long)i,
+                                 (long long)r));
     }
     b->cls.resize((size_t)b->count);
     for (int64_t i = 0; i < b->count; ++i) {

@@ -171,7 +171,36 @@ hipEvent_t take_event(Server *S)
 
 int64_t vec_bytes_of(const PoolMat &M) { return (M.n + 2 * M.m) * (int64_t)dtype_size(M.dtype); }
 
+void free_device_copy(PoolMat &M)
+{
+    if (M.d_rp) (void)hipFree(M.d_rp);
+    if (M.d_ci) (void)hipFree(M.d_ci);
+    if (M.d_val) (void)hipFree(M.d_val);
+    if (M.d_tiles) (void)hipFree(M.d_tiles);
+    M.d_rp = M.d_ci = nullptr;
+    M.d_val = nullptr;
+    M.d_tiles = nullptr;
+}
+
+spk_status upload(Server *S, PoolMat &M);
+
 spk_status make_resident(Server *S, PoolMat &M)
+{
+    const spk_status st = upload(S, M);
+    if (st != SPK_OK) {
+        // nothing of a failed upload stays allocated (copies already queued finish first)
+        (void)hipStreamSynchronize(S->upload);
+        free_device_copy(M);
+        return st;
+    }
+    M.resident = true;
+    M.upload_done = false;
+    S->used_mat += M.dev_bytes;
+    ++S->uploads;
+    return SPK_OK;
+}
+
+spk_status upload(Server *S, PoolMat &M)
 {
     const size_t vs = dtype_size(M.dtype);
     SPK_HIP(hipMalloc(&M.d_rp, sizeof(int32_t) * (M.m + 1)));
@@ -196,10 +225,6 @@ spk_status make_resident(Server *S, PoolMat &M)
     }
     if (!M.uploaded) SPK_HIP(hipEventCreateWithFlags(&M.uploaded, hipEventDisableTiming));
     SPK_HIP(hipEventRecord(M.uploaded, S->upload));
-    M.resident = true;
-    M.upload_done = false;
-    S->used_mat += M.dev_bytes;
-    ++S->uploads;
     return SPK_OK;
 }
 
@@ -207,13 +232,7 @@ void evict(Server *S, PoolMat &M)
 {
     // idle: no launch references it (refs == 0 and its last launch retired)
     (void)hipEventSynchronize(M.uploaded);
-    (void)hipFree(M.d_rp);
-    (void)hipFree(M.d_ci);
-    (void)hipFree(M.d_val);
-    if (M.d_tiles) (void)hipFree(M.d_tiles);
-    M.d_rp = M.d_ci = nullptr;
-    M.d_val = nullptr;
-    M.d_tiles = nullptr;
+    free_device_copy(M);
     M.resident = false;
     S->used_mat -= M.dev_bytes;
     ++S->evictions;
@@ -432,7 +451,18 @@ bool admit(Server *S)
         S->peak = std::max(S->peak, S->used_mat + S->used_vec);
     }
     spk_status st = launch_group(S, group);
-    if (st != SPK_OK) set_error(S, st);
+    if (st != SPK_OK) {
+        // the group never reaches a flight: release it and count its
+        // requests as rejected, so that waiters are not left behind
+        set_error(S, st);
+        for (const auto &g : group) S->mats[g.second.mat].refs--;
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->inflight -= (int64_t)group.size();
+        S->used_vec -= group_vec;
+        S->rejected += (int64_t)group.size();
+        S->completed += (int64_t)group.size();
+        S->cv_done.notify_all();
+    }
     return true;
 }
 
@@ -739,12 +769,7 @@ spk_status spk_serve_destroy(spk_server S)
         (void)hipStreamDestroy(S->upload);
     }
     for (PoolMat &M : S->mats) {
-        if (M.resident) {
-            (void)hipFree(M.d_rp);
-            (void)hipFree(M.d_ci);
-            (void)hipFree(M.d_val);
-            if (M.d_tiles) (void)hipFree(M.d_tiles);
-        }
+        free_device_copy(M);
         if (M.uploaded) (void)hipEventDestroy(M.uploaded);
         if (M.h_pinned) {
             (void)hipHostFree(M.h_rp);

@@ -1,6 +1,8 @@
 """Batched execution: one (persistent, graph-replayed) launch over many CSR
 instances matches the oracle per instance, and gives every instance the same
 bits as running it alone."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -145,6 +147,13 @@ def test_batch_rejects_bad_options(spk, dev):
     for kw in ({"persistent": 2}, {"persistent": -1}, {"block": 96}, {"tile_nnz": -5}):
         with pytest.raises(spk.SpkError, match="SPK_ERR_ARG"):
             spk.Batch(B, arrays, **kw)
+    # a row_ptr that decreases inside an instance is refused at planning
+    i = int(np.argmax(B.m > 2))
+    rp = B.row_ptr.copy()
+    o = int(B.rp_off[i])
+    rp[o + 1] = rp[o + 2] + 1
+    with pytest.raises(spk.SpkError, match="SPK_ERR_CSR"):
+        spk.Batch(dataclasses.replace(B, row_ptr=rp), arrays)
 
 
 def test_full_batched_workload_sampled(spk, dev):
