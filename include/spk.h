@@ -411,7 +411,11 @@ typedef struct {
                               * workgroup per group of wavefront tiles; other
                               * values are rejected (SPK_ERR_ARG) */
     int32_t use_graph;       /* 1 (default): replay a captured hipGraph */
-    int32_t block;           /* threads per workgroup (0 -> 256) */
+    int32_t block;           /* threads per workgroup; 0 -> the launch shape
+                              * spk_batch_tune recorded for the dtype
+                              * (workgroup size, LDS tile and launch kind,
+                              * which then replaces `persistent`), else 256
+                              * threads with 2048-entry tiles */
     int32_t tile_nnz;        /* target entries per tile of the lane-group
                               * modes (0 -> 1024) */
     int32_t waves_per_cu;    /* persistent residency (0 -> from occupancy) */
@@ -435,9 +439,15 @@ spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *desc, const spk_ba
 spk_status spk_batch_run(spk_handle h, spk_batch b, double alpha, const void *x, void *y, void *w,
                          spk_stream stream);
 
-/* Tunes the tile kernel per shape class on this batch (Section 2's search
- * applied to each class separately), validating every candidate against
- * the current plan's output, then re-plans the tiles. */
+/* Tunes the batch (Section 2's search): the launch shape (workgroup size,
+ * LDS tile per workgroup, grid or persistent kind) on the whole batch, then
+ * the tile kernel of each shape class under it, then the launch shape again
+ * with the tuned kernels; every candidate is validated against the current
+ * plan's output before it is timed.  Re-plans the tiles.  With
+ * opts->record the winners go to the plan DB: one plan per class
+ * ("batch:<dtype>:c<class>") and the launch shape ("batch:<dtype>:launch":
+ * block, lds = LDS tile entries per workgroup, grid = 1 for the persistent
+ * kind), which later plans with block 0 take. */
 spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x, void *y, void *w,
                           const spk_tune_opts *opts, spk_tune_report *report);
 
@@ -446,7 +456,9 @@ spk_status spk_batch_info(spk_handle h, spk_batch b, int64_t *tiles, int32_t *cl
                           int64_t *bytes);
 
 /* The launch configuration the batch currently uses (after planning or
- * tuning): persistence, graph use, workgroup size and LDS tile. */
+ * tuning): persistence, graph use and workgroup size; here tile_nnz is the
+ * kernel's LDS tile in entries per workgroup and waves_per_cu the
+ * persistent kind's residency. */
 spk_status spk_batch_config(spk_handle h, spk_batch b, spk_batch_opts *out);
 
 spk_status spk_batch_free(spk_handle h, spk_batch b);

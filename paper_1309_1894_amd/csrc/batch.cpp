@@ -68,6 +68,14 @@ std::string batch_key(int dtype, int cls)
     return b;
 }
 
+// Plan-DB key of the launch shape spk_batch_tune found for a dtype: block =
+// threads per workgroup, lds = LDS tile entries per workgroup, grid = 1 for
+// the persistent launch kind.
+static std::string batch_launch_key(int dtype)
+{
+    return std::string("batch:") + dtype_name(dtype) + ":launch";
+}
+
 const BatchEntry *batch_entry(int block, int tile)
 {
     int n = 0;
@@ -268,12 +276,22 @@ spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *d, const spk_batch
     if (opts) {
         o = *opts;
     }
-    if (o.block == 0) o.block = 256;
+    // block 0: the launch shape recorded by spk_batch_tune for this dtype,
+    // if any (workgroup size, LDS tile and launch kind), else 256 threads
+    // with 2048-entry tiles
+    const BatchEntry *e = nullptr;
+    if (o.block == 0) {
+        spk_variant lv{};
+        if (spk_plan_get(h, batch_launch_key(d->dtype).c_str(), &lv) == SPK_OK &&
+            (e = batch_entry(lv.block, lv.lds)) != nullptr)
+            o.persistent = lv.grid ? kBatchPersistent : kBatchGrid;
+        o.block = e ? e->block : 256;
+    }
     if (o.tile_nnz == 0) o.tile_nnz = 1024;
     if (o.persistent != kBatchGrid && o.persistent != kBatchPersistent)
         return fail(SPK_ERR_ARG, "persistent must be 0 or 1 (got %d)", o.persistent);
     if (o.tile_nnz < 0 || o.waves_per_cu < 0) return fail(SPK_ERR_ARG, "negative tile_nnz or waves_per_cu");
-    const BatchEntry *e = batch_entry(o.block, 2048);
+    if (!e) e = batch_entry(o.block, 2048);
     if (!e) return fail(SPK_ERR_ARG, "no batched kernel with block %d", o.block);
 
     int64_t rp_total = 0;
@@ -565,6 +583,14 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
             spk_plan_put(h, key.c_str(), &v);
             db_append(h, key, v, kv.second);
         }
+        spk_variant lv{};
+        lv.block = b->entry->block;
+        lv.lds = b->entry->tile;
+        lv.grid = b->opts.persistent == kBatchPersistent ? 1 : 0;
+        lv.streams = 1;
+        const std::string key = batch_launch_key(b->dtype);
+        spk_plan_put(h, key.c_str(), &lv);
+        db_append(h, key, lv, total_best);
     }
     // leave a full-batch result in the caller's buffers
     SPK_TRY(launch(b, (int64_t)b->tiles.size(), alpha, x, y, w, s));

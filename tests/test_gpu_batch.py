@@ -117,8 +117,28 @@ def test_batch_tune_per_class(spk, dev):
         b.run(0.5, xd, y, w)
         torch.cuda.synchronize()
         _check_batch(B, x, y, w, 0.5)
-        # winners are filed per class in the plan DB
+        # winners are filed per class in the plan DB, and so is the launch shape
         assert any(spk.spk_plan_get(f"batch:f64:c{c}", handle=h) is not None for c in range(8))
+        lv = spk.spk_plan_get("batch:f64:launch", handle=h)
+        tuned = b.config()
+        assert lv is not None and (lv.block, lv.lds, lv.grid) == (tuned["block"], tuned["tile_nnz"],
+                                                                   tuned["persistent"])
+        # a later plan with block 0 takes the recorded shape; an explicit block does not
+        b2 = spk.Batch(B, arrs, handle=h, block=0, persistent=not tuned["persistent"])
+        b3 = spk.Batch(B, arrs, handle=h, block=256)
+        try:
+            c2, c3 = b2.config(), b3.config()
+            assert (c2["block"], c2["tile_nnz"], c2["persistent"]) == (tuned["block"], tuned["tile_nnz"],
+                                                                       tuned["persistent"])
+            assert (c3["block"], c3["tile_nnz"]) == (256, 2048)
+            y.fill_(float("nan"))
+            w.fill_(float("nan"))
+            b2.run(0.5, xd, y, w)
+            torch.cuda.synchronize()
+            _check_batch(B, x, y, w, 0.5)
+        finally:
+            b2.free()
+            b3.free()
     finally:
         b.free()
         h.close()
