@@ -543,7 +543,10 @@ class Batch:
 
     def __init__(self, host_batch, device_arrays, persistent=True, use_graph=True, block=256, tile_nnz=2048,
                  handle=None):
-        """``host_batch``: inputs.Batch (sizes/offsets); ``device_arrays``: (row_ptr, col_idx, val) tensors."""
+        """``host_batch``: inputs.Batch (sizes/offsets); ``device_arrays``: (row_ptr, col_idx, val) tensors.
+        The keywords fill spk_batch_opts; ``tile_nnz`` defaults to 2048 here
+        (0 gives the library's 1024) and ``block=0`` takes the launch shape a
+        recorded spk_batch_tune found."""
         self.handle = handle or default_handle()
         rp, ci, val = device_arrays
         self._host = [np.ascontiguousarray(a, dtype=np.int64) for a in
