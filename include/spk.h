@@ -490,7 +490,7 @@ typedef struct {
  * owns the GPU side, and three threads that share its host copies between
  * the callers' buffers and pinned staging memory.  spk_serve_destroy joins
  * them all.  The server keeps a small record of every request submitted
- * (arrival and completion times, about 64 bytes) for spk_serve_stats_get and
+ * (arrival and completion times, under 64 bytes) for spk_serve_stats_get and
  * spk_serve_latencies until it is destroyed. */
 spk_status spk_serve_create(spk_handle h, const spk_serve_opts *opts, spk_server *out);
 
