@@ -176,25 +176,40 @@ def test_batch_rejects_bad_options(spk, dev):
         spk.Batch(dataclasses.replace(B, row_ptr=rp), arrays)
 
 
-def test_full_batched_workload_sampled(spk, dev):
-    """The full 4096-instance batch: sampled instances against the oracle."""
+def test_full_batched_workload(spk, dev):
+    """The full 4096-instance batch, every instance against the oracle: with
+    the default launch, then tuned and launched exactly as the bench times it
+    (persistent and graph requested, spk_batch_tune with the bench's
+    repetitions, graph replays)."""
     B = I.batch_banded(4096)
     x = I.batch_vector(B, seed=43)
     say(f"full batch: {int(B.m.sum())} rows, {int(B.nnz.sum())} nnz")
+    yr, _, absum = O.batch_spmv_waxpy(B, x, 0.5)
     xd = torch.from_numpy(x).to(dev)
     y = torch.empty(x.size, dtype=torch.float64, device=dev)
     w = torch.empty_like(y)
-    b = spk.Batch(B, _dev_batch(B, dev))
+    h = spk.Handle(0)
+    b = spk.Batch(B, _dev_batch(B, dev), persistent=True, use_graph=True, handle=h)
+
+    def check(what):
+        yg, wg = y.cpu().numpy(), w.cpu().numpy()
+        bad, worst, at = O.check_rows(yg, yr, absum, O.TAU_F64)
+        assert bad == 0, f"{what}: {bad} rows (worst {worst:g} at {at})"
+        d, at = O.max_ulp(wg, O.waxpy(0.5, yg, x))   # w from the GPU's own y: one fused rounding
+        assert d == 0, (what, d, at)
+
     try:
         b.run(0.5, xd, y, w)
         torch.cuda.synchronize()
-        yg, wg = y.cpu().numpy(), w.cpu().numpy()
-        idx = sorted(set(np.random.default_rng(1).integers(0, 4096, 24).tolist()) | {0, 4095})
-        for i in idx:
-            A = B.instance(i)
-            o = int(B.vec_off[i])
-            yr, wr, absum = O.spmv_waxpy(A, x[o:o + A.nrows], 0.5)
-            assert O.check_rows(yg[o:o + A.nrows], yr, absum, O.TAU_F64)[0] == 0, i
-            assert O.max_ulp(wg[o:o + A.nrows], O.waxpy(0.5, yg[o:o + A.nrows], x[o:o + A.nrows]))[0] == 0
+        check("default launch")
+        b.tune(0.5, xd, y, w, reps=10, warmup=2)
+        say(f"tuned launch: {b.config()}")
+        y.fill_(float("nan"))
+        w.fill_(float("nan"))
+        for _ in range(3):
+            b.run(0.5, xd, y, w)
+        torch.cuda.synchronize()
+        check("tuned launch")
     finally:
         b.free()
+        h.close()
