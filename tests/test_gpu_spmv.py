@@ -195,16 +195,29 @@ def test_register_validation(spk, dev):
 
 @pytest.mark.parametrize("which", ["lap3d_128", "zipf_1M"])
 def test_full_size_workloads(spk, dev, which):
-    """Workload matrices at full size, with the default and the plain kernels."""
+    """Workload matrices at full size, with the default and the plain
+    kernels, then tuned as the bench tunes them (CSR formats, cold cache):
+    the winner and the default dispatch that follows its recorded plan."""
     A = I.lap3d(128) if which == "lap3d_128" else I.zipf(1000000)
     say(f"full-size {which}: m={A.nrows} nnz={A.nnz}")
     x = I.uniform(31 if which == "lap3d_128" else 34, 0, A.ncols)
-    M = spk.Matrix(A)
+    h = spk.Handle(0)
+    M = spk.Matrix(A, handle=h)
     xd = torch.from_numpy(x).to(dev)
     y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
     try:
+        p = spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y)
         for v in [None, spk.spk_plain_variant(spk.SPK_OP_SPMV, 0), spk.spk_plain_variant(spk.SPK_OP_SPMV, 1)]:
-            spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), v)
+            y.fill_(float("nan"))
+            spk.spk_run(p, v, handle=h)
+            _check(A, x, y)
+        rep = spk.spk_tune(p, reps=10, warmup=2, flush=True, record=True, formats=spk.CSR_FORMATS, handle=h)
+        say(f"full-size {which}: tuned {rep.best}")
+        assert rep.rejected == 0
+        for v in [rep.best, None]:
+            y.fill_(float("nan"))
+            spk.spk_run(p, v, handle=h)
             _check(A, x, y)
     finally:
         M.release()
+        h.close()

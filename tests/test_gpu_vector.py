@@ -126,3 +126,44 @@ def test_plain_mode_and_tuned_dispatch(spk, dev):
         assert O.max_ulp(w2.cpu().numpy(), O.waxpy(1.5, x, y))[0] == 0
     finally:
         h.close()
+
+
+@pytest.mark.parametrize("dt", [1, 0])
+def test_vector_ops_at_2_pow_27_as_benched(spk, dev, dt):
+    """WAXPY, AXPY and dot at n = 2^27 on the bench's inputs, tuned as the
+    bench tunes them; the winners and the default dispatch (which follows
+    the recorded plan) against the oracle."""
+    n = 1 << 27
+    npdt = np.float64 if dt == 1 else np.float32
+    say(f"vector ops n=2^27 dtype={npdt.__name__}")
+    xh, yh = I.uniform(21, 0, n, npdt), I.uniform(22, 0, n, npdt)
+    x, y = torch.from_numpy(xh).to(dev), torch.from_numpy(yh).to(dev)
+    w = torch.empty_like(x)
+    d = torch.empty(1, dtype=torch.float64, device=dev)
+    h = spk.Handle(0)
+    ulp = 0 if dt == 1 else 1
+    try:
+        ref_w = O.waxpy(1.5, xh, yh)
+        ref_d = O.dot(xh, yh)
+        scale = O.dot_absum(xh, yh)
+        for op in (spk.SPK_OP_WAXPY, spk.SPK_OP_AXPY, spk.SPK_OP_DOT):
+            p = spk.problem(op, x=x, y=y, w=w if op == spk.SPK_OP_WAXPY else None,
+                            d_result=d if op == spk.SPK_OP_DOT else None, alpha=1.5)
+            rep = spk.spk_tune(p, reps=5, warmup=1, flush=False, record=True, handle=h)
+            assert rep.rejected == 0
+            for v in (rep.best, None):
+                if op == spk.SPK_OP_WAXPY:
+                    w.fill_(float("nan"))
+                    spk.spk_run(p, v, handle=h)
+                    assert O.max_ulp(w.cpu().numpy(), ref_w)[0] <= ulp, (op, v)
+                elif op == spk.SPK_OP_AXPY:
+                    y.copy_(torch.from_numpy(yh))   # in place: start from the input again
+                    spk.spk_run(p, v, handle=h)
+                    assert O.max_ulp(y.cpu().numpy(), ref_w)[0] <= ulp, (op, v)
+                    y.copy_(torch.from_numpy(yh))
+                else:
+                    d.fill_(float("nan"))
+                    spk.spk_run(p, v, handle=h)
+                    assert abs(d.item() - ref_d) <= O.tau_for(npdt) * scale, (op, v, d.item(), ref_d)
+    finally:
+        h.close()
