@@ -269,12 +269,25 @@ def test_cg_errors(spk, dev):
 
 def test_cg_full_size_lap3d_128(spk, dev):
     """The benchmark system: 7-point Laplacian on 128^3 (2,097,152 rows),
-    50 iterations, against the oracle at full size."""
+    50 iterations, against the oracle at full size: with the default tile
+    shape, then as the bench runs it -- the CSR tile shape tuned by
+    spk_cg_tune, and the matrix-free stencil form tuned the same way."""
     A = I.lap3d(128)
     b, x0 = _vecs(A, 12)
     say("cg lap3d 128, 50 iterations")
-    M = spk.Matrix(A)
-    x, hist = _run(spk, M, b, x0, 50, dev)
-    xo, ho = O.cg(A, b, 50, x0)
-    _compare(x, hist, xo, ho)
-    M.release()
+    h = spk.Handle(0)
+    M = spk.Matrix(A, handle=h)
+    try:
+        xo, ho = O.cg(A, b, 50, x0)
+        x, hist = _run(spk, M, b, x0, 50, dev)
+        _compare(x, hist, xo, ho)
+        bd = torch.from_numpy(b).to(dev)
+        for fmt in (spk.SPK_FMT_ADAPTIVE, spk.SPK_FMT_STENCIL):
+            rep = spk.spk_cg_tune(M, bd, 10, reps=5, warmup=1, formats=1 << fmt)
+            say(f"cg lap3d 128 tuned: {rep.best}")
+            assert rep.best.format == fmt and rep.rejected == 0
+            x, hist = _run(spk, M, b, x0, 50, dev)
+            _compare(x, hist, xo, ho)
+    finally:
+        M.release()
+        h.close()
