@@ -221,3 +221,52 @@ def test_full_size_workloads(spk, dev, which):
     finally:
         M.release()
         h.close()
+
+
+def test_krylov_step_lap2d_256_as_benched(spk, dev):
+    """The 2-D step (lap2d(256), w = 0.5*y + x) tuned as the bench tunes it:
+    the CSR winner through the default dispatch, the structured winner, and
+    1,000 captured steps replayed from a HIP graph, all against the oracle."""
+    A = I.lap2d(256)
+    x = I.uniform(11, 0, A.nrows)
+    say("krylov step lap2d(256) as benched")
+    h = spk.Handle(0)
+    M = spk.Matrix(A, handle=h)
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+    w = torch.empty_like(y)
+    try:
+        p = spk.problem(spk.SPK_OP_SPMV_WAXPY, A=M, x=xd, y=y, w=w, alpha=0.5)
+        rep = spk.spk_tune(p, reps=20, warmup=3, formats=spk.CSR_FORMATS, handle=h)
+        assert rep.rejected == 0
+        for v in (rep.best, None):
+            y.fill_(float("nan"))
+            w.fill_(float("nan"))
+            spk.spk_run(p, v, handle=h)
+            _check(A, x, y, w, 0.5)
+        mask = M.formats() & ((1 << spk.SPK_FMT_DIA) | (1 << spk.SPK_FMT_STENCIL))
+        st = spk.spk_tune(p, reps=20, warmup=3, record=False, formats=mask, handle=h)
+        y.fill_(float("nan"))
+        w.fill_(float("nan"))
+        spk.spk_run(p, st.best, handle=h)
+        yr, wr, _ = O.spmv_waxpy(A, x, 0.5)
+        assert np.array_equal(y.cpu().numpy(), yr) and np.array_equal(w.cpu().numpy(), wr)   # sorted rows: exact
+        # graph replay of the recorded plan, as the bench times it
+        cs = torch.cuda.Stream()
+        cs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cs):
+            spk.spk_spmv_waxpy(M, 0.5, xd, y, w)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=cs):
+            for _ in range(1000):
+                spk.spk_spmv_waxpy(M, 0.5, xd, y, w)
+        y.fill_(float("nan"))
+        w.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        _check(A, x, y, w, 0.5)
+        del g
+    finally:
+        M.release()
+        h.close()
