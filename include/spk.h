@@ -93,11 +93,22 @@ typedef enum {
     SPK_FMT_DIA = 5,        /* diagonal storage: at most 16 diagonals, one value per
                              * (diagonal, row) plus a 16-bit presence mask per row;
                              * `block` threads, `unroll` rows per lane (1, 2) */
-    SPK_FMT_STENCIL = 6     /* matrix-free: a constant-coefficient 3-, 5- or 7-point
+    SPK_FMT_STENCIL = 6,    /* matrix-free: a constant-coefficient 3-, 5- or 7-point
                              * stencil on a 1-, 2- or 3-D grid with Dirichlet
                              * truncation (only the coefficients are stored);
                              * `block` threads, `unroll` rows per lane (1..8),
                              * `lds` 1 = x staged through LDS */
+    SPK_FMT_COLBLOCK = 7    /* column-blocked CSR (FP64 registered matrices): the
+                             * matrix split by column ranges into `group` (2 or 4)
+                             * sub-matrices of all rows, built on first use; one
+                             * pass per block with the ADAPTIVE kernel (`block`
+                             * threads, `lds` entries per wavefront) into FP64
+                             * partials kept per stream, then one pass adds them
+                             * in block order (and forms w).  Each pass gathers
+                             * from one slice of x only, which pays when x is
+                             * larger than an XCD's L2.  Same algorithmic bytes
+                             * as CSR; not listed by spk_variant_get, searched
+                             * by spk_tune (`formats`) when x exceeds 4 MiB */
 } spk_format;
 
 typedef void *spk_stream;                 /* hipStream_t */

@@ -75,6 +75,20 @@ const SpmvEntry *find_spmv_entry(const spk_variant &v)
     return nullptr;
 }
 
+// The per-block kernel of a column-blocked variant: the ADAPTIVE row-block
+// kernel with the variant's workgroup size and wavefront capacity.
+spk_variant colblock_inner(const spk_variant &v)
+{
+    spk_variant iv{};
+    iv.format = SPK_FMT_ADAPTIVE;
+    iv.block = v.block;
+    iv.group = 1;
+    iv.unroll = 1;
+    iv.streams = 1;
+    iv.lds = v.lds;
+    return iv;
+}
+
 spk_status check_variant(int op, int dtype, const spk_variant &v)
 {
     if (op == SPK_OP_WAXPY || op == SPK_OP_AXPY || op == SPK_OP_DOT) {
@@ -90,6 +104,14 @@ spk_status check_variant(int op, int dtype, const spk_variant &v)
                 return fail(SPK_ERR_NOT_FOUND,
                             "no compiled structured SpMV variant format=%d block=%d unroll=%d lds=%d", v.format,
                             v.block, v.unroll, v.lds);
+            return SPK_OK;
+        }
+        if (v.format == SPK_FMT_COLBLOCK) {
+            if (dtype != SPK_F64) return fail(SPK_ERR_DTYPE, "the column-blocked form is FP64 only");
+            if (v.group != 2 && v.group != 4) return fail(SPK_ERR_ARG, "column blocks must be 2 or 4 (got %d)", v.group);
+            if (v.streams != 1) return fail(SPK_ERR_ARG, "the column-blocked form runs on one stream");
+            if (!find_spmv_entry(colblock_inner(v)))
+                return fail(SPK_ERR_NOT_FOUND, "no compiled row-block kernel block=%d lds=%d", v.block, v.lds);
             return SPK_OK;
         }
         if (!find_spmv_entry(v))
@@ -312,6 +334,7 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
     const int dtype = p.mat ? p.mat->dtype : p.csr->dtype;
     if (m == 0) return SPK_OK;
     if (v.format == SPK_FMT_DIA || v.format == SPK_FMT_STENCIL) return run_structured(h, p, v, s);
+    if (v.format == SPK_FMT_COLBLOCK) return run_colblock(h, p, v, s);
     const SpmvEntry *e = find_spmv_entry(v);
     if (!e) return fail(SPK_ERR_NOT_FOUND, "SpMV variant not compiled");
     if (!p.mat && (v.format == SPK_FMT_SELL || v.format == SPK_FMT_ADAPTIVE))
@@ -517,6 +540,128 @@ spk_status get_blocks(spk_handle h, spk_mat *A, int entries, BlockData **out)
     return SPK_OK;
 }
 
+// ------------------------------------------------------- column blocks --
+
+// Frees a matrix and everything derived from it.
+static void free_mat(spk_mat *A)
+{
+    (void)hipFree(A->rp);
+    (void)hipFree(A->ci);
+    (void)hipFree(A->val);
+    for (auto &kv : A->sell) {
+        (void)hipFree(kv.second.ptr);
+        (void)hipFree(kv.second.len);
+        (void)hipFree(kv.second.ci);
+        (void)hipFree(kv.second.val);
+    }
+    for (auto &kv : A->blocks) {
+        (void)hipFree(kv.second.blk);
+        (void)hipFree(kv.second.bk);
+    }
+    if (A->dia.val) (void)hipFree(A->dia.val);
+    if (A->dia.mask) (void)hipFree(A->dia.mask);
+    for (auto &kv : A->colblk) {
+        for (spk_mat *S : kv.second.sub) free_mat(S);
+        for (auto &pp : kv.second.part) (void)hipFree(pp.second);
+    }
+    delete A;
+}
+
+// Sub-matrices of A by column range ([b*n/nblk, (b+1)*n/nblk) for block b),
+// each holding every row, built from a host copy of A's entries; they are
+// owned by A, not listed with the handle's matrices.
+static spk_status get_colblock(spk_handle h, spk_mat *A, int nblk, ColBlockData **out)
+{
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        auto it = A->colblk.find(nblk);
+        if (it != A->colblk.end()) {
+            *out = &it->second;
+            return SPK_OK;
+        }
+    }
+    const int64_t m = A->nrows, n = A->ncols, nnz = A->nnz;
+    std::vector<int32_t> ci((size_t)std::max<int64_t>(1, nnz));
+    std::vector<double> val((size_t)std::max<int64_t>(1, nnz));
+    if (nnz > 0) {
+        SPK_HIP(hipDeviceSynchronize());
+        SPK_HIP(hipMemcpy(ci.data(), A->ci, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+        SPK_HIP(hipMemcpy(val.data(), A->val, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+    }
+    ColBlockData d;
+    auto bail = [&](spk_status st) {
+        for (spk_mat *S : d.sub) free_mat(S);
+        return st;
+    };
+    const std::vector<int32_t> &rp = A->rp_host;
+    for (int b = 0; b < nblk; ++b) {
+        const int64_t lo = n * b / nblk, hi = n * (b + 1) / nblk;
+        std::vector<int32_t> srp((size_t)m + 1, 0), sci;
+        std::vector<double> sval;
+        for (int64_t i = 0; i < m; ++i) {
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+                if (ci[k] >= lo && ci[k] < hi) {
+                    sci.push_back(ci[k]);
+                    sval.push_back(val[k]);
+                }
+            srp[i + 1] = (int32_t)sci.size();
+        }
+        spk_csr view{m, n, (int64_t)sci.size(), SPK_F64, srp.data(), sci.empty() ? nullptr : sci.data(),
+                     sval.empty() ? nullptr : sval.data()};
+        spk_matrix S = nullptr;
+        const spk_status st = spk_matrix_register(h, &view, 0, 0, &S);
+        if (st != SPK_OK) return bail(st);
+        {
+            std::lock_guard<std::mutex> lk(h->mu);
+            h->mats.erase(S);
+        }
+        d.sub.push_back(S);
+    }
+    std::lock_guard<std::mutex> lk(h->mu);
+    auto it = A->colblk.find(nblk);
+    if (it != A->colblk.end()) {
+        for (spk_mat *S : d.sub) free_mat(S);   // built meanwhile by another call
+        *out = &it->second;
+        return SPK_OK;
+    }
+    *out = &A->colblk.emplace(nblk, std::move(d)).first->second;
+    return SPK_OK;
+}
+
+spk_status run_colblock(spk_handle h, const SpmvProblem &p, const spk_variant &v, hipStream_t s)
+{
+    spk_mat *A = p.mat;
+    if (!A) return fail(SPK_ERR_ARG, "the column-blocked form needs a registered matrix");
+    if (A->dtype != SPK_F64) return fail(SPK_ERR_DTYPE, "the column-blocked form is FP64 only");
+    const int nblk = v.group;
+    const int64_t m = A->nrows;
+    ColBlockData *cb = nullptr;
+    SPK_TRY(get_colblock(h, A, nblk, &cb));
+    double *part = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        auto it = cb->part.find(s);
+        if (it != cb->part.end()) part = it->second;
+    }
+    if (!part) {
+        SPK_HIP(hipMalloc(&part, sizeof(double) * (size_t)nblk * (size_t)m));
+        std::lock_guard<std::mutex> lk(h->mu);
+        cb->part[s] = part;
+    }
+    const spk_variant iv = colblock_inner(v);
+    for (int b = 0; b < nblk; ++b) {
+        SpmvProblem q;
+        q.mat = cb->sub[b];
+        q.fused = false;
+        q.x = p.x;
+        q.y = part + (int64_t)b * m;
+        SPK_TRY(run_spmv(h, q, iv, s));
+    }
+    SPK_HIP(launch_colblock_sum(nblk, m, part, (double *)p.y, p.fused ? (double *)p.w : nullptr, (const double *)p.x,
+                                p.alpha, s));
+    return SPK_OK;
+}
+
 // --------------------------------------------------------------- plan DB --
 
 void db_load(spk_handle h)
@@ -648,26 +793,6 @@ spk_status spk_create(int device, const char *db_path, spk_handle *out)
     db_load(h);
     *out = h;
     return SPK_OK;
-}
-
-static void free_mat(spk_mat *A)
-{
-    (void)hipFree(A->rp);
-    (void)hipFree(A->ci);
-    (void)hipFree(A->val);
-    for (auto &kv : A->sell) {
-        (void)hipFree(kv.second.ptr);
-        (void)hipFree(kv.second.len);
-        (void)hipFree(kv.second.ci);
-        (void)hipFree(kv.second.val);
-    }
-    for (auto &kv : A->blocks) {
-        (void)hipFree(kv.second.blk);
-        (void)hipFree(kv.second.bk);
-    }
-    if (A->dia.val) (void)hipFree(A->dia.val);
-    if (A->dia.mask) (void)hipFree(A->dia.mask);
-    delete A;
 }
 
 spk_status spk_destroy(spk_handle h)

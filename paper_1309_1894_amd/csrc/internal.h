@@ -63,6 +63,14 @@ struct SellData {
     int64_t bytes = 0;
 };
 
+// Column-blocked form of a matrix (SPK_FMT_COLBLOCK): sub-matrices of all
+// rows holding the entries of one column range each (built on first use),
+// and the FP64 partial results, nblk * nrows doubles per stream.
+struct ColBlockData {
+    std::vector<spk_mat *> sub;
+    std::map<hipStream_t, double *> part;
+};
+
 struct BlockData {
     uint32_t *blk = nullptr;    // nblk + 1 entries (start row | mode << 30)
     int32_t *bk = nullptr;      // nblk + 1 entries (first entry of each block)
@@ -104,6 +112,7 @@ struct spk_mat {
     std::map<std::pair<int, int>, spk::BlockData> blocks;    // by (0, wavefront entries)
     spk::StructInfo st;
     spk::DiaData dia;                                        // built on first use
+    std::map<int, spk::ColBlockData> colblk;                 // by block count, built on first use
 };
 
 namespace spk {
@@ -199,6 +208,8 @@ struct SpmvProblem {
 };
 
 spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hipStream_t s);
+spk_status run_colblock(spk_handle h, const SpmvProblem &p, const spk_variant &v, hipStream_t s);
+spk_variant colblock_inner(const spk_variant &v);
 
 // Variant the dispatcher uses for a problem (the plan recorded for its
 // class, else the default).

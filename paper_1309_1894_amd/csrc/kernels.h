@@ -42,6 +42,11 @@ const VecEntry *dot_table(int *count);
 // partial[0, count) in a fixed order.
 hipError_t launch_dot_final(const double *partial, int64_t count, double *out, hipStream_t s);
 
+// Last pass of the column-blocked SpMV (FP64): y = sum of the nblk partials
+// part[b*m + i] in block order; w = alpha*y + x when w is not null.
+hipError_t launch_colblock_sum(int nblk, int64_t m, const double *part, double *y, double *w, const double *x,
+                               double alpha, hipStream_t s);
+
 // Largest dot grid finished by the ticket (each workgroup then publishes
 // its partial with a device-scope release, which writes back the XCD's L2
 // and serialises there); larger grids use launch_dot_final.

@@ -322,6 +322,27 @@ hipError_t launch_triad(int64_t n, const double *a, const double *b, double s_, 
     return hipGetLastError();
 }
 
+// Column-blocked SpMV, last pass: y_i = the row's partials over the column
+// blocks added in block order; with w, also w_i = alpha*y_i + x_i.
+__global__ __launch_bounds__(kBS) void k_colblock_sum(int nblk, int64_t m, const double *part, double *y, double *w,
+                                                      const double *x, double alpha)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBS) {
+        double acc = __builtin_nontemporal_load(part + i);
+        for (int b = 1; b < nblk; ++b) acc += __builtin_nontemporal_load(part + (int64_t)b * m + i);
+        __builtin_nontemporal_store(acc, y + i);
+        if (w) __builtin_nontemporal_store(__builtin_fma(alpha, acc, x[i]), w + i);
+    }
+}
+
+hipError_t launch_colblock_sum(int nblk, int64_t m, const double *part, double *y, double *w, const double *x,
+                               double alpha, hipStream_t s)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_colblock_sum, dim3(grid_for(m)), dim3(kBS), 0, s, nblk, m, part, y, w, x, alpha);
+    return hipGetLastError();
+}
+
 hipError_t launch_csr_colcheck(int64_t nnz, const int32_t *ci, int64_t ncols, unsigned long long *bad,
                                hipStream_t s)
 {

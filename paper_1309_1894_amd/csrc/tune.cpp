@@ -142,8 +142,27 @@ void candidate_space(const Ctx &c, uint32_t formats, std::vector<spk_variant> &o
         out.push_back(v);
     }
     if (!spmv) return;
-    // structured formats, when the matrix admits them
     const spk_mat *A = c.p.A;
+    // column blocks (FP64): only when x is larger than one XCD's L2, the
+    // case they are for; the per-block kernel from the row-block shapes
+    if ((!formats || (formats & (1u << SPK_FMT_COLBLOCK))) && format_applies(A, SPK_FMT_COLBLOCK)) {
+        if (A->ncols * (int64_t)sizeof(double) > ((int64_t)4 << 20)) {
+            for (int nb : {2, 4})
+                for (const auto &bl : {std::pair<int, int>{512, 256}, {128, 256}, {256, 1024}}) {
+                    spk_variant v{};
+                    v.format = SPK_FMT_COLBLOCK;
+                    v.block = bl.first;
+                    v.group = nb;
+                    v.unroll = 1;
+                    v.streams = 1;
+                    v.lds = bl.second;
+                    if (find_spmv_entry(colblock_inner(v))) out.push_back(v);
+                }
+        } else {
+            ++*pruned;
+        }
+    }
+    // structured formats, when the matrix admits them
     int ns = 0;
     const StructEntry *st = struct_table(&ns);
     for (int i = 0; i < ns; ++i) {
@@ -303,7 +322,8 @@ extern "C" spk_status spk_tune(spk_handle h, const spk_problem *problem, const s
         return SPK_OK;
     };
     for (const spk_variant &v : space) SPK_TRY(consider(v));
-    if (spmv && tried > 0 && bestv.format != SPK_FMT_DIA && bestv.format != SPK_FMT_STENCIL) {
+    if (spmv && tried > 0 && bestv.format != SPK_FMT_DIA && bestv.format != SPK_FMT_STENCIL &&
+        bestv.format != SPK_FMT_COLBLOCK) {
         // refinement: the winner split over 2 and 4 streams
         for (int s2 : {2, 4}) {
             spk_variant v = bestv;
