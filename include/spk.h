@@ -37,7 +37,8 @@
  *   - HIP graph capture: spk_spmv_*, spk_waxpy, spk_axpy, spk_dot, spk_run
  *     and spk_cg may be captured into a graph on the caller's stream.  What
  *     they build on first use (a matrix's derived formats, and the dot
- *     partials and CG scratch, which are kept per stream) is allocated then,
+ *     partials, column-block partials and CG scratch, which are kept per
+ *     stream) is allocated then,
  *     so make one eager call with the same matrix, size and stream before
  *     capturing: a first use inside a capture fails with SPK_ERR_HIP.  The
  *     captured launches record no memset nodes.

@@ -624,6 +624,7 @@ static spk_status get_colblock(spk_handle h, spk_mat *A, int nblk, ColBlockData 
         *out = &it->second;
         return SPK_OK;
     }
+    for (spk_mat *S : d.sub) A->bytes += S->bytes;
     *out = &A->colblk.emplace(nblk, std::move(d)).first->second;
     return SPK_OK;
 }
@@ -646,7 +647,14 @@ spk_status run_colblock(spk_handle h, const SpmvProblem &p, const spk_variant &v
     if (!part) {
         SPK_HIP(hipMalloc(&part, sizeof(double) * (size_t)nblk * (size_t)m));
         std::lock_guard<std::mutex> lk(h->mu);
-        cb->part[s] = part;
+        auto it = cb->part.find(s);
+        if (it != cb->part.end()) {
+            (void)hipFree(part);   // made meanwhile by another call on this stream
+            part = it->second;
+        } else {
+            cb->part[s] = part;
+            A->bytes += (int64_t)(sizeof(double) * (size_t)nblk * (size_t)m);
+        }
     }
     const spk_variant iv = colblock_inner(v);
     for (int b = 0; b < nblk; ++b) {

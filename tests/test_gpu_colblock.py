@@ -76,7 +76,10 @@ def test_column_blocks_two_streams_and_tuner(spk, dev):
         xd = torch.from_numpy(x).to(dev)
         y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
         p = spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y)
+        before = M.bytes()
         rep = spk.spk_tune(p, reps=3, warmup=1, formats=1 << spk.SPK_FMT_COLBLOCK, record=False, handle=h)
+        # the sub-matrices and partials are counted with the matrix
+        assert M.bytes() >= before + A.nnz * 12 + 2 * 8 * A.nrows
         assert rep.best.format == spk.SPK_FMT_COLBLOCK and rep.rejected == 0 and rep.tried >= 6
         _check(A, x, y)
         v2, v4 = _variants(spk)[0], _variants(spk)[3]
