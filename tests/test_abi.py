@@ -130,3 +130,29 @@ def test_binding_rejects_short_tensors():
         spk.spk_spmv_csr(torch.zeros(11, dtype=torch.int32), ci, val, x, y=short, nrows=10)
     with pytest.raises(ValueError, match="row_ptr holds 5"):
         spk.spk_spmv_csr(torch.zeros(5, dtype=torch.int32), ci, val, x, y=x, nrows=10)
+
+
+def test_binding_constants_match_the_header():
+    """Every SPK_* enumerator the binding names has the header's value."""
+    from paper_1309_1894_amd import spk
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    values = {}
+    for body in re.findall(r"typedef\s+enum\s*\{(.*?)\}", text, flags=re.S):
+        nxt = 0
+        for item in (x.strip() for x in body.split(",")):
+            if not item:
+                continue
+            name, _, val = item.partition("=")
+            nxt = int(val.strip(), 0) if val.strip() else nxt
+            values[name.strip()] = nxt
+            nxt += 1
+    assert values["SPK_FMT_COLBLOCK"] == 7 and values["SPK_ERR_STATE"] == 12
+    named = {k: getattr(spk, k) for k in dir(spk) if k.startswith("SPK_") and isinstance(getattr(spk, k), int)}
+    assert len(named) >= 15
+    for k, v in named.items():
+        if k in values:
+            assert v == values[k], k
+    for k in values:
+        if k.startswith(("SPK_FMT_", "SPK_OP_", "SPK_F")):
+            assert named.get(k) == values[k], k
+    assert spk.STATUS == {v: k for k, v in values.items() if k.startswith(("SPK_OK", "SPK_ERR_"))}
