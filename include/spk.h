@@ -154,34 +154,43 @@ typedef struct {
 
 /* ------------------------------------------------------------- library -- */
 
-/* SPK_ABI_VERSION of the loaded library. */
+/* SPK_ABI_VERSION of the loaded library.  Library plumbing, not in the
+ * paper. */
 int spk_abi_version(void);
 
-/* Human-readable name of a status code (static storage). */
+/* Human-readable name of a status code (static storage).  Library plumbing,
+ * not in the paper. */
 const char *spk_status_str(spk_status s);
 
 /* Creates a handle on HIP device `device`.  `db_path` (nullable) names a
- * tuning database file: winners found by spk_tune are appended there and
- * loaded by later handles; entries from another GPU architecture or library
- * build are ignored.  Environment: SPK_PLAIN=1 makes every call use the
- * fixed plain variants; SPK_DB_PATH supplies db_path when it is NULL. */
+ * tuning database file, where the outcome of Section 2's search is kept:
+ * winners found by spk_tune are appended there and loaded by later handles;
+ * entries from another GPU architecture or library build are ignored.
+ * Environment: SPK_PLAIN=1
+ * makes every call use the fixed plain variants; SPK_DB_PATH supplies
+ * db_path when it is NULL.  SPK_ERR_NULL without `out`; SPK_ERR_HIP when the
+ * device cannot be selected. */
 spk_status spk_create(int device, const char *db_path, spk_handle *out);
 
 /* Releases the handle and everything it owns (matrices and batches created
- * from it must be released first). */
+ * from it must be released first).  Library plumbing, not in the paper. */
 spk_status spk_destroy(spk_handle h);
 
-/* Message of the calling thread's last non-OK status (static per thread). */
+/* Message of the calling thread's last non-OK status (static per thread).
+ * Library plumbing, not in the paper. */
 const char *spk_last_error(void);
 
-/* Waits for `stream` and reports any asynchronous HIP error. */
+/* Waits for `stream` and reports any asynchronous HIP error.  Library
+ * plumbing, not in the paper. */
 spk_status spk_check(spk_handle h, spk_stream stream);
 
 /* Selects how untuned calls pick variants: 0 = plan DB, else built-in
- * default; 1 = always the fixed plain variants (the untuned baseline). */
+ * default; 1 = always the fixed plain variants, the analogue of Figure 1's
+ * baseline kernel without directives. */
 spk_status spk_set_plain(spk_handle h, int plain);
 
-/* Number of compute units, device name and measured-free info. */
+/* Number of compute units and device name (name_cap bytes, NUL-terminated).
+ * Library plumbing, not in the paper. */
 spk_status spk_device_info(spk_handle h, int32_t *num_cu, char *name, int32_t name_cap);
 
 /* ------------------------------------------------------- vector kernels -- */
@@ -194,41 +203,65 @@ spk_status spk_device_info(spk_handle h, int32_t *num_cu, char *name, int32_t na
 spk_status spk_waxpy(spk_handle h, int32_t dtype, int64_t n, double alpha,
                      const void *x, const void *y, void *w, spk_stream stream);
 
-/* AXPY: y_i <- alpha*x_i + y_i (WAXPY with w == y).  x may equal y. */
+/* AXPY: y_i <- alpha*x_i + y_i, the vector update of Figure 1 done in
+ * place (WAXPY with w == y), one fused rounding per element.  x, y: device
+ * arrays of n elements of `dtype`; x may equal y (then y_i <- (alpha+1)*y_i
+ * rounded once); any partial overlap is SPK_ERR_ALIAS.  For SPK_F32 alpha is
+ * rounded to float first.  n == 0 launches nothing; SPK_ERR_NULL for a NULL
+ * array with n > 0. */
 spk_status spk_axpy(spk_handle h, int32_t dtype, int64_t n, double alpha,
                     const void *x, void *y, spk_stream stream);
 
-/* Dot product d = sum_i x_i*y_i accumulated in FP64 and written to
- * d_result[0] (device, one double, also for SPK_F32).  The reduction order
- * is fixed for a given (n, variant), so repeated calls are bit-identical.
- * Calls on one handle and one stream are serialised by the stream; calls on
- * different streams use separate scratch. */
+/* Dot product d = sum_i x_i*y_i.  Not in the paper: one of the vector
+ * operations of the configured vector sweep, kept beside WAXPY/AXPY because
+ * a Krylov step needs it.  x, y: device arrays of n elements of `dtype`
+ * (may be the same array); the sum is accumulated in FP64 and written to
+ * d_result[0] (device, one double, also for SPK_F32; n == 0 writes 0).  The
+ * reduction order is fixed for a given (n, variant), so repeated calls are
+ * bit-identical.  The per-workgroup partial sums live in scratch the handle
+ * allocates per stream on first use.  Calls on one handle and one stream are
+ * serialised by the stream; calls on different streams use separate
+ * scratch. */
 spk_status spk_dot(spk_handle h, int32_t dtype, int64_t n, const void *x, const void *y,
                    double *d_result, spk_stream stream);
 
 /* ----------------------------------------------------------------- SpMV -- */
 
-/* y = A*x for a borrowed CSR matrix (all arrays device).  x has A->ncols
- * elements, y has A->nrows; both of A->dtype.  y must not overlap x
- * (SPK_ERR_ALIAS).  Only O(1) facts are checked; row_ptr/col_idx contents
- * are trusted (use spk_matrix_register(validate=1) to check them).  Formats
- * that need derived data (SELL, ADAPTIVE) are only available on registered
- * matrices, so this call uses the SCALAR/VECTOR families. */
+/* y = A*x for a borrowed CSR matrix: the sparse matrix-vector product of
+ * the prior GPU work that Section 3 cites (the paper's spmv_csr(A, x, y)).
+ * All arrays are device memory owned by the caller: row_ptr int32[nrows+1],
+ * col_idx int32[nnz], val[nnz], x[ncols] and y[nrows], all of A->dtype.
+ * y_i = sum over row i's stored entries of val_k * x[col_k], FP64
+ * accumulation (FP32 data rounded once); an empty row gives +0.  y must not
+ * overlap x (SPK_ERR_ALIAS).  Only O(1) facts are checked (pointers, sizes,
+ * dtype, aliasing); row_ptr/col_idx contents are trusted (use
+ * spk_matrix_register(validate=1) to check them).  nrows == 0 or
+ * ncols == 0 is valid (y is set to zeros when ncols == 0).  Formats that need
+ * derived data (SELL, ADAPTIVE, structured) are only available on
+ * registered matrices, so this call uses the SCALAR/VECTOR families. */
 spk_status spk_spmv_csr(spk_handle h, const spk_csr *A, const void *x, void *y, spk_stream stream);
 
 /* Copies a CSR matrix into library-owned device memory and derives the
  * metadata its formats need (row statistics, LDS row blocks, sliced ELL on
- * first use).  `where`: 0 = the arrays of A are host memory, 1 = device
- * memory.  validate != 0 checks row_ptr monotonicity, row_ptr[0] == 0,
- * row_ptr[nrows] == nnz and 0 <= col_idx < ncols (SPK_ERR_CSR otherwise).
- * The caller may free its arrays when this returns. */
+ * first use): the operand A of the sparse kernels of Section 3, kept
+ * resident so that repeated products (and the tuner's variant runs of
+ * Section 2) do not upload it again.  Beyond the spmv_csr(A, x, y)
+ * interface, the arrays may come from either side: `where` 0 = the arrays
+ * of A are host memory, 1 = device memory.  validate != 0 checks row_ptr
+ * monotonicity, row_ptr[0] == 0, row_ptr[nrows] == nnz and
+ * 0 <= col_idx < ncols (SPK_ERR_CSR otherwise).  The caller may free its
+ * arrays when this returns; the matrix is owned by the handle until
+ * spk_matrix_release.  Synchronises.  SPK_ERR_OOM when device memory runs
+ * out. */
 spk_status spk_matrix_register(spk_handle h, const spk_csr *A, int32_t where, int32_t validate,
                                spk_matrix *out);
 
+/* Frees a registered matrix and its derived formats.  Library plumbing, not
+ * in the paper. */
 spk_status spk_matrix_release(spk_handle h, spk_matrix A);
 
 /* Bytes of device memory held by a registered matrix (CSR plus derived
- * formats built so far). */
+ * formats built so far).  Library plumbing, not in the paper. */
 spk_status spk_matrix_bytes(spk_handle h, spk_matrix A, int64_t *bytes);
 
 /* Formats that apply to A, as a bitmask of (1 << spk_format): SCALAR,
@@ -237,8 +270,8 @@ spk_status spk_matrix_bytes(spk_handle h, spk_matrix A, int64_t *bytes);
  * exactly a constant-coefficient grid stencil: offsets {0, +-1} (1-D),
  * {0, +-1, +-s} (2-D, s | n) or {0, +-1, +-s, +-t} (3-D, s | t, t | n),
  * every neighbour inside the grid present, none outside, and one value per
- * offset.  The structure is detected at registration (section 3 of the
- * paper lists the storage format among the choices a tuner makes). */
+ * offset.  The structure is detected at registration (Section 3's prior
+ * GPU work counts the storage format among the choices a tuner makes). */
 spk_status spk_matrix_formats(spk_handle h, spk_matrix A, uint32_t *mask);
 
 /* The structure spk_matrix_register detects, computed from host arrays
@@ -246,7 +279,8 @@ spk_status spk_matrix_formats(spk_handle h, spk_matrix A, uint32_t *mask);
  * the diagonal offsets when DIA applies, and the grid and coefficients
  * (ascending offset order -N2*N3, -N3, -1, 0, +1, +N3, +N2*N3; absent
  * slots 0) when STENCIL applies.  row_ptr, col_idx and val of `csr` are
- * host pointers here. */
+ * host pointers here.  Structure detection for the storage-format choice of
+ * Section 3. */
 typedef struct {
     uint32_t formats;
     int32_t ndiag;
@@ -258,19 +292,28 @@ typedef struct {
 
 spk_status spk_csr_structure(const spk_csr *csr, spk_structure *out);
 
-/* Algorithmic bytes of one SpMV (fused: + the w stream) of A in `format`
+/* Measurement, not in the paper.  Algorithmic bytes of one SpMV (fused: +
+ * the w stream) of A in `format`
  * (SCALAR/VECTOR/ADAPTIVE: the CSR count; SELL: the CSR count; DIA:
  * ndiag*m values + 2m mask bytes; STENCIL: none for the matrix) plus x and
  * y.  SPK_ERR_ARG when the format does not apply to A. */
 spk_status spk_matrix_format_bytes(spk_handle h, spk_matrix A, int32_t format, int32_t fused, int64_t *bytes);
 
-/* y = A*x on a registered matrix, with the tuned variant of its shape class
- * (or the default when none is recorded). */
+/* y = A*x on a registered matrix (the sparse product of Section 3's prior
+ * GPU work), with the variant Section 2's search recorded for its shape
+ * class, or the built-in default when none is recorded.  x: device,
+ * A.ncols elements; y: device, A.nrows elements; both of A's dtype; y must
+ * not overlap x (SPK_ERR_ALIAS).  Asynchronous on `stream`; a format built
+ * on first use (sliced ELL, DIA, column blocks) is built then, on the same
+ * stream. */
 spk_status spk_spmv_mat(spk_handle h, spk_matrix A, const void *x, void *y, spk_stream stream);
 
-/* One Krylov-style step on a square registered matrix: y = A*x, then
- * w_i = alpha*y_i + x_i from the rounded y_i, in one kernel.  w must not
- * overlap x or y; y must not overlap x. */
+/* One Krylov-style step on a square registered matrix: the sparse product
+ * of Section 3 followed by the vector update of Figure 1, fused: y = A*x,
+ * then w_i = alpha*y_i + x_i (one rounding) from the rounded y_i, in one
+ * kernel.  x, y, w: device, A.nrows elements of A's dtype.  w must not
+ * overlap x or y; y must not overlap x (SPK_ERR_ALIAS); a non-square matrix
+ * is SPK_ERR_SHAPE. */
 spk_status spk_spmv_waxpy(spk_handle h, spk_matrix A, double alpha, const void *x, void *y,
                           void *w, spk_stream stream);
 
@@ -304,8 +347,12 @@ spk_status spk_cg(spk_handle h, spk_matrix A, const void *b, void *x, int32_t it
 
 /* ------------------------------------------------- variants and tuning -- */
 
-/* A problem for spk_run / spk_tune.  SPMV/SPMV_WAXPY use A (registered) and
- * x, y (and w); WAXPY uses x, y, w; AXPY x, y; DOT x, y and d_result. */
+/* A problem for spk_run / spk_tune: one call of an operation above, the
+ * unit Section 2's search runs, compares and times.  SPMV/SPMV_WAXPY use A
+ * (registered) and x, y (and w); WAXPY uses x, y, w; AXPY x, y; DOT x, y and
+ * d_result.  The operation travels inside the problem (`op`) rather than as
+ * a separate argument of spk_tune, so that spk_run and spk_tune share one
+ * description of it. */
 typedef struct {
     int32_t op;          /* spk_op */
     int32_t dtype;       /* vector ops; SpMV takes A's dtype */
@@ -318,13 +365,17 @@ typedef struct {
     double *d_result;
 } spk_problem;
 
-/* Runs `problem` with an explicit variant (NULL = the dispatcher's choice).
- * Used by the tuner and by tests that exercise every compiled variant. */
+/* Runs `problem` with an explicit variant (NULL = the dispatcher's choice):
+ * one code variant of Section 2's search.  Used by the tuner and by tests
+ * that exercise every compiled variant.  SPK_ERR_ARG for a variant outside
+ * the compiled space. */
 spk_status spk_run(spk_handle h, const spk_problem *problem, const spk_variant *variant,
                    spk_stream stream);
 
-/* The variant space compiled into the library for an op and dtype:
- * spk_variant_count gives its size, spk_variant_get the i-th point. */
+/* The variant space compiled into the library for an op and dtype (the
+ * parameter variations of Section 3: threads per block, unroll, streams,
+ * cache-sized staging, plus the storage format): spk_variant_count gives
+ * its size, spk_variant_get the i-th point. */
 spk_status spk_variant_count(int32_t op, int32_t dtype, int32_t *count);
 spk_status spk_variant_get(int32_t op, int32_t dtype, int32_t index, spk_variant *out);
 
@@ -371,10 +422,12 @@ typedef struct {
 spk_status spk_tune(spk_handle h, const spk_problem *problem, const spk_tune_opts *opts,
                     spk_tune_report *report);
 
-/* Shape class a problem is filed under in the plan DB (for inspection). */
+/* Shape class a problem is filed under in the plan DB (for inspection):
+ * where Section 2's selected variant is kept. */
 spk_status spk_class_key(spk_handle h, const spk_problem *problem, char *out, int32_t cap);
 
-/* Looks up / stores a plan DB entry directly. */
+/* Looks up / stores a plan DB entry directly (the record of Section 2's
+ * selected variant for a class). */
 spk_status spk_plan_get(spk_handle h, const char *class_key, spk_variant *out);
 spk_status spk_plan_put(spk_handle h, const char *class_key, const spk_variant *v);
 
@@ -402,7 +455,10 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
 
 /* ------------------------------------------------------------- batching -- */
 
-/* Many independent square CSR instances stored back to back (instance i:
+/* Batched execution is not in the paper: it is the configured batched
+ * workload, thousands of independent instances of Section 3's sparse
+ * product followed by Figure 1's update, run as one launch.
+ * Many independent square CSR instances stored back to back (instance i:
  * row_ptr[rp_off[i] .. rp_off[i]+m[i]] with values local to the instance,
  * entries col_idx/val[nz_off[i] .. nz_off[i]+nnz[i]) with local column
  * indices, vectors x/y/w[vec_off[i] .. vec_off[i]+m[i])).  Size and offset
@@ -433,7 +489,8 @@ typedef struct {
     int32_t waves_per_cu;    /* persistent residency (0 -> from occupancy) */
 } spk_batch_opts;
 
-/* Plans the batch: instances -> shape classes -> tiles, each class served by
+/* Plans the batch (not in the paper; the configured batched workload):
+ * instances -> shape classes -> tiles, each class served by
  * the variant recorded for it (see spk_batch_tune), tiles ordered largest
  * first.  The descriptor arrays are copied; the device arrays are borrowed
  * for the batch's lifetime.  Each instance's row_ptr is checked (starts at
@@ -445,8 +502,9 @@ typedef struct {
 spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *desc, const spk_batch_opts *opts,
                           spk_batch *out);
 
-/* One step over every instance: y = A_i*x_i, w = alpha*y + x (w may be NULL
- * for SpMV only), all instances in one launch.  With use_graph the launch is
+/* One step over every instance: Section 3's sparse product y = A_i*x_i,
+ * then Figure 1's update w = alpha*y + x (w may be NULL for SpMV only), all
+ * instances in one launch.  With use_graph the launch is
  * captured once per (x, y, w, alpha) and replayed. */
 spk_status spk_batch_run(spk_handle h, spk_batch b, double alpha, const void *x, void *y, void *w,
                          spk_stream stream);
@@ -463,20 +521,26 @@ spk_status spk_batch_run(spk_handle h, spk_batch b, double alpha, const void *x,
 spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x, void *y, void *w,
                           const spk_tune_opts *opts, spk_tune_report *report);
 
-/* Number of tiles and classes and the algorithmic bytes of one step. */
+/* Number of tiles and classes and the algorithmic bytes of one step.
+ * Library plumbing, not in the paper. */
 spk_status spk_batch_info(spk_handle h, spk_batch b, int64_t *tiles, int32_t *classes,
                           int64_t *bytes);
 
 /* The launch configuration the batch currently uses (after planning or
- * tuning): persistence, graph use and workgroup size; here tile_nnz is the
- * kernel's LDS tile in entries per workgroup and waves_per_cu the
- * persistent kind's residency. */
+ * tuning, Section 3's threads per block and blocks per grid): persistence,
+ * graph use and workgroup size; here tile_nnz is the kernel's LDS tile in
+ * entries per workgroup and waves_per_cu the persistent kind's residency. */
 spk_status spk_batch_config(spk_handle h, spk_batch b, spk_batch_opts *out);
 
+/* Frees a batch plan (its tiles, counters and captured graphs).  Library
+ * plumbing, not in the paper. */
 spk_status spk_batch_free(spk_handle h, spk_batch b);
 
 /* -------------------------------------------------------------- serving -- */
 
+/* Serving is not in the paper: it is the configured serving workload,
+ * requests for one Krylov-style step (Section 3's sparse product, then
+ * Figure 1's update) arriving over time and batched continuously. */
 typedef struct {
     int32_t streams;          /* device streams used concurrently (0 -> 4) */
     int32_t max_inflight;     /* request slots (0 -> 256) */
@@ -498,7 +562,8 @@ typedef struct {
     double bytes_moved;       /* algorithmic bytes of completed requests */
 } spk_serve_stats;
 
-/* Starts a serving loop on the handle's device: a scheduler thread, which
+/* Starts a serving loop (not in the paper; the configured serving
+ * workload) on the handle's device: a scheduler thread, which
  * owns the GPU side, and three threads that share its host copies between
  * the callers' buffers and pinned staging memory.  spk_serve_destroy joins
  * them all.  The server keeps a small record of every request submitted
@@ -506,7 +571,9 @@ typedef struct {
  * spk_serve_latencies until it is destroyed. */
 spk_status spk_serve_create(spk_handle h, const spk_serve_opts *opts, spk_server *out);
 
-/* Adds a matrix to the server's pool.  A's arrays are host memory and are
+/* Adds a matrix to the server's pool (the operand of Section 3's sparse
+ * product, kept resident while the budget allows).  A's arrays are host
+ * memory and are
  * copied; the matrix is uploaded (made resident) when a request needs it
  * and evicted, least recently used first, only while idle.  SPK_ERR_SHAPE
  * for a non-square matrix, nnz >= 2^31, nrows >= 2^30 or more than 2^24
@@ -514,40 +581,51 @@ spk_status spk_serve_create(spk_handle h, const spk_serve_opts *opts, spk_server
  * stay within it). */
 spk_status spk_serve_add_matrix(spk_server s, const spk_csr *A, int32_t *id);
 
-/* Submits one request: y = A_id*x, w = alpha*y + x.  x is host memory of
+/* Submits one request: y = A_id*x (Section 3's product), w = alpha*y + x
+ * (Figure 1's update).  x is host memory of
  * ncols elements (copied at admission); y and w are host memory of nrows
  * elements filled in before the request is reported complete.  The buffers
  * stay borrowed until then.  *req receives the request id. */
 spk_status spk_serve_submit(spk_server s, int32_t mat_id, const void *x, void *y, void *w,
                             int64_t *req);
 
-/* Completed request ids since the last poll (up to cap). */
+/* Completed request ids since the last poll (up to cap).  Serving plumbing,
+ * not in the paper. */
 spk_status spk_serve_poll(spk_server s, int64_t *ids, int32_t cap, int32_t *n);
 
-/* Blocks until every submitted request has completed. */
+/* Blocks until every submitted request has completed.  Serving plumbing,
+ * not in the paper. */
 spk_status spk_serve_drain(spk_server s);
 
-/* Open-loop replay: submits request i at arrival_s[i] seconds after the
- * call (by the library's own clock) and returns when all have completed. */
+/* Open-loop replay (measurement of the configured serving workload, not in
+ * the paper): submits request i at arrival_s[i] seconds after the call (by
+ * the library's own clock) and returns when all have completed. */
 spk_status spk_serve_replay(spk_server s, int64_t n, const double *arrival_s, const int32_t *mat_ids,
                             const void *const *x, void *const *y, void *const *w);
 
+/* Counters and latency percentiles of the server so far.  Measurement, not
+ * in the paper. */
 spk_status spk_serve_stats_get(spk_server s, spk_serve_stats *out);
 
-/* Per-request latency in microseconds, by request id (cap entries). */
+/* Per-request latency in microseconds, by request id (cap entries).
+ * Measurement, not in the paper. */
 spk_status spk_serve_latencies(spk_server s, double *out_us, int64_t cap, int64_t *n);
 
+/* Drains and stops the server, joins its threads and frees its device
+ * memory.  Serving plumbing, not in the paper. */
 spk_status spk_serve_destroy(spk_server s);
 
 /* --------------------------------------------------------- measurement -- */
 
-/* STREAM-style probes on device arrays of n doubles: kind 0 = copy
+/* Measurement, not in the paper.  STREAM-style probes on device arrays of
+ * n doubles: kind 0 = copy
  * (c = a; b unused), 1 = triad (c = a + 3*b).  Used for the measured
  * bandwidth roofline and to calibrate byte counters. */
 spk_status spk_stream_probe(spk_handle h, int32_t kind, int64_t n, const double *a, const double *b,
                             double *c, spk_stream stream);
 
-/* Reads a library-owned 512 MiB buffer (twice the last-level cache) so the
+/* Measurement, not in the paper.  Reads a library-owned 512 MiB buffer
+ * (twice the last-level cache) so the
  * next kernel starts with cold caches holding only clean lines: it pays for
  * its own misses and not for writing back someone else's dirty lines. */
 spk_status spk_flush_cache(spk_handle h, spk_stream stream);

@@ -62,7 +62,6 @@ def lib():
             "orc_spmv_csr_f32": (None, [_I64, _P, _P, _P, _P, _P, _P]),
             "orc_spmv_waxpy_f64": (None, [_I64, _P, _P, _P, _P, _D, _P, _P, _P]),
             "orc_batch_spmv_waxpy_f64": (None, [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _D, _P, _P, _P]),
-            "orc_batch_spmv_f32": (None, [_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
             "orc_max_ulp_f64": (_I64, [_I64, _P, _P, _P]),
             "orc_max_ulp_f32": (_I64, [_I64, _P, _P, _P]),
             "orc_check_rows": (_I64, [_I64, _P, _P, _P, _D, _P, _P]),
@@ -132,6 +131,8 @@ def dot(x: np.ndarray, y: np.ndarray) -> float:
 
 
 def dot_absum(x: np.ndarray, y: np.ndarray) -> float:
+    """sum_i |x_i*y_i|: the scale of the dot tolerance (the magnitude sum of
+    the same products the dot adds, as the per-row SpMV tolerance uses)."""
     dt = _fdt(x)
     x, y = _c(x, dt), _c(y, dt)
     f = lib().orc_dot_absum_f64 if dt == np.float64 else lib().orc_dot_absum_f32

@@ -240,18 +240,6 @@ ORC_API void orc_batch_spmv_waxpy_f64(int64_t count, const int64_t *m, const int
     }
 }
 
-ORC_API void orc_batch_spmv_f32(int64_t count, const int64_t *m, const int64_t *rp_off,
-                                const int64_t *nz_off, const int64_t *vec_off,
-                                const int32_t *row_ptr, const int32_t *col_idx,
-                                const float *val, const float *x, double *y, double *absum)
-{
-    for (int64_t b = 0; b < count; ++b) {
-        const int64_t vo = vec_off[b];
-        orc_spmv_csr_f32(m[b], row_ptr + rp_off[b], col_idx + nz_off[b], val + nz_off[b],
-                         x + vo, y + vo, absum ? absum + vo : NULL);
-    }
-}
-
 /* ---------------------------------------------------- acceptance checks -- */
 
 /* Monotone integer image of an IEEE double: ord(a) < ord(b) iff a < b for

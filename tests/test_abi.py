@@ -156,3 +156,31 @@ def test_binding_constants_match_the_header():
         if k.startswith(("SPK_FMT_", "SPK_OP_", "SPK_F")):
             assert named.get(k) == values[k], k
     assert spk.STATUS == {v: k for k, v in values.items() if k.startswith(("SPK_OK", "SPK_ERR_"))}
+
+
+CITES = re.compile(r"Section [1-4]|Figure 1|not in the paper|callers that cannot allocate")
+
+
+def declaration_comments():
+    """(function name, the comment that documents it) for every function the
+    header declares: the comment of the blank-line-separated paragraph the
+    declaration sits in, else the closest comment above it."""
+    text = open(HEADER).read()
+    out = []
+    last_comment = ""
+    for para in re.split(r"\n\s*\n", text):
+        comments = re.findall(r"/\*.*?\*/", para, flags=re.S)
+        if comments:
+            last_comment = comments[0]
+        code = re.sub(r"/\*.*?\*/", "", para, flags=re.S)
+        for name in re.findall(r"^\s*(?:spk_status|int|const char \*)\s*\**(spk_[a-z0-9_]+)\s*\(", code, flags=re.M):
+            out.append((name, " ".join(comments) if comments else last_comment))
+    return out
+
+
+def test_every_declaration_cites_the_paper_or_says_it_is_not_in_it():
+    decl = declaration_comments()
+    assert {n for n, _ in decl} == set(declared())
+    flat = lambda c: re.sub(r"\s+", " ", re.sub(r"^\s*\*(?!/)", " ", c, flags=re.M))
+    bad = [n for n, c in decl if not CITES.search(flat(c))]
+    assert not bad, bad

@@ -486,3 +486,118 @@ def test_cg_exact_solution_stays_put():
     b = 2.0 * x0
     x, hist = O.cg(A, b, 3, x0=x0)
     assert np.array_equal(x, x0) and np.all(hist == 0.0)
+
+
+# --- the scale of the dot tolerance: sum_i |x_i*y_i| -------------------------
+# Every dot parity test accepts |d - ref| <= tau * dot_absum(x, y), so a scale
+# that came out too large would loosen them silently.  The scale is pinned to
+# the exact rational magnitude sum; each of the n products is rounded once
+# (exact for FP32 operands) and the n - 1 additions once each.
+
+def _absum_exact(x, y):
+    return sum((abs(Fraction(float(a)) * Fraction(float(b))) for a, b in zip(x, y)), Fraction(0))
+
+
+def _absum_pinned(s, x, y, unit):
+    """Is s the sum of |x_i y_i| within (n+1)*unit of it?"""
+    ex = _absum_exact(x, y)
+    return abs(Fraction(s) - ex) <= Fraction(len(x) + 1) * Fraction(unit) * ex
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 4096, 10001])
+def test_dot_absum_vs_exact_rational(n):
+    x = I.uniform(21, 0, n)
+    y = I.uniform(22, 0, n)
+    s = O.dot_absum(x, y)
+    assert s >= 0.0
+    assert _absum_pinned(s, x, y, U64)
+    if n == 0:
+        assert s == 0.0
+
+
+def test_dot_absum_f32_widens_exactly():
+    n = 9000
+    x = I.uniform(21, 0, n, np.float32)
+    y = I.uniform(22, 0, n, np.float32)
+    s = O.dot_absum(x, y)
+    # FP32 products are exact in double: only the additions round
+    assert _absum_pinned(s, x, y, U64)
+    # and the FP32 value itself would not do: the products are formed in double
+    xs = x.astype(np.float64) * y.astype(np.float64)
+    assert np.any(xs != (x * y).astype(np.float64))
+
+
+@pytest.mark.parametrize("n", [1, 2, 1000, 4097, (1 << 20) + 1])
+def test_dot_absum_integer_closed_forms(n):
+    # alternating signs: sum |(-1)^i i * 1| = n(n-1)/2 although the dot itself
+    # is -(n//2) or (n-1)/2, so the absolute value must be taken per product
+    i = np.arange(n, dtype=np.float64)
+    alt = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    assert O.dot_absum(alt * i, np.ones(n)) == n * (n - 1) // 2
+    assert O.dot_absum(i, -alt) == n * (n - 1) // 2
+    assert O.dot(alt * i, np.ones(n)) == ((n - 1) // 2 if n % 2 else -(n // 2))
+    assert O.dot_absum(-np.ones(n), np.ones(n)) == n
+    # FP32 operands: exact integers, widened before the product
+    f = (alt * np.minimum(i, 4000)).astype(np.float32)
+    exact = int(np.sum(np.minimum(np.arange(n), 4000)))
+    assert O.dot_absum(f, np.full(n, -3, np.float32)) == 3 * exact
+
+
+def test_dot_absum_bounds_the_dot_error():
+    # the scale must be at least |sum x_i y_i| (triangle inequality) and is
+    # what the compensated dot's own error is measured against
+    x = I.uniform(31, 0, 50000)
+    y = I.uniform(32, 0, 50000)
+    s = O.dot_absum(x, y)
+    assert s >= abs(O.dot(x, y))
+    assert s == pytest.approx(float(np.sum(np.abs(x) * np.abs(y))), rel=1e-13)
+
+
+def test_dot_absum_mutations_fail_the_pin():
+    # plausible wrong scales, planted here on the CPU, fail the same pin
+    x = I.uniform(21, 0, 257)
+    y = I.uniform(22, 0, 257)
+    assert _absum_pinned(O.dot_absum(x, y), x, y, U64)
+    wrong_abs_of_sum = abs(O.dot(x, y))                              # |sum x y|
+    wrong_product_of_sums = float(np.sum(np.abs(x)) * np.sum(np.abs(y)))  # sum|x| * sum|y|
+    wrong_dropped_last = O.dot_absum(x[:-1], y[:-1])                 # one term short
+    wrong_signed_x = float(np.sum(np.abs(x) * y))                    # |.| on one operand only
+    for bad in (wrong_abs_of_sum, wrong_product_of_sums, wrong_dropped_last, wrong_signed_x):
+        assert not _absum_pinned(bad, x, y, U64), bad
+
+
+# Every function the oracle exports, and the tests above that pin it.
+PINNED_BY = {
+    "orc_num_threads": ["test_dot_thread_count_independent"],
+    "orc_set_num_threads": ["test_dot_thread_count_independent"],
+    "orc_waxpy_f64": ["test_waxpy_correctly_rounded", "test_waxpy_alpha_not_special_cased"],
+    "orc_waxpy_f32": ["test_waxpy_f32_rounds_from_exact"],
+    "orc_axpy_f64": ["test_axpy_is_waxpy_in_place"],
+    "orc_axpy_f32": ["test_axpy_is_waxpy_in_place"],
+    "orc_dot_f64": ["test_dot_vs_exact_rational", "test_dot_integer_closed_forms"],
+    "orc_dot_f32": ["test_dot_f32_vs_exact"],
+    "orc_dot_absum_f64": ["test_dot_absum_vs_exact_rational", "test_dot_absum_integer_closed_forms",
+                          "test_dot_absum_mutations_fail_the_pin"],
+    "orc_dot_absum_f32": ["test_dot_absum_f32_widens_exactly", "test_dot_absum_integer_closed_forms"],
+    "orc_spmv_csr_f64": ["test_spmv_matches_exact_rational", "test_lap2d_polynomial_closed_form",
+                         "test_lap3d_polynomial_closed_form", "test_identity_and_diagonal"],
+    "orc_spmv_csr_f32": ["test_spmv_f32_promotes_exactly"],
+    "orc_spmv_waxpy_f64": ["test_spmv_waxpy_step_definition"],
+    "orc_batch_spmv_waxpy_f64": ["test_batch_oracle_is_per_instance"],
+    "orc_max_ulp_f64": ["test_ulp_metric"],
+    "orc_max_ulp_f32": ["test_ulp_metric"],
+    "orc_check_rows": ["test_check_rows_semantics"],
+    "orc_cg_f64": ["test_cg_terminates_on_k_distinct_eigenvalues", "test_cg_matches_direct_solve_on_laplacian",
+                   "test_cg_first_step_closed_form", "test_cg_exact_solution_stays_put"],
+}
+
+
+def test_every_exported_oracle_function_is_pinned():
+    import re
+    src = open(O.SRC_PATH).read()
+    exported = set(re.findall(r"ORC_API\s+[\w\s\*]+?\b(orc_\w+)\s*\(", src))
+    assert exported == set(PINNED_BY), exported ^ set(PINNED_BY)
+    here = globals()
+    for name, tests in PINNED_BY.items():
+        for t in tests:
+            assert callable(here.get(t)), (name, t)
