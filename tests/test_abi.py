@@ -158,7 +158,7 @@ def test_binding_constants_match_the_header():
     assert spk.STATUS == {v: k for k, v in values.items() if k.startswith(("SPK_OK", "SPK_ERR_"))}
 
 
-CITES = re.compile(r"Section [1-4]|Figure 1|not in the paper|callers that cannot allocate")
+CITES = re.compile(r"Section [1-4]|Figure 1|[Nn]ot in the paper|callers that cannot allocate")
 
 
 def declaration_comments():
