@@ -28,6 +28,9 @@ def csr_from_entries(m, n, entries, dtype=np.float64):
 def edge_cases():
     rng = np.random.default_rng(11)
     out = {
+        "m0": csr_from_entries(0, 5, []),                 # no rows: nothing to write
+        "m0_n0": csr_from_entries(0, 0, []),
+        "n0": csr_from_entries(6, 0, []),                 # no columns: y = 0, x never read
         "1x1": csr_from_entries(1, 1, [(0, 0, 2.5)]),
         "empty_rows": csr_from_entries(7, 5, [(1, 0, 1.25), (1, 4, -3.0), (5, 2, 0.5)]),
         "all_empty": csr_from_entries(300, 300, []),
@@ -52,15 +55,26 @@ CASES = edge_cases()
 def _check(A, x, y_gpu, w_gpu=None, alpha=None, dt=1):
     ref, absum = O.spmv(A, x)
     yg = y_gpu.cpu().numpy()
+    assert yg.size == A.nrows
     bad, worst, at = O.check_rows(yg.astype(np.float64), ref, absum, O.tau_for(NP[dt]))
     assert bad == 0, f"{bad} rows outside tolerance (worst {worst:g} at row {at})"
     empty = np.diff(A.row_ptr) == 0
     assert np.all(yg[empty] == 0)
     if w_gpu is not None:
+        wg = w_gpu.cpu().numpy()
         # the step's w from the GPU's own y: one fused rounding
         wr = O.waxpy(alpha, yg, x[:A.nrows])
-        d, at = O.max_ulp(w_gpu.cpu().numpy(), wr)
+        d, at = O.max_ulp(wg, wr)
         assert d <= (0 if dt == 1 else 1), (d, at)
+        # end to end against the oracle's step: |w - w_ref| <= |alpha|*tau*sum|a x| + 1 ulp of w
+        w_ref = O.waxpy(alpha, ref, x[:A.nrows].astype(np.float64))
+        fin = np.isfinite(w_ref)
+        inf = np.isinf(w_ref)
+        assert np.array_equal(np.isnan(wg), np.isnan(w_ref)), "NaN positions of w"
+        assert np.array_equal(wg[inf], w_ref[inf].astype(wg.dtype)), "Inf of w"
+        err = np.abs(wg[fin].astype(np.float64) - w_ref[fin])
+        bound = abs(alpha) * O.tau_for(NP[dt]) * absum[fin] + np.spacing(np.abs(wg[fin])).astype(np.float64)
+        assert np.all(err <= bound), f"w end to end: worst excess {np.max(err - bound):g}"
 
 
 @pytest.mark.parametrize("dt", [1, 0])
@@ -145,17 +159,58 @@ def test_bit_exact_cases(spk, dev):
             M.release()
 
 
-def test_nan_inf_positions(spk, dev):
-    A = I.banded(3000, 4, 0.8, stream=2)
-    x = I.uniform(3, 0, 3000)
+@pytest.mark.parametrize("dt", [1, 0])
+def test_nan_inf_positions(spk, dev, dt):
+    A = I.banded(3000, 4, 0.8, stream=2).astype(NP[dt])
+    x = I.uniform(3, 0, 3000, NP[dt])
     x[[10, 500, 2999]] = [np.nan, np.inf, -np.inf]
     M = spk.Matrix(A)
     xd = torch.from_numpy(x).to(dev)
-    y = torch.empty(3000, dtype=torch.float64, device=dev)
+    y = torch.empty(3000, dtype=M.torch_dtype, device=dev)
+    w = torch.empty_like(y)
+    say(f"NaN/Inf in x, dtype={dt}")
     try:
-        for v in spk.variants(spk.SPK_OP_SPMV, 1):
+        for v in spk.variants(spk.SPK_OP_SPMV, dt):
+            y.fill_(0.0)
             spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), v)
-            _check(A, x, y)
+            try:
+                _check(A, x, y, dt=dt)
+            except AssertionError as e:
+                raise AssertionError(f"{v}: {e}")
+        for v in spk.variants(spk.SPK_OP_SPMV_WAXPY, dt):
+            y.fill_(0.0)
+            w.fill_(0.0)
+            spk.spk_run(spk.problem(spk.SPK_OP_SPMV_WAXPY, A=M, x=xd, y=y, w=w, alpha=0.5), v)
+            try:
+                _check(A, x, y, w, 0.5, dt)
+            except AssertionError as e:
+                raise AssertionError(f"{v}: {e}")
+    finally:
+        M.release()
+
+
+@pytest.mark.parametrize("dt", [1, 0])
+@pytest.mark.parametrize("name", ["m0", "m0_n0", "n0"])
+def test_degenerate_shapes_default_entry_points(spk, dev, name, dt):
+    """No rows or no columns through the borrowed-CSR call, the registered
+    call and (square shapes) the fused step: OK, nothing written for m = 0,
+    y = 0 for n = 0."""
+    A = CASES[name].astype(NP[dt])
+    say(f"degenerate {name} dtype={dt}")
+    x = torch.from_numpy(I.uniform(5, 0, A.ncols, NP[dt])).to(dev)
+    rp, ci, val = spk.to_device_csr(A, dev)
+    y = torch.full((A.nrows,), float("nan"), dtype=val.dtype, device=dev)
+    spk.spk_spmv_csr(rp, ci, val, x, y, nrows=A.nrows, ncols=A.ncols)
+    _check(A, x.cpu().numpy(), y, dt=dt)
+    M = spk.Matrix(A)
+    try:
+        y.fill_(float("nan"))
+        spk.spk_spmv_mat(M, x, y)
+        _check(A, x.cpu().numpy(), y, dt=dt)
+        if A.nrows == A.ncols:
+            w = torch.empty_like(y)
+            spk.spk_spmv_waxpy(M, 0.5, x, y, w)
+            _check(A, x.cpu().numpy(), y, w, 0.5, dt)
     finally:
         M.release()
 
