@@ -505,15 +505,29 @@ spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *desc, const spk_ba
 /* One step over every instance: Section 3's sparse product y = A_i*x_i,
  * then Figure 1's update w = alpha*y + x (w may be NULL for SpMV only), all
  * instances in one launch.  With use_graph the launch is
- * captured once per (x, y, w, alpha) and replayed. */
+ * captured once per (stream, x, y, w, alpha) and replayed.  The batch keeps
+ * its persistent queue counters and its captured graph per stream, so runs
+ * on different streams (with distinct y / w) may overlap; the first run on a
+ * stream allocates that stream's counters and synchronises, so a caller
+ * capturing runs into its own graph makes one eager run on the capture
+ * stream first.  Calls on one batch from several host threads are
+ * serialised by the library only for that per-stream state: runs that share
+ * y or w race as any two writers do. */
 spk_status spk_batch_run(spk_handle h, spk_batch b, double alpha, const void *x, void *y, void *w,
                          spk_stream stream);
 
 /* Tunes the batch (Section 2's search): the launch shape (workgroup size,
  * LDS tile per workgroup, grid or persistent kind) on the whole batch, then
  * the tile kernel of each shape class under it, then the launch shape again
- * with the tuned kernels; every candidate is validated against the current
- * plan's output before it is timed.  Re-plans the tiles.  With
+ * with the tuned kernels.  Every candidate is validated before it is timed
+ * against the unannotated program's output: the plain kernel (one lane per
+ * row, fused with the update when w is given) run instance by instance,
+ * per row within tau * sum_k |a_ik x_k| (tau from opts, else 1e-12 FP64 /
+ * 1e-5 FP32), w within |alpha| times that plus two rounding units.
+ * opts->ref_host (nullable, host, FP64, one entry per vector element up to
+ * the last instance's end) replaces the plain kernels' y as the reference;
+ * when no candidate matches the reference the call fails with
+ * SPK_ERR_VALIDATION.  Re-plans the tiles.  With
  * opts->record the winners go to the plan DB: one plan per class
  * ("batch:<dtype>:c<class>") and the launch shape ("batch:<dtype>:launch":
  * block, lds = LDS tile entries per workgroup, grid = 1 for the persistent

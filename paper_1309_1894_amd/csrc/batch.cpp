@@ -11,10 +11,24 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "device_common.h"
 #include "internal.h"
+
+// State a batch keeps per stream it runs on: the persistent kind's queue
+// heads and completion count (a run on another stream must not share them:
+// two runs in flight would claim each other's tiles), and the executable
+// graph of the launch, which bakes those counters in.
+struct BatchStream {
+    uint32_t *ctr = nullptr;              // 8 per-XCD queue heads (256 B apart), then the done count
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void *gx = nullptr;
+    void *gy = nullptr, *gw = nullptr;
+    double galpha = 0.0;
+};
 
 struct spk_batch_s {
     spk_handle h = nullptr;
@@ -31,14 +45,9 @@ struct spk_batch_s {
     std::vector<spk::BatchTile> tiles;
     spk::BatchTile *d_tiles = nullptr;
     int64_t d_tiles_cap = 0;
-    uint32_t *d_ctr = nullptr;            // 8 per-XCD queue heads (256 B apart), then the done count
     int64_t grid_persistent = 0;
-    // captured launch
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    const void *gx = nullptr;
-    void *gy = nullptr, *gw = nullptr;
-    double galpha = 0.0;
+    std::mutex mu;                        // guards `streams`
+    std::map<hipStream_t, BatchStream> streams;
 };
 
 namespace spk {
@@ -178,11 +187,39 @@ void invalidate_graph(spk_batch b)
     // a replay may still be queued on any of the caller's streams: let it
     // finish before its executable graph goes (rare: a change of x, y, w,
     // alpha or of the plan)
-    if (b->exec) (void)hipDeviceSynchronize();
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
+    std::lock_guard<std::mutex> lk(b->mu);
+    bool any = false;
+    for (auto &kv : b->streams) any = any || kv.second.exec;
+    if (any) (void)hipDeviceSynchronize();
+    for (auto &kv : b->streams) {
+        BatchStream &st = kv.second;
+        if (st.exec) (void)hipGraphExecDestroy(st.exec);
+        if (st.graph) (void)hipGraphDestroy(st.graph);
+        st.exec = nullptr;
+        st.graph = nullptr;
+    }
+}
+
+// The state of stream s; on the first use of s, its queue counters are
+// allocated and zeroed (an allocation and a synchronisation: not inside a
+// graph capture, so a captured run needs an eager run on its stream first).
+spk_status stream_state(spk_batch b, hipStream_t s, BatchStream **out)
+{
+    std::lock_guard<std::mutex> lk(b->mu);
+    BatchStream &st = b->streams[s];
+    if (!st.ctr) {
+        uint32_t *c = nullptr;
+        SPK_HIP(hipMalloc(&c, kCounterBytes));
+        hipError_t e = hipMemsetAsync(c, 0, kCounterBytes, b->h->work);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->h->work);
+        if (e != hipSuccess) {
+            (void)hipFree(c);
+            return hip_fail(e, "batch queue counters");
+        }
+        st.ctr = c;
+    }
+    *out = &st;
+    return SPK_OK;
 }
 
 // Tiles of instance i under `mode`.
@@ -229,10 +266,17 @@ spk_status replan(spk_batch b)
     return upload_tiles(b, b->tiles);
 }
 
-// Launches the tile kernel over `ntiles` tiles already on the device.
+// Launches the tile kernel over `ntiles` tiles already on the device, on
+// stream s with s's queue counters.
 spk_status launch(spk_batch b, int64_t ntiles, double alpha, const void *x, void *y, void *w, hipStream_t s)
 {
-    return launch_tiles(b->entry, b->dtype, b->d_tiles, ntiles, alpha, x, y, w, b->opts.persistent, b->d_ctr,
+    uint32_t *ctr = nullptr;
+    if (b->opts.persistent == kBatchPersistent) {
+        BatchStream *st = nullptr;
+        SPK_TRY(stream_state(b, s, &st));
+        ctr = st->ctr;
+    }
+    return launch_tiles(b->entry, b->dtype, b->d_tiles, ntiles, alpha, x, y, w, b->opts.persistent, ctr,
                         b->grid_persistent, s);
 }
 
@@ -350,11 +394,6 @@ spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *d, const spk_batch
                 b->mode[c] = batch_default_mode(c, batch_wave_entries(*e));
         }
     }
-    hipError_t he = hipSuccess;
-    if (he == hipSuccess) he = hipMalloc(&b->d_ctr, kCounterBytes);
-    if (he == hipSuccess) he = hipMemsetAsync(b->d_ctr, 0, kCounterBytes, h->work);
-    if (he == hipSuccess) he = hipStreamSynchronize(h->work);
-    if (he != hipSuccess) return bail(hip_fail(he, "batch descriptors"));
     spk_status st = occupancy(b);
     if (st == SPK_OK) st = replan(b);
     if (st != SPK_OK) return bail(st);
@@ -371,26 +410,43 @@ spk_status spk_batch_run(spk_handle h, spk_batch b, double alpha, const void *x,
     DeviceGuard g(h);
     hipStream_t s = (hipStream_t)stream;
     if (!b->opts.use_graph) return launch(b, (int64_t)b->tiles.size(), alpha, x, y, w, s);
-    if (!b->exec || b->gx != x || b->gy != y || b->gw != w || b->galpha != alpha) {
-        invalidate_graph(b);
+    BatchStream *st = nullptr;
+    SPK_TRY(stream_state(b, s, &st));
+    if (!st->exec || st->gx != x || st->gy != y || st->gw != w || st->galpha != alpha) {
+        if (st->exec) {
+            // a replay of the old graph may still be queued on s
+            SPK_HIP(hipStreamSynchronize(s));
+            (void)hipGraphExecDestroy(st->exec);
+            (void)hipGraphDestroy(st->graph);
+            st->exec = nullptr;
+            st->graph = nullptr;
+        }
+        // captured on the library's own stream (s may itself be capturing),
+        // with s's counters, for replay on s
         SPK_HIP(hipStreamSynchronize(h->work));
         SPK_HIP(hipStreamBeginCapture(h->work, hipStreamCaptureModeThreadLocal));
-        spk_status st = launch(b, (int64_t)b->tiles.size(), alpha, x, y, w, h->work);
+        spk_status ls = launch_tiles(b->entry, b->dtype, b->d_tiles, (int64_t)b->tiles.size(), alpha, x, y, w,
+                                     b->opts.persistent, st->ctr, b->grid_persistent, h->work);
         hipGraph_t graph = nullptr;
         const hipError_t ce = hipStreamEndCapture(h->work, &graph);
-        if (st != SPK_OK) {
+        if (ls != SPK_OK) {
             if (graph) (void)hipGraphDestroy(graph);
-            return st;
+            return ls;
         }
         if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
-        b->graph = graph;
-        SPK_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-        b->gx = x;
-        b->gy = y;
-        b->gw = w;
-        b->galpha = alpha;
+        const hipError_t ie = hipGraphInstantiate(&st->exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            st->exec = nullptr;
+            return hip_fail(ie, "hipGraphInstantiate");
+        }
+        st->graph = graph;
+        st->gx = x;
+        st->gy = y;
+        st->gw = w;
+        st->galpha = alpha;
     }
-    SPK_HIP(hipGraphLaunch(b->exec, s));
+    SPK_HIP(hipGraphLaunch(st->exec, s));
     return SPK_OK;
 }
 
@@ -426,8 +482,15 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
     for (int64_t i = 0; i < b->count; ++i) nvec = std::max<int64_t>(nvec, b->vec_off[i] + b->m[i]);
     if (nvec == 0) return SPK_OK;
 
-    // reference: the current plan's output, and the row tolerance scales
+    // Reference (Section 2: the unannotated program's results): the
+    // library's plain kernel -- one lane per row, the fused step when w is
+    // given -- run instance by instance on borrowed views of the batch's
+    // arrays.  It shares no code with the tile kernels it judges.  Its
+    // output stays in the caller's y / w and is kept in native precision
+    // too, and every trial starts from it, so rows a trial does not
+    // rewrite (other classes, gaps between instances) hold reference values.
     double *ref_y = nullptr, *ref_w = nullptr, *scale = nullptr, *scale_w = nullptr;
+    void *nat_y = nullptr, *nat_w = nullptr;
     unsigned long long *bad = nullptr, *hbad = nullptr;
     struct Free {
         std::vector<void *> d;
@@ -439,16 +502,44 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
         }
     } fr;
     SPK_HIP(hipMalloc(&ref_y, 8 * nvec)); fr.d.push_back(ref_y);
+    SPK_HIP(hipMalloc(&nat_y, vs * nvec)); fr.d.push_back(nat_y);
     SPK_HIP(hipMalloc(&scale, 8 * nvec)); fr.d.push_back(scale);
     SPK_HIP(hipMalloc(&bad, 8)); fr.d.push_back(bad);
     SPK_HIP(hipHostMalloc((void **)&hbad, 8, hipHostMallocDefault)); fr.hp = hbad;
     if (w) {
         SPK_HIP(hipMalloc(&ref_w, 8 * nvec)); fr.d.push_back(ref_w);
+        SPK_HIP(hipMalloc(&nat_w, vs * nvec)); fr.d.push_back(nat_w);
         SPK_HIP(hipMalloc(&scale_w, 8 * nvec)); fr.d.push_back(scale_w);
     }
-    SPK_TRY(launch(b, (int64_t)b->tiles.size(), alpha, x, y, w, s));
+    {
+        const spk_variant plain = plain_variant(w ? SPK_OP_SPMV_WAXPY : SPK_OP_SPMV, 0);
+        for (int64_t i = 0; i < b->count; ++i) {
+            if (b->m[i] == 0) continue;
+            spk_csr view{};
+            view.nrows = b->m[i];
+            view.ncols = b->m[i];
+            view.nnz = b->nnz[i];
+            view.dtype = b->dtype;
+            view.row_ptr = b->rp + b->rp_off[i];
+            view.col_idx = b->ci + b->nz_off[i];
+            view.val = (const char *)b->val + vs * b->nz_off[i];
+            SpmvProblem q;
+            q.csr = &view;
+            q.fused = w != nullptr;
+            q.alpha = alpha;
+            q.x = (const char *)x + vs * b->vec_off[i];
+            q.y = (char *)y + vs * b->vec_off[i];
+            q.w = w ? (char *)w + vs * b->vec_off[i] : nullptr;
+            SPK_TRY(run_spmv(h, q, plain, s));
+        }
+    }
+    SPK_HIP(hipMemcpyAsync(nat_y, y, vs * nvec, hipMemcpyDeviceToDevice, s));
     SPK_HIP(launch_widen(b->dtype, nvec, y, ref_y, s));
-    if (w) SPK_HIP(launch_widen(b->dtype, nvec, w, ref_w, s));
+    if (w) {
+        SPK_HIP(hipMemcpyAsync(nat_w, w, vs * nvec, hipMemcpyDeviceToDevice, s));
+        SPK_HIP(launch_widen(b->dtype, nvec, w, ref_w, s));
+    }
+    SPK_HIP(hipMemsetAsync(scale, 0, 8 * nvec, s));   // gaps between instances: exact match required
     SPK_HIP(launch_tiles_absum(b->dtype, b->d_tiles, (int64_t)b->tiles.size(), x, scale, s));
     if (w) {
         std::vector<double> sc((size_t)nvec), wr((size_t)nvec);
@@ -458,6 +549,11 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
         const double eps = b->dtype == SPK_F64 ? 0x1p-52 : 0x1p-23;
         for (int64_t i = 0; i < nvec; ++i) sc[i] = std::fabs(alpha) * sc[i] + 2.0 * eps * std::fabs(wr[i]) / tau;
         SPK_HIP(hipMemcpyAsync(scale_w, sc.data(), 8 * nvec, hipMemcpyHostToDevice, s));
+    }
+    if (o.ref_host) {
+        // a caller-supplied reference y (FP64, nvec entries) replaces the
+        // plain kernels' y; its tolerance scale stays the batch's own
+        SPK_HIP(hipMemcpyAsync(ref_y, o.ref_host, 8 * nvec, hipMemcpyHostToDevice, s));
     }
     SPK_HIP(hipStreamSynchronize(s));
 
@@ -476,6 +572,8 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
     auto validate_and_time = [&](int64_t ntiles, double *med) -> spk_status {
         *med = -1.0;
         SPK_HIP(hipMemsetAsync(bad, 0, 8, s));
+        SPK_HIP(hipMemcpyAsync(y, nat_y, vs * nvec, hipMemcpyDeviceToDevice, s));
+        if (w) SPK_HIP(hipMemcpyAsync(w, nat_w, vs * nvec, hipMemcpyDeviceToDevice, s));
         SPK_TRY(launch(b, ntiles, alpha, x, y, w, s));
         SPK_HIP(launch_check(b->dtype, 0, nvec, y, ref_y, scale, tau, bad, s));
         if (w) SPK_HIP(launch_check(b->dtype, 0, nvec, w, ref_w, scale_w, tau, bad, s));
@@ -571,6 +669,10 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
     }
     SPK_TRY(replan(b));
     SPK_TRY(pick_launch());
+    if (tried == 0) {
+        report->rejected = rejected;
+        return fail(SPK_ERR_VALIDATION, "no tile kernel reproduced the reference (%d rejected)", rejected);
+    }
     if (o.record) {
         for (const auto &kv : class_best) {
             spk_variant v{};
@@ -603,7 +705,6 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
     report->best.lds = b->entry->tile;
     snprintf(report->class_key, sizeof report->class_key, "batch:%s:%d-classes", dtype_name(b->dtype),
              (int)by_class.size());
-    if (tried == 0) return fail(SPK_ERR_VALIDATION, "no tile kernel reproduced the reference");
     return SPK_OK;
 }
 
@@ -624,7 +725,8 @@ spk_status spk_batch_free(spk_handle h, spk_batch b)
     (void)hipDeviceSynchronize();
     invalidate_graph(b);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
-    if (b->d_ctr) (void)hipFree(b->d_ctr);
+    for (auto &kv : b->streams)
+        if (kv.second.ctr) (void)hipFree(kv.second.ctr);
     delete b;
     return SPK_OK;
 }

@@ -576,10 +576,17 @@ class Batch:
         _ok(_lib.spk_batch_run(self.handle.ptr, self.ptr, float(alpha), _dev(x, "x"), _dev(y, "y"), _dev(w, "w"),
                                _stream(stream)), "spk_batch_run")
 
-    def tune(self, alpha, x, y, w=None, reps=10, warmup=2, flush=False, record=True, verbose=False):
+    def tune(self, alpha, x, y, w=None, reps=10, warmup=2, flush=False, record=True, verbose=False, ref=None):
+        """spk_batch_tune; ``ref`` (optional, host FP64, one entry per vector
+        element) replaces the plain kernels' y as the reference."""
         self._check(x, y, w)
         o = spk_tune_opts()
         o.reps, o.warmup, o.flush, o.record, o.verbose = reps, warmup, int(flush), int(record), int(verbose)
+        if ref is not None:
+            r = np.ascontiguousarray(ref, dtype=np.float64)
+            if r.size < int(self._host[0].sum()):
+                raise ValueError(f"ref holds {r.size} elements; the batch has {int(self._host[0].sum())} rows")
+            o.ref_host = r.ctypes.data
         rep = spk_tune_report()
         _ok(_lib.spk_batch_tune(self.handle.ptr, self.ptr, float(alpha), _dev(x, "x"), _dev(y, "y"), _dev(w, "w"),
                                 C.byref(o), C.byref(rep)), "spk_batch_tune")

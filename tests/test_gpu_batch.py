@@ -144,6 +144,74 @@ def test_batch_tune_per_class(spk, dev):
         h.close()
 
 
+def test_batch_tune_reference_is_the_plain_kernel(spk, dev):
+    """spk_batch_tune judges candidates by the plain kernels' output: with the
+    oracle's y supplied as the reference every candidate passes; with one row
+    of that reference planted wrong, every candidate is rejected and nothing
+    is recorded."""
+    B = mixed_batch()
+    x = I.batch_vector(B, seed=17)
+    arrs = _dev_batch(B, dev)
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(x.size, dtype=torch.float64, device=dev)
+    w = torch.empty_like(y)
+    yr = np.concatenate([O.spmv(B.instance(i), x[int(B.vec_off[i]):int(B.vec_off[i]) + int(B.m[i])])[0]
+                         for i in range(B.count)])
+    h = spk.Handle(0)
+    b = spk.Batch(B, arrs, handle=h)
+    try:
+        say("batch tune against the oracle's y")
+        rep = b.tune(0.5, xd, y, w, reps=2, warmup=1, record=False, ref=yr)
+        assert rep.tried > 0 and rep.rejected == 0
+        wrong = yr.copy()
+        row = int(B.vec_off[7]) + int(B.m[7]) // 2
+        wrong[row] += 1e-6 * (1.0 + abs(wrong[row]))
+        say("batch tune against a planted wrong reference")
+        with pytest.raises(spk.SpkError, match="SPK_ERR_VALIDATION"):
+            b.tune(0.5, xd, y, w, reps=2, warmup=1, record=True, ref=wrong)
+        assert spk.spk_plan_get("batch:f64:launch", handle=h) is None
+        assert all(spk.spk_plan_get(f"batch:f64:c{c}", handle=h) is None for c in range(16))
+        # the batch still runs correctly after the failed search
+        y.fill_(float("nan"))
+        w.fill_(float("nan"))
+        b.run(0.5, xd, y, w)
+        torch.cuda.synchronize()
+        _check_batch(B, x, y, w, 0.5)
+    finally:
+        b.free()
+        h.close()
+
+
+@pytest.mark.parametrize("persistent,graph", [(1, 1), (1, 0), (0, 1)])
+def test_batch_runs_on_two_streams(spk, dev, persistent, graph):
+    """One batch run on two streams at once with different x, y and w: each
+    stream has its own queue counters and graph, so both results match the
+    oracle, every time."""
+    B = mixed_batch()
+    xa = I.batch_vector(B, seed=18)
+    xb = I.batch_vector(B, seed=19)
+    arrs = _dev_batch(B, dev)
+    xad, xbd = torch.from_numpy(xa).to(dev), torch.from_numpy(xb).to(dev)
+    ya, yb = (torch.empty(xa.size, dtype=torch.float64, device=dev) for _ in range(2))
+    wa, wb = torch.empty_like(ya), torch.empty_like(yb)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    b = spk.Batch(B, arrs, persistent=persistent, use_graph=graph)
+    say(f"batch on two streams persistent={persistent} graph={graph}")
+    try:
+        for rnd in range(3):
+            for t in (ya, yb, wa, wb):
+                t.fill_(float("nan"))
+            torch.cuda.synchronize()
+            for _ in range(4):
+                b.run(0.5, xad, ya, wa, stream=sa)
+                b.run(0.5, xbd, yb, wb, stream=sb)
+            torch.cuda.synchronize()
+            _check_batch(B, xa, ya, wa, 0.5)
+            _check_batch(B, xb, yb, wb, 0.5)
+    finally:
+        b.free()
+
+
 def test_batch_spmv_only_and_empty(spk, dev):
     B = mixed_batch()
     x = I.batch_vector(B, seed=16)
