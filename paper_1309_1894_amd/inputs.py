@@ -337,6 +337,24 @@ def batch_banded(count: int = 4096, fill: float = 0.6, seed_struct: int = 41, se
     return batch_from_instances(insts, b)
 
 
+def block_diagonal(batch: Batch) -> CSR:
+    """The batch as one square block-diagonal CSR matrix: instance i's rows
+    become rows vec_off[i].., its columns shifted by vec_off[i] (instances
+    stored back to back, as batch_from_instances lays them out)."""
+    nv = int(batch.m.sum())
+    nz = int(batch.nnz.sum())
+    rp = np.empty(nv + 1, dtype=np.int64)
+    rp[nv] = nz
+    keep = np.ones(batch.row_ptr.shape[0], dtype=bool)
+    keep[(batch.rp_off + batch.m).astype(np.int64)] = False          # each instance's closing row_ptr entry
+    local = batch.row_ptr[keep].astype(np.int64)
+    rp[:nv] = local + np.repeat(batch.nz_off, batch.m)
+    if nz >= 2 ** 31:
+        raise ValueError("block-diagonal form needs nnz < 2^31")
+    ci = batch.col_idx + np.repeat(batch.vec_off, batch.nnz).astype(np.int32)
+    return CSR(nv, nv, rp.astype(np.int32), ci.astype(np.int32, copy=False), batch.val)
+
+
 def batch_vector(batch: Batch, seed: int = 43, dtype=np.float64) -> np.ndarray:
     """Concatenated x for a batch: instance i draws from stream i."""
     parts = [uniform(seed, i, int(batch.m[i]), dtype) for i in range(batch.count)]

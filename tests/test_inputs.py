@@ -116,3 +116,25 @@ def test_spd_zipf_symmetric_dominant_sorted():
     assert A.row_lengths().max() >= 2000
     B = I.spd_zipf(2000, seed_struct=5, seed_val=6)
     assert np.array_equal(A.val, B.val) and np.array_equal(A.col_idx, B.col_idx)
+
+
+def test_block_diagonal_equals_per_instance():
+    """The batch as one block-diagonal matrix (the plain baseline's operand)
+    gives, row for row, each instance's own product, bit for bit (same entry
+    order per row); structure: square, sorted row_ptr, shifted columns."""
+    import oracle as O
+    insts = [I.banded(50, 3, 0.6, stream=1), I.banded(7, 2, 0.1, stream=2), I.lap2d(5),
+             I.banded(1, 1, 1.0, stream=4), I.zipf(300, seed_struct=5, seed_val=6)]
+    B = I.batch_from_instances(insts)
+    D = I.block_diagonal(B)
+    assert D.nrows == D.ncols == int(B.m.sum()) and D.nnz == int(B.nnz.sum())
+    assert np.all(np.diff(D.row_ptr) >= 0) and D.row_ptr[0] == 0 and D.row_ptr[-1] == D.nnz
+    x = I.batch_vector(B, seed=3)
+    y, _ = O.spmv(D, x)
+    for i in range(B.count):
+        o, m = int(B.vec_off[i]), int(B.m[i])
+        A = B.instance(i)
+        assert np.array_equal(y[o:o + m], O.spmv(A, x[o:o + m])[0]), i
+        ro = D.row_ptr[o:o + m + 1]
+        assert np.array_equal(ro - ro[0], A.row_ptr)
+        assert np.all((D.col_idx[ro[0]:ro[-1]] >= o) & (D.col_idx[ro[0]:ro[-1]] < o + m))
