@@ -225,6 +225,21 @@ spk_status spk_axpy(spk_handle h, int32_t dtype, int64_t n, double alpha,
 spk_status spk_dot(spk_handle h, int32_t dtype, int64_t n, const void *x, const void *y,
                    double *d_result, spk_stream stream);
 
+/* spk_dot for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels, variant and result bits as spk_dot, but the
+ * partial sums and the ticket live in a fixed per-GPU array of the library
+ * (65,536 partials, 512 KiB plus one 256-byte line, held by each GPU the
+ * library runs on until the process ends) instead of scratch the handle
+ * allocates; the call allocates nothing, launches a small kernel that zeroes
+ * the ticket, then the dot.  A dot whose variant needs more than 65,536
+ * workgroups (only the one-pass plain variant, above 16.7M elements) is
+ * rejected with SPK_ERR_SHAPE.  Every call on a GPU, from any handle or
+ * stream, shares that GPU's array: calls that overlap on one GPU race and
+ * give wrong results, so serialise them (one stream, or events). */
+spk_status spk_dot_noalloc(spk_handle h, int32_t dtype, int64_t n, const void *x, const void *y,
+                           double *d_result, spk_stream stream);
+
 /* ----------------------------------------------------------------- SpMV -- */
 
 /* y = A*x for a borrowed CSR matrix: the sparse matrix-vector product of

@@ -271,29 +271,57 @@ static spk_status dot_scratch(spk_handle h, hipStream_t s, int64_t need, DotScra
     return SPK_OK;
 }
 
-spk_status run_dot(spk_handle h, int dtype, int64_t n, const void *x, const void *y, double *out,
-                   const spk_variant &v, hipStream_t s)
+// Kernel and grid of a dot variant on these operands (vector width 1 when
+// x or y is not aligned to the variant's access size).
+static spk_status dot_plan(spk_handle h, int dtype, int64_t n, const void *x, const void *y, const spk_variant &v,
+                           const VecEntry **e, int64_t *grid)
 {
     spk_variant vv = v;
     const size_t bytes = (size_t)vv.vec * dtype_size(dtype);
     if (vv.vec > 1 && (((uintptr_t)x | (uintptr_t)y) % bytes) != 0) vv.vec = 1;
-    const VecEntry *e = find_vec_entry(SPK_OP_DOT, dtype, vv);
-    if (!e) return fail(SPK_ERR_NOT_FOUND, "dot variant not compiled");
-    const int64_t g = vec_grid(*e, n, vv.grid, h->num_cu);
-    DotScratch *d = nullptr;
-    SPK_TRY(dot_scratch(h, s, g, &d));
+    *e = find_vec_entry(SPK_OP_DOT, dtype, vv);
+    if (!*e) return fail(SPK_ERR_NOT_FOUND, "dot variant not compiled");
+    *grid = vec_grid(**e, n, vv.grid, h->num_cu);
+    return SPK_OK;
+}
+
+// One dot on the given scratch: `partial` holds `grid` doubles; `ticket`
+// (used when grid <= kDotTicketMaxGrid, else NULL) is zero on entry and left
+// at zero by the kernel.
+static spk_status dot_launch(const VecEntry *e, int dtype, int64_t n, const void *x, const void *y, double *out,
+                             int64_t grid, double *partial, uint32_t *ticket, hipStream_t s)
+{
     VecLaunch L{};
     L.n = n;
     L.x = x;
     L.y = y;
-    L.partial = d->partial;
-    L.ticket = g <= kDotTicketMaxGrid ? d->ticket : nullptr;
+    L.partial = partial;
+    L.ticket = grid <= kDotTicketMaxGrid ? ticket : nullptr;
     L.out = out;
-    L.grid = g;
+    L.grid = grid;
     SPK_HIP(e->fn[dtype](L, s));
-    if (!L.ticket) SPK_HIP(launch_dot_final(d->partial, g, out, s));
+    if (!L.ticket) SPK_HIP(launch_dot_final(partial, grid, out, s));
     return SPK_OK;
 }
+
+spk_status run_dot(spk_handle h, int dtype, int64_t n, const void *x, const void *y, double *out,
+                   const spk_variant &v, hipStream_t s)
+{
+    const VecEntry *e = nullptr;
+    int64_t g = 0;
+    SPK_TRY(dot_plan(h, dtype, n, x, y, v, &e, &g));
+    DotScratch *d = nullptr;
+    SPK_TRY(dot_scratch(h, s, g, &d));
+    return dot_launch(e, dtype, n, x, y, out, g, d->partial, d->ticket, s);
+}
+
+// Scratch of spk_dot_noalloc, one copy per GPU for the life of the process:
+// kNoAllocPartials workgroup partials, then one 256-byte line whose first
+// word is the dot's ticket.  Host code reaches it only through the address
+// spk_create stores in the handle (hipGetSymbolAddress on the handle's
+// device); the array's name in host code is not a device address.
+constexpr int64_t kNoAllocPartials = 65536;
+static __device__ __align__(256) double scratch[kNoAllocPartials + 32];
 
 // ----------------------------------------------------------------- SpMV --
 
@@ -792,6 +820,8 @@ spk_status spk_create(int device, const char *db_path, spk_handle *out)
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->work, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
     for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&h->ev_join[i], hipEventDisableTiming);
+    // this device's copy of the allocation-free dot's scratch
+    if (e == hipSuccess) e = hipGetSymbolAddress((void **)&h->noalloc_scratch, HIP_SYMBOL(scratch));
     (void)hipSetDevice(prev);
     if (e != hipSuccess) {
         spk_status s = hip_fail(e, "stream/event creation");
@@ -915,6 +945,44 @@ spk_status spk_dot(spk_handle h, int32_t dtype, int64_t n, const void *x, const 
     SPK_TRY(resolve(h, p, nullptr, &v));
     DeviceGuard g(h);
     return run_dot(h, dtype, n, x, y, d_result, v, (hipStream_t)stream);
+}
+
+spk_status spk_dot_noalloc(spk_handle h, int32_t dtype, int64_t n, const void *x, const void *y, double *d_result,
+                           spk_stream stream)
+{
+    if (!h) return fail(SPK_ERR_NULL, "handle is NULL");
+    if (!dtype_ok(dtype)) return fail(SPK_ERR_DTYPE, "bad dtype %d", dtype);
+    if (n < 0) return fail(SPK_ERR_SHAPE, "n = %lld < 0", (long long)n);
+    if (!d_result) return fail(SPK_ERR_NULL, "d_result is NULL");
+    if (n > 0 && (!x || !y)) return fail(SPK_ERR_NULL, "x and y must be non-NULL");
+    if (!h->noalloc_scratch) return fail(SPK_ERR_HIP, "the device scratch of this handle is not set up");
+    const size_t nb = (size_t)n * dtype_size(dtype);
+    if (overlaps(d_result, 8, x, nb) || overlaps(d_result, 8, y, nb))
+        return fail(SPK_ERR_ALIAS, "d_result overlaps x or y");
+    spk_problem p{};
+    p.op = SPK_OP_DOT;
+    p.dtype = dtype;
+    p.n = n;
+    spk_variant v;
+    SPK_TRY(resolve(h, p, nullptr, &v));
+    const VecEntry *e = nullptr;
+    int64_t g = 0;
+    SPK_TRY(dot_plan(h, dtype, n, x, y, v, &e, &g));
+    if (g > kNoAllocPartials)
+        return fail(SPK_ERR_SHAPE,
+                    "this dot (n = %lld, block %d, vec %d, unroll %d, grid %d) needs %lld workgroup partials; "
+                    "the allocation-free form holds at most %lld",
+                    (long long)n, v.block, v.vec, v.unroll, v.grid, (long long)g, (long long)kNoAllocPartials);
+    DeviceGuard dg(h);
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *ticket = nullptr;
+    if (g <= kDotTicketMaxGrid) {
+        // the array keeps the last call's contents: the ticket starts at zero
+        // (a kernel, not a memset node, so the call can be captured)
+        ticket = (uint32_t *)(h->noalloc_scratch + kNoAllocPartials);
+        SPK_HIP(launch_zero_u32(ticket, 1, s));
+    }
+    return dot_launch(e, dtype, n, x, y, d_result, g, h->noalloc_scratch, ticket, s);
 }
 
 // ----------------------------------------------------------------- SpMV --

@@ -156,6 +156,7 @@ struct spk_ctx {
     std::mutex mu;
     std::map<std::string, spk_variant> plans;
     std::map<hipStream_t, spk::DotScratch> dot;
+    double *noalloc_scratch = nullptr;   // this device's copy of spk_dot_noalloc's static scratch
     std::map<hipStream_t, spk::CgScratch> cg;
     void *flush_buf = nullptr;
     int64_t flush_bytes = 0;

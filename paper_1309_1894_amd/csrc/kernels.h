@@ -232,6 +232,9 @@ hipError_t launch_tiles_absum(int dtype, const BatchTile *tiles, int64_t ntiles,
 hipError_t launch_dot_absum(int dtype, int64_t n, const void *x, const void *y, double *out,
                             hipStream_t s);
 
+// Sets n 32-bit words to zero (a kernel: capture-safe, unlike a memset node).
+hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
+
 // Fills n bytes (n a multiple of 16) with a pattern: evicts caches.
 hipError_t launch_fill(void *p, int64_t n, uint32_t pattern, hipStream_t s);
 

@@ -279,6 +279,18 @@ hipError_t launch_dot_absum(int dtype, int64_t n, const void *x, const void *y, 
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kBS) void k_zero_u32(uint32_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBS) p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(n, 8)), dim3(kBS), 0, s, p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(void *p, int64_t n, uint32_t pattern, hipStream_t s)
 {
     const int64_t n16 = n / 16;

@@ -115,6 +115,7 @@ _SIGS = {
     "spk_waxpy": (_S, [_P, _I32, _I64, _D, _P, _P, _P, _P]),
     "spk_axpy": (_S, [_P, _I32, _I64, _D, _P, _P, _P]),
     "spk_dot": (_S, [_P, _I32, _I64, _P, _P, _P, _P]),
+    "spk_dot_noalloc": (_S, [_P, _I32, _I64, _P, _P, _P, _P]),
     "spk_spmv_csr": (_S, [_P, C.POINTER(spk_csr), _P, _P, _P]),
     "spk_matrix_register": (_S, [_P, C.POINTER(spk_csr), _I32, _I32, C.POINTER(_P)]),
     "spk_matrix_release": (_S, [_P, _P]),
@@ -294,6 +295,17 @@ def spk_dot(x, y, out=None, handle=None, stream=None):
         raise ValueError("x, y must share dtype and size")
     _ok(_lib.spk_dot(_h(handle), _dtype_code(x), x.numel(), _dev(x, "x"), _dev(y, "y"), _dev(out, "out"),
                      _stream(stream)), "spk_dot")
+    return out
+
+
+def spk_dot_noalloc(x, y, out, handle=None, stream=None):
+    """spk_dot on the library's fixed per-GPU scratch (allocates nothing):
+    ``out`` is a caller-provided 1-element float64 device tensor."""
+    if x.dtype != y.dtype or x.numel() != y.numel():
+        raise ValueError("x, y must share dtype and size")
+    _need(out, 1, "out")
+    _ok(_lib.spk_dot_noalloc(_h(handle), _dtype_code(x), x.numel(), _dev(x, "x"), _dev(y, "y"), _dev(out, "out"),
+                             _stream(stream)), "spk_dot_noalloc")
     return out
 
 
