@@ -416,12 +416,14 @@ def per_format(spk, torch, M, xd, y, reps=5):
     """Best cold-cache time (us) per storage format: the tuner's search
     (validation, then timing) restricted to one format at a time."""
     names = {spk.SPK_FMT_SCALAR: "csr_scalar", spk.SPK_FMT_VECTOR: "csr_vector", spk.SPK_FMT_SELL: "sliced_ell",
-             spk.SPK_FMT_ADAPTIVE: "csr_lds_tiles", spk.SPK_FMT_COLBLOCK: "csr_column_blocks", spk.SPK_FMT_DIA: "dia",
+             spk.SPK_FMT_ADAPTIVE: "csr_lds_tiles", spk.SPK_FMT_COLBLOCK: "csr_column_blocks",
+             spk.SPK_FMT_XWIN: "csr_x_windows_in_lds", spk.SPK_FMT_DIA: "dia",
              spk.SPK_FMT_STENCIL: "stencil"}
     best = {}
     p = spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y)
     for fmt, name in names.items():
-        if fmt in (spk.SPK_FMT_DIA, spk.SPK_FMT_STENCIL, spk.SPK_FMT_COLBLOCK) and not M.formats() & (1 << fmt):
+        if fmt in (spk.SPK_FMT_DIA, spk.SPK_FMT_STENCIL, spk.SPK_FMT_COLBLOCK, spk.SPK_FMT_XWIN) and \
+                not M.formats() & (1 << fmt):
             continue
         try:
             rep = spk.spk_tune(p, reps=reps, warmup=1, flush=True, record=False, formats=1 << fmt)

@@ -109,7 +109,22 @@ typedef enum {
                              * from one slice of x only, which pays when x is
                              * larger than an XCD's L2.  Same algorithmic bytes
                              * as CSR; not listed by spk_variant_get, searched
-                             * by spk_tune (`formats`) when x exceeds 4 MiB */
+                             * by spk_tune (`formats`) when x exceeds 4 MiB */,
+    SPK_FMT_XWIN = 8        /* x staged in LDS by column window (registered
+                             * matrices, FP64 and FP32): the columns cut into
+                             * windows of `group` KiB of x (128 or 64); the
+                             * entries regrouped at first use into (row, window)
+                             * pairs, window-major, with 16-bit column indices
+                             * inside the window; one pass in which each
+                             * workgroup (`block` threads, `lds` row-stream
+                             * entries per wavefront) copies one window of x to
+                             * LDS and writes an FP64 partial per pair of its
+                             * chunk (about `grid` chunks per compute unit), then
+                             * one pass adds each row's partials in window order
+                             * (and forms w).  The gathers of x never leave the
+                             * compute unit.  Not listed by spk_variant_get,
+                             * searched by spk_tune (`formats`) when x exceeds
+                             * 4 MiB */
 } spk_format;
 
 typedef void *spk_stream;                 /* hipStream_t */

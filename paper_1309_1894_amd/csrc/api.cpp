@@ -114,6 +114,14 @@ spk_status check_variant(int op, int dtype, const spk_variant &v)
                 return fail(SPK_ERR_NOT_FOUND, "no compiled row-block kernel block=%d lds=%d", v.block, v.lds);
             return SPK_OK;
         }
+        if (v.format == SPK_FMT_XWIN) {
+            if (!find_xwin_entry(v.block, v.group, v.lds))
+                return fail(SPK_ERR_NOT_FOUND, "no compiled x-window kernel block=%d window=%d KiB entries=%d",
+                            v.block, v.group, v.lds);
+            if (v.grid < 1 || v.grid > 4) return fail(SPK_ERR_ARG, "x-window chunks per CU must be 1..4 (got %d)", v.grid);
+            if (v.streams != 1) return fail(SPK_ERR_ARG, "the x-window form runs on one stream");
+            return SPK_OK;
+        }
         if (!find_spmv_entry(v))
             return fail(SPK_ERR_NOT_FOUND, "no compiled SpMV variant format=%d block=%d group=%d unroll=%d lds=%d",
                         v.format, v.block, v.group, v.unroll, v.lds);
@@ -363,6 +371,7 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
     if (m == 0) return SPK_OK;
     if (v.format == SPK_FMT_DIA || v.format == SPK_FMT_STENCIL) return run_structured(h, p, v, s);
     if (v.format == SPK_FMT_COLBLOCK) return run_colblock(h, p, v, s);
+    if (v.format == SPK_FMT_XWIN) return run_xwin(h, p, v, s);
     const SpmvEntry *e = find_spmv_entry(v);
     if (!e) return fail(SPK_ERR_NOT_FOUND, "SpMV variant not compiled");
     if (!p.mat && (v.format == SPK_FMT_SELL || v.format == SPK_FMT_ADAPTIVE))
@@ -496,53 +505,6 @@ spk_status get_sell(spk_handle h, spk_mat *A, int C, SellData **out)
     return SPK_OK;
 }
 
-// Row blocks for the LDS-staged kernel: runs of short rows whose entries
-// fit `tile` (at most 2*block rows), up to block/64 medium rows handled one
-// wavefront each, and single long rows handled by a whole workgroup.
-// Wavefront tiles for the LDS-staged kernel, E = row-stream capacity:
-// runs of short rows (at most 96 entries each) whose entries fit E and that
-// number at most 128; runs of medium rows, up to 4E entries in all, one
-// wavefront with 64 lanes per row; single long rows (over 8E entries).
-static void make_blocks(const std::vector<int32_t> &rp, int64_t m, int E, std::vector<uint32_t> &out,
-                        std::vector<int32_t> &out_k)
-{
-    const int64_t kShort = std::min<int64_t>(96, E);
-    const int64_t kLong = 8 * (int64_t)E;
-    const int64_t kRows = 2 * 64;
-    out.clear();
-    out_k.clear();
-    int64_t r = 0;
-    while (r < m) {
-        const int64_t len = rp[r + 1] - rp[r];
-        out_k.push_back(rp[r]);
-        if (len > kLong) {
-            out.push_back((uint32_t)r | (kBlkLong << 30));
-            ++r;
-        } else if (len > kShort) {
-            out.push_back((uint32_t)r | (kBlkWave << 30));
-            int64_t nz = 0;
-            while (r < m) {
-                const int64_t l = rp[r + 1] - rp[r];
-                if (l <= kShort || l > kLong || (nz > 0 && nz + l > 4 * (int64_t)E)) break;
-                nz += l;
-                ++r;
-            }
-        } else {
-            out.push_back((uint32_t)r | (kBlkStream << 30));
-            int64_t nz = 0, c = 0;
-            while (r < m && c < kRows) {
-                const int64_t l = rp[r + 1] - rp[r];
-                if (l > kShort || nz + l > E) break;
-                nz += l;
-                ++r;
-                ++c;
-            }
-        }
-    }
-    out.push_back((uint32_t)m);
-    out_k.push_back(rp[m]);
-}
-
 spk_status get_blocks(spk_handle h, spk_mat *A, int entries, BlockData **out)
 {
     std::lock_guard<std::mutex> lk(h->mu);
@@ -553,7 +515,7 @@ spk_status get_blocks(spk_handle h, spk_mat *A, int entries, BlockData **out)
         return SPK_OK;
     }
     BlockData d;
-    make_blocks(A->rp_host, A->nrows, entries, d.host, d.host_k);
+    make_blocks(A->rp_host.data(), A->nrows, entries, d.host, d.host_k);
     d.nblk = (int32_t)d.host.size() - 1;
     SPK_HIP(hipMalloc(&d.blk, sizeof(uint32_t) * d.host.size()));
     SPK_HIP(hipMalloc(&d.bk, sizeof(int32_t) * d.host_k.size()));
@@ -592,6 +554,7 @@ static void free_mat(spk_mat *A)
         for (spk_mat *S : kv.second.sub) free_mat(S);
         for (auto &pp : kv.second.part) (void)hipFree(pp.second);
     }
+    for (auto &kv : A->xwin) free_xwin(kv.second);
     delete A;
 }
 
@@ -1013,8 +976,9 @@ spk_status spk_spmv_csr(spk_handle h, const spk_csr *A, const void *x, void *y, 
     p.dtype = A->dtype;
     spk_variant v;
     SPK_TRY(resolve(h, p, A, &v));
+    // formats built from a registered matrix do not apply to a borrowed one
     if (v.format == SPK_FMT_SELL || v.format == SPK_FMT_ADAPTIVE || v.format == SPK_FMT_DIA ||
-        v.format == SPK_FMT_STENCIL)
+        v.format == SPK_FMT_STENCIL || v.format == SPK_FMT_COLBLOCK || v.format == SPK_FMT_XWIN)
         v = default_variant(h, p, A);
     SpmvProblem q;
     q.csr = A;

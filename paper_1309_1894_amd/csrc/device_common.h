@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include "batch_types.h"
+#include "row_tiles.h"
 
 namespace spk {
 
@@ -165,11 +166,6 @@ struct SpmvArgs {
 };
 
 // Row blocks of the LDS-staged kernel are wavefront tiles:
-constexpr uint32_t kBlkRowMask = 0x3FFFFFFFu;
-constexpr uint32_t kBlkStream = 0u;     // short rows streamed through the wavefront's LDS slice
-constexpr int kStreamRowsPerThread = 2; // a workgroup row stream holds at most 2*BS rows
-constexpr uint32_t kBlkWave = 1u;       // medium rows, one after another, 64 lanes per row
-constexpr uint32_t kBlkLong = 2u;       // one long row, 64 lanes
 
 // ------------------------------------------------------------ batched tiles
 

@@ -71,6 +71,37 @@ struct ColBlockData {
     std::map<hipStream_t, double *> part;
 };
 
+// SPK_FMT_XWIN (see kernels.h, XwinArgs): the entries regrouped by column
+// window, built on first use for one window size; the wavefront tiles and
+// chunks of each (entries per wavefront, chunks per compute unit); the FP64
+// partials, one per (row, window) pair, per stream.
+struct XwinPlan {
+    uint32_t *tiles = nullptr;      // ntiles + 1
+    int32_t *tile_k = nullptr;      // ntiles + 1
+    int32_t *chunk_t = nullptr;     // nchunk + 1
+    int32_t *chunk_w = nullptr;     // nchunk
+    int32_t ntiles = 0, nchunk = 0;
+    int64_t bytes = 0;
+};
+
+struct XwinData {
+    int64_t wc = 0;                 // window columns
+    int64_t nwin = 0, npairs = 0;
+    uint16_t *ci = nullptr;         // nnz, column inside the window
+    void *val = nullptr;            // nnz, window-major
+    int32_t *ent = nullptr;         // npairs + 1
+    int32_t *pos_ptr = nullptr;     // nrows + 1: row i's pairs are [pos_ptr[i], pos_ptr[i+1]) in window order
+    uint16_t *rowpos = nullptr;     // npairs: each staged partial's place in its row block's row order
+    int32_t *first = nullptr;       // nblk * nwin: first pair of each window's run in each row block
+    int32_t *pre = nullptr;         // nblk * (nwin + 1): staging slot of each run
+    int64_t rb = 0, nblk = 0;       // rows per block of the second pass, blocks
+    std::vector<int32_t> ent_host;
+    std::vector<int64_t> pair_off;  // nwin + 1: first pair of each window
+    std::map<std::pair<int, int>, XwinPlan> plans;
+    std::map<hipStream_t, double *> part;
+    int64_t bytes = 0;
+};
+
 struct BlockData {
     uint32_t *blk = nullptr;    // nblk + 1 entries (start row | mode << 30)
     int32_t *bk = nullptr;      // nblk + 1 entries (first entry of each block)
@@ -113,6 +144,7 @@ struct spk_mat {
     spk::StructInfo st;
     spk::DiaData dia;                                        // built on first use
     std::map<int, spk::ColBlockData> colblk;                 // by block count, built on first use
+    std::map<int, spk::XwinData> xwin;                       // by window KiB, built on first use
 };
 
 namespace spk {
@@ -236,6 +268,11 @@ int64_t format_bytes(const spk_mat *A, int format, bool fused);
 // Derived formats of a registered matrix (built on first use; synchronous).
 spk_status get_sell(spk_handle h, spk_mat *A, int C, SellData **out);
 spk_status get_blocks(spk_handle h, spk_mat *A, int entries, BlockData **out);
+
+// SPK_FMT_XWIN: kernel entry, validity, run and release.
+const XwinEntry *find_xwin_entry(int block, int window_kib, int entries);
+spk_status run_xwin(spk_handle h, const SpmvProblem &p, const spk_variant &v, hipStream_t s);
+void free_xwin(XwinData &d);
 int64_t sell_padded_entries(const spk_mat *A, int C);
 
 // Plan DB persistence.

@@ -88,6 +88,60 @@ struct SpmvEntry {
 
 const SpmvEntry *spmv_table(int *count);
 
+// ------------------------------------------- x staged in LDS by window
+
+// SPK_FMT_XWIN: the entries regrouped by column window (window w holds the
+// columns [w*WC, (w+1)*WC), WC = window bytes / sizeof(T)) into (row,
+// window) pairs, window-major and, inside a window, in row order; a pair's
+// entries keep their order in the row.  Pair p has entries [ent[p],
+// ent[p+1]) of ci (column inside the window) and val.  Wavefront tiles over
+// the pairs never cross a window (start pair | mode << 30, as the row
+// blocks of the LDS-staged kernel, and their first entries); chunk c is the
+// tiles [chunk_t[c], chunk_t[c+1]) of window chunk_w[c], one workgroup each.
+struct XwinArgs {
+    const uint32_t *tiles;     // ntiles + 1
+    const int32_t *tile_k;     // ntiles + 1
+    const int32_t *chunk_t;    // nchunk + 1
+    const int32_t *chunk_w;    // nchunk
+    const int32_t *ent;        // npairs + 1
+    const uint16_t *ci;        // nnz
+    const void *val;           // T[nnz]
+    const void *x;             // T[n]
+    int64_t n;
+    double *part;              // npairs FP64 partial sums
+    int32_t nchunk;
+};
+
+using XwinFn = hipError_t (*)(const XwinArgs &a, hipStream_t s);
+
+struct XwinEntry {
+    int block, window_kib, entries;   // a variant's block, group and lds
+    XwinFn fn[2];                     // [dtype]
+};
+
+const XwinEntry *xwin_table(int *count);
+
+// Second pass, one workgroup per block of rb rows (block b = rows [b*rb,
+// (b+1)*rb)): the block's partials are read run by run (window w's run
+// starts at pair first[b*nwin + w] and at slot pre[b*(nwin+1) + w]) and
+// placed in LDS in row order (slot j of the block goes to place
+// rowpos[pos_ptr[b*rb] + j]), then y_i = the sum of row i's places (its
+// pairs in window order); w_i = alpha*y_i + x_i when fused.
+struct XsumArgs {
+    int64_t m;
+    int32_t rb, nwin;
+    const int32_t *first;      // nblk * nwin
+    const int32_t *pre;        // nblk * (nwin + 1)
+    const int32_t *pos_ptr;    // m + 1
+    const uint16_t *rowpos;    // npairs
+    const double *part;        // npairs
+    void *y, *w;
+    const void *x;
+    double alpha;
+};
+
+hipError_t launch_xwin_sum(int dtype, bool fused, const XsumArgs &a, hipStream_t s);
+
 // ------------------------------------------------ structured SpMV formats
 
 constexpr int kMaxDiag = 16;

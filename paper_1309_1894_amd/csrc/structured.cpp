@@ -159,6 +159,7 @@ bool format_applies(const spk_mat *A, int format)
     if (format == SPK_FMT_DIA) return A && A->st.dia;
     if (format == SPK_FMT_STENCIL) return A && A->st.stencil;
     if (format == SPK_FMT_COLBLOCK) return A && A->dtype == SPK_F64;
+    if (format == SPK_FMT_XWIN) return A != nullptr;
     return format >= SPK_FMT_SCALAR && format <= SPK_FMT_ADAPTIVE;
 }
 
@@ -264,7 +265,7 @@ spk_status spk_matrix_formats(spk_handle h, spk_matrix A, uint32_t *mask)
 {
     if (!h || !A || !mask) return fail(SPK_ERR_NULL, "NULL argument");
     uint32_t m = 0;
-    for (int f = SPK_FMT_SCALAR; f <= SPK_FMT_COLBLOCK; ++f)
+    for (int f = SPK_FMT_SCALAR; f <= SPK_FMT_XWIN; ++f)
         if (format_applies(A, f)) m |= 1u << f;
     *mask = m;
     return SPK_OK;

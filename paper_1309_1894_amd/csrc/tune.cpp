@@ -162,6 +162,27 @@ void candidate_space(const Ctx &c, uint32_t formats, std::vector<spk_variant> &o
             ++*pruned;
         }
     }
+    // x staged in LDS by column window: when x is larger than one XCD's L2
+    if ((!formats || (formats & (1u << SPK_FMT_XWIN))) && format_applies(A, SPK_FMT_XWIN)) {
+        if (A->ncols * (int64_t)dtype_size(A->dtype) > ((int64_t)4 << 20)) {
+            int nx = 0;
+            const XwinEntry *xt = xwin_table(&nx);
+            for (int i = 0; i < nx; ++i)
+                for (int g : {1, 2}) {
+                    spk_variant v{};
+                    v.format = SPK_FMT_XWIN;
+                    v.block = xt[i].block;
+                    v.group = xt[i].window_kib;
+                    v.lds = xt[i].entries;
+                    v.grid = g;
+                    v.unroll = 1;
+                    v.streams = 1;
+                    out.push_back(v);
+                }
+        } else {
+            ++*pruned;
+        }
+    }
     // structured formats, when the matrix admits them
     int ns = 0;
     const StructEntry *st = struct_table(&ns);
@@ -323,7 +344,7 @@ extern "C" spk_status spk_tune(spk_handle h, const spk_problem *problem, const s
     };
     for (const spk_variant &v : space) SPK_TRY(consider(v));
     if (spmv && tried > 0 && bestv.format != SPK_FMT_DIA && bestv.format != SPK_FMT_STENCIL &&
-        bestv.format != SPK_FMT_COLBLOCK) {
+        bestv.format != SPK_FMT_COLBLOCK && bestv.format != SPK_FMT_XWIN) {
         // refinement: the winner split over 2 and 4 streams
         for (int s2 : {2, 4}) {
             spk_variant v = bestv;

@@ -27,10 +27,11 @@ SPK_OK = 0
 SPK_F32, SPK_F64 = 0, 1
 SPK_OP_SPMV, SPK_OP_WAXPY, SPK_OP_AXPY, SPK_OP_DOT, SPK_OP_SPMV_WAXPY = 0, 1, 2, 3, 4
 SPK_FMT_AUTO, SPK_FMT_SCALAR, SPK_FMT_VECTOR, SPK_FMT_SELL, SPK_FMT_ADAPTIVE = 0, 1, 2, 3, 4
-SPK_FMT_DIA, SPK_FMT_STENCIL, SPK_FMT_COLBLOCK = 5, 6, 7
-# the formats that store the CSR entries (same algorithmic bytes)
+SPK_FMT_DIA, SPK_FMT_STENCIL, SPK_FMT_COLBLOCK, SPK_FMT_XWIN = 5, 6, 7, 8
+# the formats that store the CSR entries, in some order (measured on the CSR
+# algorithmic bytes)
 CSR_FORMATS = ((1 << SPK_FMT_SCALAR) | (1 << SPK_FMT_VECTOR) | (1 << SPK_FMT_SELL) | (1 << SPK_FMT_ADAPTIVE) |
-               (1 << SPK_FMT_COLBLOCK))
+               (1 << SPK_FMT_COLBLOCK) | (1 << SPK_FMT_XWIN))
 STATUS = {0: "SPK_OK", 1: "SPK_ERR_NULL", 2: "SPK_ERR_SHAPE", 3: "SPK_ERR_DTYPE", 4: "SPK_ERR_ALIAS",
           5: "SPK_ERR_CSR", 6: "SPK_ERR_OOM", 7: "SPK_ERR_BUDGET", 8: "SPK_ERR_HIP", 9: "SPK_ERR_VALIDATION",
           10: "SPK_ERR_NOT_FOUND", 11: "SPK_ERR_ARG", 12: "SPK_ERR_STATE"}
