@@ -135,7 +135,8 @@ def main():
 
     # plain baseline on the same batch: per-instance plain kernels, unfused
     cfg = batch.config()
-    kname = (f"k_batch_{'persistent' if cfg['persistent'] else 'grid'}<double,{cfg['block']},{cfg['tile_nnz']}>")
+    kname = (f"k_batch_{'persistent' if cfg['persistent'] else 'grid'}<double,{cfg['block']},{cfg['tile_nnz']},"
+             f"{cfg['x_window']}>")
     if args.no_plain:
         plain = {"ms": None, "skipped": True}
         plain_bd = {"ms": None, "skipped": True}
@@ -762,7 +763,7 @@ def cpu_single_thread(B, x, alpha, step_bytes, steps=3):
 
 # The files whose contents define the batched tile kernel's device code:
 # the committed counter figures apply only while these are unchanged.
-TILE_KERNEL_SOURCES = ["kernels_batch.hip", "device_rows.h", "device_common.h", "batch_types.h"]
+TILE_KERNEL_SOURCES = ["kernels_batch.hip", "device_rows.h", "device_common.h", "batch_types.h", "row_tiles.h"]
 
 
 def tile_kernel_hash() -> str:

@@ -517,6 +517,12 @@ typedef struct {
     int32_t tile_nnz;        /* target entries per tile of the lane-group
                               * modes (0 -> 1024) */
     int32_t waves_per_cu;    /* persistent residency (0 -> from occupancy) */
+    int32_t x_window;        /* LDS room for x per wavefront (entries; 0 or 256)
+                              * of the kernel used with an explicit block; a
+                              * kernel with room runs the tiles of classes
+                              * tuned to mode 1 with the tile's window of x
+                              * staged in LDS (block 0 takes the recorded
+                              * value) */
 } spk_batch_opts;
 
 /* Plans the batch (not in the paper; the configured batched workload):
@@ -547,8 +553,10 @@ spk_status spk_batch_run(spk_handle h, spk_batch b, double alpha, const void *x,
                          spk_stream stream);
 
 /* Tunes the batch (Section 2's search): the launch shape (workgroup size,
- * LDS tile per workgroup, grid or persistent kind) on the whole batch, then
- * the tile kernel of each shape class under it, then the launch shape again
+ * LDS tile per workgroup, room for x in LDS, grid or persistent kind) on
+ * the whole batch, then the tile kernel of each shape class under it (LDS
+ * row stream, the same with the tile's x window staged in LDS when the
+ * kernel has room for it, or G lanes per row), then the launch shape again
  * with the tuned kernels.  Every candidate is validated before it is timed
  * against the unannotated program's output: the plain kernel (one lane per
  * row, fused with the update when w is given) run instance by instance,
@@ -560,8 +568,9 @@ spk_status spk_batch_run(spk_handle h, spk_batch b, double alpha, const void *x,
  * SPK_ERR_VALIDATION.  Re-plans the tiles.  With
  * opts->record the winners go to the plan DB: one plan per class
  * ("batch:<dtype>:c<class>") and the launch shape ("batch:<dtype>:launch":
- * block, lds = LDS tile entries per workgroup, grid = 1 for the persistent
- * kind), which later plans with block 0 take. */
+ * block, lds = LDS tile entries per workgroup, unroll = LDS room for x per
+ * wavefront, grid = 1 for the persistent kind), which later plans with
+ * block 0 take. */
 spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x, void *y, void *w,
                           const spk_tune_opts *opts, spk_tune_report *report);
 

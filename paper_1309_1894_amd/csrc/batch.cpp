@@ -85,16 +85,16 @@ static std::string batch_launch_key(int dtype)
     return std::string("batch:") + dtype_name(dtype) + ":launch";
 }
 
-const BatchEntry *batch_entry(int block, int tile)
+const BatchEntry *batch_entry(int block, int tile, int xw)
 {
     int n = 0;
     const BatchEntry *t = batch_table(&n);
     for (int i = 0; i < n; ++i)
-        if (t[i].block == block && t[i].tile == tile) return &t[i];
+        if (t[i].block == block && t[i].tile == tile && t[i].xw == xw) return &t[i];
     return nullptr;
 }
 
-bool is_stream_mode(int mode) { return mode == 0; }
+bool is_stream_mode(int mode) { return mode == 0 || mode == 1; }
 
 void cut_rows(const int32_t *rp, int64_t m, int mode, int entries, int64_t target, std::vector<BatchTile> &out)
 {
@@ -250,6 +250,9 @@ spk_status upload_tiles(spk_batch b, const std::vector<BatchTile> &tiles)
     if (!tiles.empty()) {
         SPK_HIP(hipMemcpyAsync(b->d_tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice,
                                b->h->work));
+        // the x windows of mode-1 tiles, for a kernel with room for them
+        if (b->entry->xw > 0)
+            SPK_HIP(launch_tile_windows(b->d_tiles, (int64_t)tiles.size(), b->entry->xw, b->h->work));
         SPK_HIP(hipStreamSynchronize(b->h->work));
     }
     return SPK_OK;
@@ -288,7 +291,8 @@ spk_status occupancy(spk_batch b)
     // waits on another workgroup, so a workgroup that does not fit at once
     // simply starts later.
     const int nw = b->entry->block / 64;
-    const int64_t lds = (int64_t)b->entry->tile * 8 + (int64_t)nw * (2 * 64 + 1) * 4;
+    const int64_t lds = (int64_t)b->entry->tile * 8 + (int64_t)nw * (2 * 64 + 1) * 4 +
+                        (int64_t)nw * b->entry->xw * (int64_t)dtype_size(b->dtype);
     const int64_t by_lds = (160 * 1024) / std::max<int64_t>(1, lds);
     const int64_t by_waves = 32 / nw;
     int64_t per_cu = std::max<int64_t>(b->entry->occupancy[b->dtype](), std::min(by_lds, by_waves));
@@ -321,22 +325,23 @@ spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *d, const spk_batch
         o = *opts;
     }
     // block 0: the launch shape recorded by spk_batch_tune for this dtype,
-    // if any (workgroup size, LDS tile and launch kind), else 256 threads
-    // with 2048-entry tiles
+    // if any (workgroup size, LDS tile, room for x and launch kind), else
+    // 256 threads with 2048-entry tiles and no room for x
     const BatchEntry *e = nullptr;
     if (o.block == 0) {
         spk_variant lv{};
         if (spk_plan_get(h, batch_launch_key(d->dtype).c_str(), &lv) == SPK_OK &&
-            (e = batch_entry(lv.block, lv.lds)) != nullptr)
+            (e = batch_entry(lv.block, lv.lds, lv.unroll)) != nullptr)
             o.persistent = lv.grid ? kBatchPersistent : kBatchGrid;
         o.block = e ? e->block : 256;
+        if (!e) o.x_window = 0;
     }
     if (o.tile_nnz == 0) o.tile_nnz = 1024;
     if (o.persistent != kBatchGrid && o.persistent != kBatchPersistent)
         return fail(SPK_ERR_ARG, "persistent must be 0 or 1 (got %d)", o.persistent);
     if (o.tile_nnz < 0 || o.waves_per_cu < 0) return fail(SPK_ERR_ARG, "negative tile_nnz or waves_per_cu");
-    if (!e) e = batch_entry(o.block, 2048);
-    if (!e) return fail(SPK_ERR_ARG, "no batched kernel with block %d", o.block);
+    if (!e) e = batch_entry(o.block, 2048, o.x_window);
+    if (!e) return fail(SPK_ERR_ARG, "no batched kernel with block %d and x window %d", o.block, o.x_window);
 
     int64_t rp_total = 0;
     for (int64_t i = 0; i < d->count; ++i) {
@@ -388,7 +393,7 @@ spk_status spk_batch_plan(spk_handle h, const spk_batch_desc *d, const spk_batch
         b->cls[i] = c;
         if (!b->mode.count(c)) {
             spk_variant v{};
-            if (spk_plan_get(h, batch_key(b->dtype, c).c_str(), &v) == SPK_OK && (v.group == 0 || v.group >= 2))
+            if (spk_plan_get(h, batch_key(b->dtype, c).c_str(), &v) == SPK_OK && (v.group >= 0 && v.group <= 64))
                 b->mode[c] = v.group;
             else
                 b->mode[c] = batch_default_mode(c, batch_wave_entries(*e));
@@ -622,8 +627,8 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
                 double med = 0;
                 SPK_TRY(validate_and_time((int64_t)b->tiles.size(), &med));
                 if (o.verbose)
-                    fprintf(stderr, "spk_batch_tune: block %d tile %d persistent %d: %.2f us\n", tab[i].block,
-                            tab[i].tile, pers, med);
+                    fprintf(stderr, "spk_batch_tune: block %d tile %d x window %d persistent %d: %.2f us\n",
+                            tab[i].block, tab[i].tile, tab[i].xw, pers, med);
                 if (med > 0 && med < best_t) {
                     best_t = med;
                     best_e = &tab[i];
@@ -647,13 +652,27 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
         double best = 1e300;
         int best_mode = b->mode[c];
         double plain_time = -1.0;
-        for (int mode : {0, 2, 4, 8, 16, 32, 64}) {
+        for (int mode : {0, 1, 2, 4, 8, 16, 32, 64}) {
+            // mode 1 is timed with the kernel of the same shape that has
+            // room for x (without that room it would run as mode 0)
+            const BatchEntry *keep = b->entry;
+            if (mode == 1) {
+                const BatchEntry *xe = keep->xw > 0 ? keep : batch_entry(keep->block, keep->tile, 256);
+                if (!xe) continue;
+                b->entry = xe;
+                SPK_TRY(occupancy(b));
+            }
             std::vector<BatchTile> tl;
             for (int64_t i : kv.second) cut_instance(b, i, mode, tl);
-            SPK_TRY(upload_tiles(b, tl));
+            spk_status ts = upload_tiles(b, tl);
             // only this class's rows are rewritten by the trial launches
             double med = 0;
-            SPK_TRY(validate_and_time((int64_t)tl.size(), &med));
+            if (ts == SPK_OK) ts = validate_and_time((int64_t)tl.size(), &med);
+            if (b->entry != keep) {
+                b->entry = keep;
+                SPK_TRY(occupancy(b));
+            }
+            SPK_TRY(ts);
             if (med < 0) continue;
             if (o.verbose) fprintf(stderr, "spk_batch_tune: class %d mode %d: %.2f us\n", c, mode, med);
             if (mode == batch_default_mode(c, batch_wave_entries(*b->entry))) plain_time = med;
@@ -688,6 +707,7 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
         spk_variant lv{};
         lv.block = b->entry->block;
         lv.lds = b->entry->tile;
+        lv.unroll = b->entry->xw;
         lv.grid = b->opts.persistent == kBatchPersistent ? 1 : 0;
         lv.streams = 1;
         const std::string key = batch_launch_key(b->dtype);
@@ -714,6 +734,7 @@ spk_status spk_batch_config(spk_handle h, spk_batch b, spk_batch_opts *out)
     *out = b->opts;
     out->block = b->entry->block;
     out->tile_nnz = b->entry->tile;
+    out->x_window = b->entry->xw;
     out->waves_per_cu = (int32_t)(b->grid_persistent / std::max(1, b->h->num_cu)) * (b->entry->block / 64);
     return SPK_OK;
 }

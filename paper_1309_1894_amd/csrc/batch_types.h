@@ -8,7 +8,11 @@ namespace spk {
 
 // A tile is rows [r0, r1) (entries [k0, k1)) of one CSR matrix, processed
 // with kernel `mode`: 0 = LDS-staged row stream summed one lane per row,
-// G in {2, 4, ..., 64} = G lanes per row straight from memory.  The tile
+// 1 = the same with the tile's window of x staged in LDS too (columns
+// [xlo, xlo + xn), found on the device after planning; xn = 0 when the
+// window is wider than the kernel's room for it, and then x is gathered
+// from memory as in mode 0), G in {2, 4, ..., 64} = G lanes per row
+// straight from memory.  The tile
 // carries its matrix's arrays and the offset of the matrix's vectors inside
 // the launch's x / y / w, so a wavefront needs one 64-byte descriptor load
 // before it can start streaming.
@@ -18,7 +22,7 @@ struct BatchTile {
     const void *val;
     int64_t vec_off;
     int32_t r0, r1, k0, k1;
-    int32_t mode, pad0, pad1, pad2;
+    int32_t mode, xlo, xn, pad;
 };
 
 static_assert(sizeof(BatchTile) == 64, "tile descriptor is one 64-byte line");

@@ -56,10 +56,15 @@ __device__ __forceinline__ gptr_mut<T> as_global_mut(T *p) { return (gptr_mut<T>
 // interleaved partial sums).
 // With DOT, also returns the lane's part of sum_i x_i*y_i over the tile's
 // rows (square matrices: x_i is the row's own entry of x).
-template <typename T, int ITEMS, bool DOT = false>
+// With XW > 0 and xn > 0, the tile's window of x (columns [xlo, xlo + xn),
+// xn <= XW, every column of the tile inside it) is copied to the
+// wavefront's LDS slice xs with coalesced loads issued together with the
+// entry loads (they do not wait for the column indices), and the gathers
+// read LDS.
+template <typename T, int ITEMS, bool DOT = false, int XW = 0>
 __device__ __forceinline__ double wave_stream(const int32_t *rp_, const int32_t *ci_, const T *val_, const T *x_,
                                               T *y_, T *w_, T alpha, int r0, int r1, int k0, int k1, double *sp,
-                                              int *srp)
+                                              int *srp, int xlo = 0, int xn = 0, T *xs = nullptr)
 {
     constexpr int STEPS = (ITEMS * kWave + 3 + 4 * kWave - 1) / (4 * kWave);
     static_assert(STEPS * 4 * kWave <= 2 * kWave * ITEMS, "staged index groups must fit the product slice");
@@ -89,6 +94,15 @@ __device__ __forceinline__ double wave_stream(const int32_t *rp_, const int32_t 
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) v[j] = __builtin_nontemporal_load(val + k0 + min(l + j * kWave, klast));
     }
+    constexpr int XQ = XW > 0 ? XW / kWave : 1;
+    T xwv[XQ];
+    const bool win = XW > 0 && xn > 0;
+    if constexpr (XW > 0) {
+        if (win) {
+#pragma unroll
+            for (int q = 0; q < XQ; ++q) xwv[q] = x[xlo + min(l + q * kWave, xn - 1)];
+        }
+    }
     int rpv[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) rpv[q] = rp[r0 + min(l + q * kWave, nr)] - k0;
@@ -100,14 +114,26 @@ __device__ __forceinline__ double wave_stream(const int32_t *rp_, const int32_t 
     if (nk > 0) {
 #pragma unroll
         for (int s = 0; s < STEPS; ++s) *(int4v *)(sci + 4 * (l + kWave * s)) = g[s];
+        if constexpr (XW > 0) {
+            if (win) {
+#pragma unroll
+                for (int q = 0; q < XQ; ++q)
+                    if (l + q * kWave < xn) xs[l + q * kWave] = xwv[q];
+            }
+        }
         wave_lds_sync();
         int c[ITEMS];
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) c[j] = sci[min(l + j * kWave, klast) + off];
         wave_lds_sync();   // the staged indices are read before products overwrite them
         T xv[ITEMS];
+        if (win) {
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) xv[j] = x[c[j]];
+            for (int j = 0; j < ITEMS; ++j) xv[j] = xs[c[j] - xlo];
+        } else {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) xv[j] = x[c[j]];
+        }
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const int k = l + j * kWave;

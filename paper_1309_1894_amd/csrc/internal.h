@@ -290,7 +290,7 @@ int batch_class(int64_t m, int64_t nnz);
 bool is_stream_mode(int mode);
 int batch_default_mode(int cls, int entries);
 std::string batch_key(int dtype, int cls);
-const BatchEntry *batch_entry(int block, int tile);
+const BatchEntry *batch_entry(int block, int tile, int xw);
 
 // Cuts rows [0, m) of one CSR (host row_ptr) into wavefront tiles for
 // `mode` (0 = LDS row stream of at most `entries` entries and 128 rows;

@@ -206,6 +206,7 @@ constexpr int kBatchPersistent = 1;  // persistent grid pulling tile groups from
 
 struct BatchEntry {
     int block, tile;     // threads per workgroup, LDS products per workgroup
+    int xw;              // LDS room for x per wavefront (entries) for mode-1 tiles, 0 = none
     BatchFn fn[2][2];    // [dtype][launch kind]
     int (*occupancy[2])();  // [dtype] resident workgroups per CU (persistent kernel)
 };
@@ -214,6 +215,12 @@ const BatchEntry *batch_table(int *count);
 
 // Row-stream capacity (entries) of one wavefront's tile.
 inline int batch_wave_entries(const BatchEntry &e) { return e.tile / (e.block / 64); }
+
+// The x windows of mode-1 tiles: for each such tile with entries, the
+// smallest and largest column of its entries; the window is recorded
+// (xlo, xn) when it spans at most `cap` columns, else xn = 0.  One
+// wavefront per tile.
+hipError_t launch_tile_windows(BatchTile *tiles, int64_t ntiles, int cap, hipStream_t s);
 
 // ------------------------------------------------------ conjugate gradients
 

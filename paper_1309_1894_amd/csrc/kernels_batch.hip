@@ -35,8 +35,8 @@ struct WaveTiles {
     static_assert(ITEMS * kWave * NW == TILE, "tile must split evenly over the wavefronts");
 };
 
-template <typename T, int BS, int TILE>
-__device__ __forceinline__ void run_wave_tile(const BatchArgs<T> &a, const BatchTile &td, double *sp, int *srp)
+template <typename T, int BS, int TILE, int XW>
+__device__ __forceinline__ void run_wave_tile(const BatchArgs<T> &a, const BatchTile &td, double *sp, int *srp, T *xs)
 {
     const int32_t *rp = td.rp;
     const int32_t *ci = td.ci;
@@ -49,6 +49,11 @@ __device__ __forceinline__ void run_wave_tile(const BatchArgs<T> &a, const Batch
         wave_stream<T, WaveTiles<T, BS, TILE>::ITEMS>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1, td.k0, td.k1,
                                                       sp, srp);
         break;
+    case 1:  // the same, x from the tile's window in LDS when it fits the kernel's room
+        wave_stream<T, WaveTiles<T, BS, TILE>::ITEMS, false, XW>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1,
+                                                                 td.k0, td.k1, sp, srp, td.xlo,
+                                                                 XW > 0 && td.xn <= XW ? td.xn : 0, xs);
+        break;
     case 2: wave_group_rows<T, 2>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
     case 4: wave_group_rows<T, 4>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
     case 8: wave_group_rows<T, 8>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
@@ -58,12 +63,13 @@ __device__ __forceinline__ void run_wave_tile(const BatchArgs<T> &a, const Batch
     }
 }
 
-template <typename T, int BS, int TILE>
+template <typename T, int BS, int TILE, int XW>
 __global__ __launch_bounds__(BS) void k_batch_grid(BatchArgs<T> a)
 {
     using WT = WaveTiles<T, BS, TILE>;
     __shared__ double sp[TILE];
     __shared__ int srp[WT::NW * (kWaveTileRows + 1)];
+    __shared__ T xs[WT::NW * (XW > 0 ? XW : 1)];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int ngroups = (a.ntiles + WT::NW - 1) / WT::NW;
     const int b = (int)blockIdx.x;
@@ -93,7 +99,8 @@ __global__ __launch_bounds__(BS) void k_batch_grid(BatchArgs<T> a)
     BatchTile td;
     __builtin_memcpy(&td, parts, sizeof td);
     if (voff >= 0) td.vec_off = voff;
-    run_wave_tile<T, BS, TILE>(a, td, sp + wv * WT::ENTRIES, srp + wv * (kWaveTileRows + 1));
+    run_wave_tile<T, BS, TILE, XW>(a, td, sp + wv * WT::ENTRIES, srp + wv * (kWaveTileRows + 1),
+                                   xs + wv * (XW > 0 ? XW : 1));
 }
 
 // Persistent form: a grid sized to fill the GPU whose wavefronts pull tiles
@@ -103,12 +110,13 @@ __global__ __launch_bounds__(BS) void k_batch_grid(BatchArgs<T> a)
 constexpr int kChunk = 4;
 constexpr int kCtrStride = 64;   // uint32 per counter line
 
-template <typename T, int BS, int TILE>
+template <typename T, int BS, int TILE, int XW>
 __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs<T> a)
 {
     using WT = WaveTiles<T, BS, TILE>;
     __shared__ double sp[TILE];
     __shared__ int srp[WT::NW * (kWaveTileRows + 1)];
+    __shared__ T xs[WT::NW * (XW > 0 ? XW : 1)];
     const int l = threadIdx.x & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int xcd = (int)blockIdx.x % kXcds;
@@ -117,6 +125,7 @@ __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs<T> a)
     uint32_t *head = a.next + xcd * kCtrStride;
     double *my_sp = sp + wv * WT::ENTRIES;
     int *my_srp = srp + wv * (kWaveTileRows + 1);
+    T *my_xs = xs + wv * (XW > 0 ? XW : 1);
     // the next claim is issued before the current chunk is streamed, so the
     // atomic's round trip overlaps the chunk's loads
     int claim = 0;
@@ -126,7 +135,7 @@ __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs<T> a)
         if (c0 >= hi) break;
         if (l == 0) claim = (int)atomicAdd(head, (uint32_t)kChunk);
         const int c1 = min(c0 + kChunk, hi);
-        for (int tile = c0; tile < c1; ++tile) run_wave_tile<T, BS, TILE>(a, a.tiles[tile], my_sp, my_srp);
+        for (int tile = c0; tile < c1; ++tile) run_wave_tile<T, BS, TILE, XW>(a, a.tiles[tile], my_sp, my_srp, my_xs);
     }
     // Every wavefront has drawn past the end of its queue before it counts
     // itself done, so the last one may reset all counters.  Only atomics
@@ -143,40 +152,69 @@ __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs<T> a)
     }
 }
 
+// The x windows of mode-1 tiles (see launch_tile_windows).
+__global__ __launch_bounds__(256) void k_tile_windows(BatchTile *tiles, int64_t ntiles, int cap)
+{
+    const int64_t t = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
+    if (t >= ntiles) return;
+    const int l = threadIdx.x & (kWave - 1);
+    BatchTile &td = tiles[t];
+    if (td.mode != 1) return;
+    const int k0 = td.k0, k1 = td.k1;
+    int lo = INT32_MAX, hi = -1;
+    for (int k = k0 + l; k < k1; k += kWave) {
+        const int c = td.ci[k];
+        lo = min(lo, c);
+        hi = max(hi, c);
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d *= 2) {
+        lo = min(lo, __shfl_xor(lo, d));
+        hi = max(hi, __shfl_xor(hi, d));
+    }
+    if (l == 0) {
+        const bool fits = hi >= lo && (int64_t)hi - lo + 1 <= cap;
+        td.xlo = fits ? lo : 0;
+        td.xn = fits ? hi - lo + 1 : 0;
+    }
+}
+
 namespace {
 
-template <typename T, int BS, int TILE>
+template <typename T, int BS, int TILE, int XW>
 int occ_batch()
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_batch_persistent<T, BS, TILE>),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_batch_persistent<T, BS, TILE, XW>),
                                                      BS, 0) != hipSuccess)
         n = 1;
     return n > 0 ? n : 1;
 }
 
-template <typename T, int BS, int TILE, int KIND>
+template <typename T, int BS, int TILE, int XW, int KIND>
 hipError_t L_batch(const void *p, dim3 g, hipStream_t s)
 {
     if constexpr (KIND == 1)
-        hipLaunchKernelGGL((k_batch_persistent<T, BS, TILE>), g, dim3(BS), 0, s, *(const BatchArgs<T> *)p);
+        hipLaunchKernelGGL((k_batch_persistent<T, BS, TILE, XW>), g, dim3(BS), 0, s, *(const BatchArgs<T> *)p);
     else
-        hipLaunchKernelGGL((k_batch_grid<T, BS, TILE>), g, dim3(BS), 0, s, *(const BatchArgs<T> *)p);
+        hipLaunchKernelGGL((k_batch_grid<T, BS, TILE, XW>), g, dim3(BS), 0, s, *(const BatchArgs<T> *)p);
     return hipGetLastError();
 }
 
-#define BENTRY(BS, TILE)                                                                     \
-    {BS, TILE,                                                                               \
-     {{L_batch<float, BS, TILE, 0>, L_batch<float, BS, TILE, 1>},                            \
-      {L_batch<double, BS, TILE, 0>, L_batch<double, BS, TILE, 1>}},                         \
-     {occ_batch<float, BS, TILE>, occ_batch<double, BS, TILE>}}
+#define BENTRY(BS, TILE, XW)                                                                 \
+    {BS, TILE, XW,                                                                           \
+     {{L_batch<float, BS, TILE, XW, 0>, L_batch<float, BS, TILE, XW, 1>},                    \
+      {L_batch<double, BS, TILE, XW, 0>, L_batch<double, BS, TILE, XW, 1>}},                 \
+     {occ_batch<float, BS, TILE, XW>, occ_batch<double, BS, TILE, XW>}}
 
-// (threads per workgroup, LDS products per workgroup): a wavefront's row
-// stream holds TILE/(BS/64) entries: 256, 512 or 1024
+// (threads per workgroup, LDS products per workgroup, LDS room for x per
+// wavefront): a wavefront's row stream holds TILE/(BS/64) entries: 256,
+// 512 or 1024; the kernels with room for x run mode-1 tiles from LDS
 const BatchEntry kBatch[] = {
-    BENTRY(256, 2048), BENTRY(256, 1024), BENTRY(256, 4096),
-    BENTRY(128, 1024), BENTRY(128, 2048),
-    BENTRY(512, 2048), BENTRY(512, 4096),
+    BENTRY(256, 2048, 0), BENTRY(256, 1024, 0), BENTRY(256, 4096, 0),
+    BENTRY(128, 1024, 0), BENTRY(128, 2048, 0),
+    BENTRY(512, 2048, 0), BENTRY(512, 4096, 0),
+    BENTRY(256, 2048, 256), BENTRY(256, 4096, 256), BENTRY(128, 2048, 256),
 };
 
 }  // namespace
@@ -185,6 +223,13 @@ const BatchEntry *batch_table(int *count)
 {
     *count = (int)(sizeof(kBatch) / sizeof(kBatch[0]));
     return kBatch;
+}
+
+hipError_t launch_tile_windows(BatchTile *tiles, int64_t ntiles, int cap, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_windows, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, tiles, ntiles, cap);
+    return hipGetLastError();
 }
 
 }  // namespace spk

@@ -222,6 +222,9 @@ spk_status upload(Server *S, PoolMat &M)
         // pageable source: the call returns once the tiles are staged
         SPK_HIP(hipMemcpyAsync(M.d_tiles, M.tiles.data(), sizeof(BatchTile) * M.tiles.size(), hipMemcpyHostToDevice,
                                S->upload));
+        // the x windows of mode-1 tiles, after the columns and tiles arrive
+        if (S->entry->xw > 0)
+            SPK_HIP(launch_tile_windows(M.d_tiles, (int64_t)M.tiles.size(), S->entry->xw, S->upload));
     }
     if (!M.uploaded) SPK_HIP(hipEventCreateWithFlags(&M.uploaded, hipEventDisableTiming));
     SPK_HIP(hipEventRecord(M.uploaded, S->upload));
@@ -538,7 +541,8 @@ spk_status spk_serve_create(spk_handle h, const spk_serve_opts *opts, spk_server
     Server *S = new Server();
     S->h = h;
     S->opts = o;
-    S->entry = batch_entry(256, 2048);
+    // with room for x in LDS: classes tuned to the windowed row stream run it
+    S->entry = batch_entry(256, 2048, 256);
     for (int i = 0; i < (o.mode == 1 ? 1 : o.streams); ++i) {
         hipStream_t s = nullptr;
         if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {

@@ -85,7 +85,7 @@ class spk_batch_desc(C.Structure):
 
 class spk_batch_opts(C.Structure):
     _fields_ = [("persistent", _I32), ("use_graph", _I32), ("block", _I32), ("tile_nnz", _I32),
-                ("waves_per_cu", _I32)]
+                ("waves_per_cu", _I32), ("x_window", _I32)]
 
 
 class spk_serve_opts(C.Structure):
@@ -557,7 +557,7 @@ class Batch:
     """Many independent CSR instances driven by one (persistent, graph-replayed) launch."""
 
     def __init__(self, host_batch, device_arrays, persistent=True, use_graph=True, block=256, tile_nnz=2048,
-                 handle=None):
+                 handle=None, x_window=0):
         """``host_batch``: inputs.Batch (sizes/offsets); ``device_arrays``: (row_ptr, col_idx, val) tensors.
         The keywords fill spk_batch_opts; ``tile_nnz`` defaults to 2048 here
         (0 gives the library's 1024) and ``block=0`` takes the launch shape a
@@ -573,7 +573,7 @@ class Batch:
         d.m, d.nnz, d.rp_off, d.nz_off, d.vec_off = (a.ctypes.data for a in self._host)
         d.row_ptr, d.col_idx, d.val = _dev(rp, "row_ptr"), _dev(ci, "col_idx"), _dev(val, "val")
         d.row_ptr_host = self._rp_host.ctypes.data
-        o = spk_batch_opts(int(persistent), int(use_graph), int(block), int(tile_nnz), 0)
+        o = spk_batch_opts(int(persistent), int(use_graph), int(block), int(tile_nnz), 0, int(x_window))
         b = _P()
         _ok(_lib.spk_batch_plan(self.handle.ptr, C.byref(d), C.byref(o), C.byref(b)), "spk_batch_plan")
         self.ptr = b.value

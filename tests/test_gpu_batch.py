@@ -281,3 +281,37 @@ def test_full_batched_workload(spk, dev):
     finally:
         b.free()
         h.close()
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_batch_x_window_mode(spk, dev, dt):
+    """Every class planned to the row stream with the tile's x window staged
+    in LDS (mode 1, a kernel with room for 256 entries of x per wavefront):
+    each instance matches the oracle, and the bits equal the plain row
+    stream's (mode 0; only where x is read from differs), also for tiles
+    whose window is too wide for the room (x then read from memory)."""
+    B = mixed_batch(dt)
+    x = I.batch_vector(B, seed=21, dtype=dt)
+    arrs = _dev_batch(B, dev)
+    xd = torch.from_numpy(x).to(dev)
+    outs = {}
+    for mode, xw in ((0, 0), (1, 256)):
+        h = spk.Handle(0)
+        for c in range(20):
+            spk.spk_plan_put(f"batch:{'f64' if dt == np.float64 else 'f32'}:c{c}",
+                             spk.make_variant(format=spk.SPK_FMT_ADAPTIVE, block=256, group=mode, unroll=1,
+                                              streams=1, lds=2048), handle=h)
+        b = spk.Batch(B, arrs, handle=h, block=256, x_window=xw)
+        y = torch.full((x.size,), float("nan"), dtype=xd.dtype, device=dev)
+        w = torch.full_like(y, float("nan"))
+        say(f"batch x window: mode {mode} room {xw} dtype={np.dtype(dt).name}")
+        try:
+            assert b.config()["x_window"] == xw
+            b.run(0.5, xd, y, w)
+            torch.cuda.synchronize()
+            _check_batch(B, x, y, w, 0.5, dt)
+            outs[mode] = (y.clone(), w.clone())
+        finally:
+            b.free()
+            h.close()
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
