@@ -69,7 +69,7 @@ const SpmvEntry *find_spmv_entry(const spk_variant &v)
         if (e.format != v.format || e.block != v.block || e.unroll != v.unroll) continue;
         if (e.format == SPK_FMT_VECTOR && (e.group != v.group || e.lds != v.lds)) continue;
         if (e.format == SPK_FMT_SELL && e.group != v.group) continue;
-        if (e.format == SPK_FMT_ADAPTIVE && e.lds != v.lds) continue;
+        if (e.format == SPK_FMT_ADAPTIVE && (e.lds != v.lds || e.group != v.group)) continue;
         return &e;
     }
     return nullptr;
@@ -384,7 +384,10 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
     SellData *sd = nullptr;
     BlockData *bd = nullptr;
     if (v.format == SPK_FMT_SELL) SPK_TRY(get_sell(h, p.mat, v.group, &sd));
-    if (v.format == SPK_FMT_ADAPTIVE) SPK_TRY(get_blocks(h, p.mat, v.lds, &bd));
+    if (v.format == SPK_FMT_ADAPTIVE) {
+        SPK_TRY(get_blocks(h, p.mat, v.lds, &bd));
+        if (v.group > 1) SPK_TRY(get_block_windows(h, p.mat, bd));
+    }
 
     const int parts = std::max(1, v.streams);
     // launch pieces: rows [cut[i], cut[i+1]) or row blocks for ADAPTIVE
@@ -417,6 +420,7 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
             if (v.format == SPK_FMT_ADAPTIVE) {
                 a.blocks = bd->blk;
                 a.block_k = bd->bk;
+                a.block_x = v.group > 1 ? bd->bx : nullptr;
                 a.blk0 = (int32_t)lo;
                 a.nblk = (int32_t)(hi - lo);   // one wavefront tile per wavefront
             } else {
@@ -530,6 +534,25 @@ spk_status get_blocks(spk_handle h, spk_mat *A, int entries, BlockData **out)
     return SPK_OK;
 }
 
+// The x windows of a matrix's row-stream blocks (room for 256 entries),
+// made on the device when a variant with room for x first needs them.
+spk_status get_block_windows(spk_handle h, spk_mat *A, BlockData *bd)
+{
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (bd->bx) return SPK_OK;
+    int32_t *bx = nullptr;
+    SPK_HIP(hipMalloc(&bx, sizeof(int32_t) * 2 * (size_t)std::max(1, bd->nblk)));
+    hipError_t e = launch_block_windows(bd->blk, bd->bk, A->ci, bd->nblk, 256, bx, h->work);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->work);
+    if (e != hipSuccess) {
+        (void)hipFree(bx);
+        return hip_fail(e, "block windows");
+    }
+    bd->bx = bx;
+    A->bytes += (int64_t)(sizeof(int32_t) * 2 * (size_t)bd->nblk);
+    return SPK_OK;
+}
+
 // ------------------------------------------------------- column blocks --
 
 // Frees a matrix and everything derived from it.
@@ -547,6 +570,7 @@ static void free_mat(spk_mat *A)
     for (auto &kv : A->blocks) {
         (void)hipFree(kv.second.blk);
         (void)hipFree(kv.second.bk);
+        if (kv.second.bx) (void)hipFree(kv.second.bx);
     }
     if (A->dia.val) (void)hipFree(A->dia.val);
     if (A->dia.mask) (void)hipFree(A->dia.mask);

@@ -162,6 +162,7 @@ struct SpmvArgs {
     // nblk + 1 entries each
     const uint32_t *blocks;
     const int32_t *block_k;
+    const int32_t *block_x;   // row-stream blocks' x windows (first column, length; length 0 = none), or null
     int32_t blk0, nblk;
 };
 

@@ -105,6 +105,7 @@ struct XwinData {
 struct BlockData {
     uint32_t *blk = nullptr;    // nblk + 1 entries (start row | mode << 30)
     int32_t *bk = nullptr;      // nblk + 1 entries (first entry of each block)
+    int32_t *bx = nullptr;      // 2 * nblk: x window of each row-stream block (made when first needed)
     int32_t nblk = 0;
     std::vector<uint32_t> host;
     std::vector<int32_t> host_k;
@@ -268,6 +269,7 @@ int64_t format_bytes(const spk_mat *A, int format, bool fused);
 // Derived formats of a registered matrix (built on first use; synchronous).
 spk_status get_sell(spk_handle h, spk_mat *A, int C, SellData **out);
 spk_status get_blocks(spk_handle h, spk_mat *A, int entries, BlockData **out);
+spk_status get_block_windows(spk_handle h, spk_mat *A, BlockData *bd);
 
 // SPK_FMT_XWIN: kernel entry, validity, run and release.
 const XwinEntry *find_xwin_entry(int block, int window_kib, int entries);

@@ -222,6 +222,12 @@ inline int batch_wave_entries(const BatchEntry &e) { return e.tile / (e.block / 
 // wavefront per tile.
 hipError_t launch_tile_windows(BatchTile *tiles, int64_t ntiles, int cap, hipStream_t s);
 
+// The same for the row-stream blocks of the single-matrix row-block kernel:
+// bx[2b], bx[2b+1] = first column and length of block b's window (length 0
+// for other blocks and for windows wider than `cap`).
+hipError_t launch_block_windows(const uint32_t *blocks, const int32_t *block_k, const int32_t *ci, int32_t nblk,
+                                int cap, int32_t *bx, hipStream_t s);
+
 // ------------------------------------------------------ conjugate gradients
 
 // Device scalars of one solve: r.r of the current iteration alternates

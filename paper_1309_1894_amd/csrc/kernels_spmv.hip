@@ -130,12 +130,15 @@ __global__ __launch_bounds__(BS) void k_spmv_sell(SpmvArgs<T> a)
 // Row blocks are wavefront tiles (precomputed at registration for a
 // wavefront capacity of E entries): each wavefront of a workgroup runs its
 // own block with a private LDS slice, without workgroup barriers.
-template <typename T, int BS, int E, bool FUSED>
+// With XW > 0, row-stream blocks whose x window fits XW entries take x from
+// LDS (the window copied there beside the entry loads).
+template <typename T, int BS, int E, int XW, bool FUSED>
 __global__ __launch_bounds__(BS) void k_spmv_adaptive(SpmvArgs<T> a)
 {
     constexpr int NW = BS / kWave;
     __shared__ double sp[NW * E];
     __shared__ int srp[NW * (kWaveTileRows + 1)];
+    __shared__ T xs[NW * (XW > 0 ? XW : 1)];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int ngroups = (a.nblk + NW - 1) / NW;
     const int g = xcd_remap((int)blockIdx.x, ngroups);
@@ -147,12 +150,56 @@ __global__ __launch_bounds__(BS) void k_spmv_adaptive(SpmvArgs<T> a)
     const uint32_t mode = e0 >> 30;
     T *w = FUSED ? a.w : nullptr;
     if (mode == kBlkStream) {
-        wave_stream<T, E / kWave>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, r1, a.block_k[b], a.block_k[b + 1],
-                                  sp + wv * E, srp + wv * (kWaveTileRows + 1));
+        int xlo = 0, xn = 0;
+        if constexpr (XW > 0) {
+            xlo = a.block_x[2 * b];
+            xn = a.block_x[2 * b + 1];
+            xn = xn <= XW ? xn : 0;
+        }
+        wave_stream<T, E / kWave, false, XW>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, r1, a.block_k[b],
+                                             a.block_k[b + 1], sp + wv * E, srp + wv * (kWaveTileRows + 1), xlo, xn,
+                                             xs + wv * (XW > 0 ? XW : 1));
     } else {
         // medium rows (kBlkWave) and single long rows (kBlkLong)
         wave_rows_mlp<T, 8>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, r1);
     }
+}
+
+// --------------------------------------------------- block x windows --
+
+__global__ __launch_bounds__(256) void k_block_windows(const uint32_t *blocks, const int32_t *block_k,
+                                                       const int32_t *ci, int32_t nblk, int cap, int32_t *bx)
+{
+    const int b = (int)blockIdx.x * 4 + (int)threadIdx.x / kWave;
+    if (b >= nblk) return;
+    const int l = threadIdx.x & (kWave - 1);
+    const int k0 = block_k[b], k1 = block_k[b + 1];
+    int lo = INT32_MAX, hi = -1;
+    if ((blocks[b] >> 30) == kBlkStream)
+        for (int k = k0 + l; k < k1; k += kWave) {
+            const int c = ci[k];
+            lo = min(lo, c);
+            hi = max(hi, c);
+        }
+#pragma unroll
+    for (int d = 1; d < kWave; d *= 2) {
+        lo = min(lo, __shfl_xor(lo, d));
+        hi = max(hi, __shfl_xor(hi, d));
+    }
+    if (l == 0) {
+        const bool fits = hi >= lo && (int64_t)hi - lo + 1 <= cap;
+        bx[2 * b] = fits ? lo : 0;
+        bx[2 * b + 1] = fits ? hi - lo + 1 : 0;
+    }
+}
+
+hipError_t launch_block_windows(const uint32_t *blocks, const int32_t *block_k, const int32_t *ci, int32_t nblk,
+                                int cap, int32_t *bx, hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_block_windows, dim3((unsigned)((nblk + 3) / 4)), dim3(256), 0, s, blocks, block_k, ci, nblk,
+                       cap, bx);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------ registry --
@@ -180,10 +227,10 @@ hipError_t L_sell(const void *p, dim3 g, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int BS, int E, bool F>
+template <typename T, int BS, int E, int XW, bool F>
 hipError_t L_adaptive(const void *p, dim3 g, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_spmv_adaptive<T, BS, E, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
+    hipLaunchKernelGGL((k_spmv_adaptive<T, BS, E, XW, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
     return hipGetLastError();
 }
 
@@ -195,8 +242,10 @@ hipError_t L_adaptive(const void *p, dim3 g, hipStream_t s)
 #define VECTOR(BS, G, U) {2, BS, G, U, 0, FN4(L_vector, BS, G, U, false)}
 #define VECTOR_LDS(BS, G) {2, BS, G, 1, 1, FN4(L_vector, BS, G, 1, true)}
 #define SELL(C, U) {3, 256, C, U, 0, FN4(L_sell, 256, C, U)}
-// lds = row-stream entries per wavefront tile
-#define ADAPT(BS, E) {4, BS, 1, 1, E, FN4(L_adaptive, BS, E)}
+// lds = row-stream entries per wavefront tile; group = LDS room for x per
+// wavefront (1 = none)
+#define ADAPT(BS, E) {4, BS, 1, 1, E, FN4(L_adaptive, BS, E, 0)}
+#define ADAPT_X(BS, E) {4, BS, 256, 1, E, FN4(L_adaptive, BS, E, 256)}
 
 #define VECTOR_U(BS, G) VECTOR(BS, G, 1), VECTOR(BS, G, 2), VECTOR(BS, G, 4)
 #define VECTOR_G(BS) VECTOR_U(BS, 2), VECTOR_U(BS, 4), VECTOR_U(BS, 8), VECTOR_U(BS, 16), \
@@ -220,6 +269,7 @@ const SpmvEntry kSpmv[] = {
     ADAPT(128, 256), ADAPT(128, 512), ADAPT(128, 1024),
     ADAPT(256, 256), ADAPT(256, 512), ADAPT(256, 1024),
     ADAPT(512, 256), ADAPT(512, 512), ADAPT(512, 1024),
+    ADAPT_X(128, 256), ADAPT_X(256, 256), ADAPT_X(256, 512), ADAPT_X(512, 256),
 };
 
 }  // namespace

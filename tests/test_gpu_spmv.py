@@ -325,3 +325,30 @@ def test_krylov_step_lap2d_256_as_benched(spk, dev):
     finally:
         M.release()
         h.close()
+
+
+@pytest.mark.parametrize("dt", [1, 0])
+def test_row_blocks_with_x_window_equal_plain_row_blocks(spk, dev, dt):
+    """The row-block kernel with room for x in LDS (group 256) gives the bits
+    of the same kernel without it on a banded matrix (every row-stream block's
+    window fits) and on a 2-D Laplacian of 256 columns per grid line (the
+    windows do not fit, x is read from memory), plain and fused."""
+    for A in (I.banded(20000, 12, 0.6, stream=3), I.lap2d(256)):
+        A = A.astype(NP[dt])
+        M = spk.Matrix(A)
+        x = I.uniform(41, 0, A.ncols, NP[dt])
+        xd = torch.from_numpy(x).to(dev)
+        say(f"row blocks with x window: m={A.nrows} dtype={dt}")
+        try:
+            for bs, e in ((128, 256), (256, 256), (256, 512), (512, 256)):
+                outs = []
+                for g in (1, 256):
+                    v = spk.make_variant(format=spk.SPK_FMT_ADAPTIVE, block=bs, group=g, unroll=1, streams=1, lds=e)
+                    y = torch.full((A.nrows,), float("nan"), dtype=M.torch_dtype, device=dev)
+                    w = torch.full_like(y, float("nan"))
+                    spk.spk_run(spk.problem(spk.SPK_OP_SPMV_WAXPY, A=M, x=xd, y=y, w=w, alpha=0.5), v)
+                    _check(A, x, y, w, 0.5, dt)
+                    outs.append((y, w))
+                assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1]), (bs, e)
+        finally:
+            M.release()
