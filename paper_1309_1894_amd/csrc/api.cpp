@@ -67,6 +67,7 @@ const SpmvEntry *find_spmv_entry(const spk_variant &v)
     for (int i = 0; i < n; ++i) {
         const SpmvEntry &e = t[i];
         if (e.format != v.format || e.block != v.block || e.unroll != v.unroll) continue;
+        if (std::max(1, e.vec) != std::max(1, v.vec)) continue;
         if (e.format == SPK_FMT_VECTOR && (e.group != v.group || e.lds != v.lds)) continue;
         if (e.format == SPK_FMT_SELL && e.group != v.group) continue;
         if (e.format == SPK_FMT_ADAPTIVE && (e.lds != v.lds || e.group != v.group)) continue;
@@ -379,6 +380,16 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
     const int32_t *rp = p.mat ? p.mat->rp : p.csr->row_ptr;
     const int32_t *ci = p.mat ? p.mat->ci : p.csr->col_idx;
     const void *val = p.mat ? p.mat->val : p.csr->val;
+    if (e->vec > 1 && ((uintptr_t)val % ((size_t)e->vec * dtype_size(dtype)) != 0 ||
+                       (uintptr_t)ci % ((size_t)e->vec * 4) != 0)) {
+        // wider accesses need arrays aligned to their width: one entry at a time
+        spk_variant v1 = v;
+        v1.vec = 0;
+        v1.unroll = 1;
+        if (v.format == SPK_FMT_VECTOR) v1.unroll = 2;
+        const SpmvEntry *e1 = find_spmv_entry(v1);
+        if (e1) e = e1;
+    }
     SpmvFn fn = e->fn[dtype][p.fused ? 1 : 0];
 
     SellData *sd = nullptr;
@@ -1235,6 +1246,7 @@ static void spmv_space(std::vector<spk_variant> &out)
         v.group = t[i].group;
         v.unroll = t[i].unroll;
         v.lds = t[i].lds;
+        v.vec = t[i].vec > 1 ? t[i].vec : 0;
         v.streams = 1;
         out.push_back(v);
     }

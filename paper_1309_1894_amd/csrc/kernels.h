@@ -84,6 +84,7 @@ using SpmvFn = hipError_t (*)(const void *args, dim3 grid, hipStream_t);
 struct SpmvEntry {
     int format, block, group, unroll, lds;
     SpmvFn fn[2][2];     // [dtype][fused]
+    int vec = 1;         // entries per value/index access (SCALAR, VECTOR): 1, 2 or 4
 };
 
 const SpmvEntry *spmv_table(int *count);

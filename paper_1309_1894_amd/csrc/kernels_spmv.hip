@@ -33,31 +33,61 @@ __device__ __forceinline__ void store_row(const SpmvArgs<T> &a, int row, double 
 
 // --------------------------------------------------------------- SCALAR --
 
-template <typename T, int BS, int UNR, bool FUSED>
+// VEC > 1: the row's entries from the first index that is a multiple of
+// VEC on are read VEC at a time (one VEC*sizeof(T)-byte value access and one
+// VEC*4-byte index access), the few before it and after the last full
+// group one at a time; partial sum u takes the u-th entry of each group.
+template <typename T, int BS, int UNR, int VEC, bool FUSED>
 __global__ __launch_bounds__(BS) void k_spmv_scalar(SpmvArgs<T> a)
 {
     const int row = a.row0 + (int)blockIdx.x * BS + (int)threadIdx.x;
     if (row >= a.row0 + a.m) return;
     const int s = a.rp[row], e = a.rp[row + 1];
-    double acc[UNR];
+    if constexpr (VEC == 1) {
+        double acc[UNR];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) acc[u] = 0.0;
-    int k = s;
-    for (; k + UNR <= e; k += UNR) {
+        for (int u = 0; u < UNR; ++u) acc[u] = 0.0;
+        int k = s;
+        for (; k + UNR <= e; k += UNR) {
 #pragma unroll
-        for (int u = 0; u < UNR; ++u)
-            acc[u] = fma_t((double)a.val[k + u], (double)a.x[a.ci[k + u]], acc[u]);
+            for (int u = 0; u < UNR; ++u)
+                acc[u] = fma_t((double)a.val[k + u], (double)a.x[a.ci[k + u]], acc[u]);
+        }
+        for (; k < e; ++k) acc[0] = fma_t((double)a.val[k], (double)a.x[a.ci[k]], acc[0]);
+        double sum = acc[0];
+#pragma unroll
+        for (int u = 1; u < UNR; ++u) sum += acc[u];
+        store_row<T, FUSED>(a, row, sum);
+    } else {
+        double acc[VEC];
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) acc[u] = 0.0;
+        int k = s;
+        const int ka = min(e, (s + VEC - 1) / VEC * VEC);
+        for (; k < ka; ++k) acc[0] = fma_t((double)a.val[k], (double)a.x[a.ci[k]], acc[0]);
+        using VT = vec_t<T, VEC>;
+        using VI = vec_t<int32_t, VEC>;
+        for (; k + VEC <= e; k += VEC) {
+            const VT v = *reinterpret_cast<const VT *>(a.val + k);
+            const VI c = *reinterpret_cast<const VI *>(a.ci + k);
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) acc[u] = fma_t((double)v.v[u], (double)a.x[c.v[u]], acc[u]);
+        }
+        for (; k < e; ++k) acc[0] = fma_t((double)a.val[k], (double)a.x[a.ci[k]], acc[0]);
+        double sum = acc[0];
+#pragma unroll
+        for (int u = 1; u < VEC; ++u) sum += acc[u];
+        store_row<T, FUSED>(a, row, sum);
     }
-    for (; k < e; ++k) acc[0] = fma_t((double)a.val[k], (double)a.x[a.ci[k]], acc[0]);
-    double sum = acc[0];
-#pragma unroll
-    for (int u = 1; u < UNR; ++u) sum += acc[u];
-    store_row<T, FUSED>(a, row, sum);
 }
 
 // --------------------------------------------------------------- VECTOR --
 
-template <typename T, int BS, int G, int UNR, bool LDSRP, bool FUSED>
+// VEC > 1: lanes take groups of VEC consecutive entries (one
+// VEC*sizeof(T)-byte value access and one VEC*4-byte index access each),
+// from the row's first index that is a multiple of VEC; the entries before
+// it and after its last full group go one per lane.
+template <typename T, int BS, int G, int UNR, bool LDSRP, int VEC, bool FUSED>
 __global__ __launch_bounds__(BS) void k_spmv_vector(SpmvArgs<T> a)
 {
     constexpr int RPB = BS / G;  // rows per workgroup
@@ -80,11 +110,31 @@ __global__ __launch_bounds__(BS) void k_spmv_vector(SpmvArgs<T> a)
     double acc[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) acc[u] = 0.0;
-    for (int k = s + lane; k < e; k += G * UNR) {
+    if constexpr (VEC == 1) {
+        for (int k = s + lane; k < e; k += G * UNR) {
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const int kk = k + u * G;
-            if (kk < e) acc[u] = fma_t((double)a.val[kk], (double)a.x[a.ci[kk]], acc[u]);
+            for (int u = 0; u < UNR; ++u) {
+                const int kk = k + u * G;
+                if (kk < e) acc[u] = fma_t((double)a.val[kk], (double)a.x[a.ci[kk]], acc[u]);
+            }
+        }
+    } else {
+        static_assert(G >= 2 * (VEC - 1), "the head and tail entries need a lane each");
+        const int ka = min(e, (s + VEC - 1) / VEC * VEC);         // first group boundary
+        const int kb = ka + (e - ka) / VEC * VEC;                  // end of the full groups
+        // head and tail: at most 2*(VEC-1) entries, one per lane
+        {
+            const int h = ka - s;
+            const int k = lane < h ? s + lane : kb + (lane - h);
+            if (lane < h + (e - kb)) acc[0] = fma_t((double)a.val[k], (double)a.x[a.ci[k]], acc[0]);
+        }
+        using VT = vec_t<T, VEC>;
+        using VI = vec_t<int32_t, VEC>;
+        for (int k = ka + lane * VEC; k < kb; k += G * VEC) {
+            const VT v = *reinterpret_cast<const VT *>(a.val + k);
+            const VI c = *reinterpret_cast<const VI *>(a.ci + k);
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) acc[u % UNR] = fma_t((double)v.v[u], (double)a.x[c.v[u]], acc[u % UNR]);
         }
     }
     double sum = acc[0];
@@ -206,17 +256,17 @@ hipError_t launch_block_windows(const uint32_t *blocks, const int32_t *block_k, 
 
 namespace {
 
-template <typename T, int BS, int UNR, bool F>
+template <typename T, int BS, int UNR, int VEC, bool F>
 hipError_t L_scalar(const void *p, dim3 g, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_spmv_scalar<T, BS, UNR, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
+    hipLaunchKernelGGL((k_spmv_scalar<T, BS, UNR, VEC, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
     return hipGetLastError();
 }
 
-template <typename T, int BS, int G, int UNR, bool LDSRP, bool F>
+template <typename T, int BS, int G, int UNR, bool LDSRP, int VEC, bool F>
 hipError_t L_vector(const void *p, dim3 g, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_spmv_vector<T, BS, G, UNR, LDSRP, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
+    hipLaunchKernelGGL((k_spmv_vector<T, BS, G, UNR, LDSRP, VEC, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
     return hipGetLastError();
 }
 
@@ -237,10 +287,12 @@ hipError_t L_adaptive(const void *p, dim3 g, hipStream_t s)
 #define FN4(L, ...) {{L<float, __VA_ARGS__, false>, L<float, __VA_ARGS__, true>}, \
                      {L<double, __VA_ARGS__, false>, L<double, __VA_ARGS__, true>}}
 
-// format, block, group, unroll, lds
-#define SCALAR(BS, U) {1, BS, 1, U, 0, FN4(L_scalar, BS, U)}
-#define VECTOR(BS, G, U) {2, BS, G, U, 0, FN4(L_vector, BS, G, U, false)}
-#define VECTOR_LDS(BS, G) {2, BS, G, 1, 1, FN4(L_vector, BS, G, 1, true)}
+// format, block, group, unroll, lds (, entries per access)
+#define SCALAR(BS, U) {1, BS, 1, U, 0, FN4(L_scalar, BS, U, 1)}
+#define SCALAR_V(BS, V) {1, BS, 1, V, 0, FN4(L_scalar, BS, V, V), V}
+#define VECTOR(BS, G, U) {2, BS, G, U, 0, FN4(L_vector, BS, G, U, false, 1)}
+#define VECTOR_V(BS, G, U, V) {2, BS, G, U, 0, FN4(L_vector, BS, G, U, false, V), V}
+#define VECTOR_LDS(BS, G) {2, BS, G, 1, 1, FN4(L_vector, BS, G, 1, true, 1)}
 #define SELL(C, U) {3, 256, C, U, 0, FN4(L_sell, 256, C, U)}
 // lds = row-stream entries per wavefront tile; group = LDS room for x per
 // wavefront (1 = none)
@@ -270,6 +322,11 @@ const SpmvEntry kSpmv[] = {
     ADAPT(256, 256), ADAPT(256, 512), ADAPT(256, 1024),
     ADAPT(512, 256), ADAPT(512, 512), ADAPT(512, 1024),
     ADAPT_X(128, 256), ADAPT_X(256, 256), ADAPT_X(256, 512), ADAPT_X(512, 256),
+    // wider accesses: two entries (16 bytes of FP64 values, 8 of FP32) or
+    // four (16 bytes of FP32 values) per access
+    SCALAR_V(256, 2), SCALAR_V(256, 4),
+    VECTOR_V(256, 4, 2, 2), VECTOR_V(256, 8, 2, 2), VECTOR_V(256, 16, 2, 2), VECTOR_V(256, 32, 2, 2),
+    VECTOR_V(256, 64, 2, 2), VECTOR_V(256, 8, 4, 4), VECTOR_V(256, 16, 4, 4), VECTOR_V(256, 64, 4, 4),
 };
 
 }  // namespace
