@@ -16,7 +16,8 @@ batch (two launches over the batch as one block-diagonal matrix, and one
 launch pair per instance), the vector sweep (WAXPY/AXPY/dot at n = 2^27, FP64 and FP32,
 tuned vs plain), the large single SpMVs (3-D Laplacian 128^3 and a 1M-row
 Zipf matrix, tuned vs the better plain kernel, cold cache), the 2-D Laplacian
-step, a short open-loop serving run (p50/p99), the STREAM copy bandwidth, the
+step, open-loop serving of 20,000 requests over 256 matrices of 1e3..1e6
+rows at four offered loads (p50/p99 against a FIFO server), the STREAM copy bandwidth, the
 roofline of the dominant kernel and the oracle timed on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
@@ -52,7 +53,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-instance baseline")
     ap.add_argument("--verbose", action="store_true", help="print every tuning candidate")
     ap.add_argument("--instances", type=int, default=4096)
-    ap.add_argument("--serve-requests", type=int, default=6000)
+    ap.add_argument("--serve-requests", type=int, default=20000, help="measured requests per offered load")
+    ap.add_argument("--serve-warmup", type=int, default=1000, help="warm-up requests before them")
+    ap.add_argument("--serve-pool", type=int, default=256, help="matrices in the serving pool")
     return ap.parse_args()
 
 
@@ -167,7 +170,7 @@ def main():
                 "spmv_large": lambda: spmv_large(spk, torch, I, dev),
                 "krylov_step_lap2d": lambda: lap2d_step(spk, torch, I, dev),
                 "cg_lap3d_128": lambda: cg_lap3d(spk, torch, I, dev),
-                "serving": lambda: serving(spk, I, args.serve_requests),
+                "serving": lambda: serving(spk, I, args.serve_requests, args.serve_warmup, args.serve_pool),
                 "host_simd": lambda: host_simd()}
         want = list(legs) if args.extras == "all" else [e.strip() for e in args.extras.split(",") if e.strip()]
         for name in want:
@@ -601,76 +604,171 @@ def host_simd():
     return rep
 
 
-def serving(spk, I, nreq):
+def serving(spk, I, nreq, warm, npool):
     """Open-loop Poisson serving of SpMV+WAXPY requests over a pool of banded
-    and Zipf matrices (1e3..1e5 rows here, 70% FP64 / 30% FP32): continuous
-    batching vs a FIFO server that runs one request at a time with the plain
-    unbatched kernels, both on the same arrival traces at four offered loads
-    (70% of the FIFO server's and 50/70/90% of the batching server's
-    closed-loop saturation rate)."""
+    and Zipf matrices (rows log-uniform in [1e3, 1e6], 70% FP64 / 30% FP32):
+    continuous batching vs a FIFO server that runs one request at a time with
+    the plain unbatched kernels, both with a 200 GB HBM budget and on the same
+    arrival traces at four offered loads (70% of the FIFO server's and
+    50/70/90% of the batching server's closed-loop saturation rate).  Each
+    load replays warm + nreq requests and reports the last nreq: latency
+    p50/p99 (arrival to results in the caller's buffers), its split into the
+    wait for admission and the run after it, latency by row-count decade,
+    where the scheduler's time goes per launch, and the device and host-link
+    rates.  Requests for one pool matrix share its x and its y/w buffers
+    (every such request writes the same bytes); the buffers are pinned host
+    memory, as a serving front end that owns them would allocate them, and
+    one load is replayed from pageable buffers too."""
     import numpy as np
-    npool = 48
-    sizes = I.log_uniform_int(1e3, 1e5, 51, 0, npool)
+    from concurrent.futures import ThreadPoolExecutor
+    sizes = I.log_uniform_int(1e3, 1e6, 51, 0, npool)
     kinds = I.u64(51, 1, 0, npool) % np.uint64(2)
     fp64 = I.unit_from_u64(I.u64(51, 2, 0, npool)) < 0.7
-    pool = []
-    for i in range(npool):
+
+    def gen(i):
         m = int(sizes[i])
         dt = np.float64 if fp64[i] else np.float32
         if kinds[i] == 0:
             b = 1 + int(I.u64(51, 3, i, 1)[0] % np.uint64(32))
-            pool.append(I.banded(m, b, 0.6, seed_struct=53, seed_val=54, stream=i, dtype=dt))
-        else:
-            pool.append(I.zipf(m, kmax=min(4096, m), seed_struct=55 + i, seed_val=56, dtype=dt))
-    mats = (I.u64(52, 0, 0, nreq) % np.uint64(npool)).astype(np.int64)
-    xs = [I.uniform(52, 1 + i, pool[mats[i]].ncols, pool[mats[i]].val.dtype) for i in range(nreq)]
+            return I.banded(m, b, 0.6, seed_struct=53, seed_val=54, stream=i, dtype=dt)
+        return I.zipf(m, kmax=min(4096, m), seed_struct=55 + i, seed_val=56, dtype=dt)
 
-    def make(mode):
-        srv = spk.Server(streams=4, max_inflight=256, max_batch=64, mode=mode, alpha=0.5)
-        ids = [srv.add_matrix(A) for A in pool]
-        for i, A in enumerate(pool):   # one request per matrix makes it resident
-            srv.submit(ids[i], np.zeros(A.ncols, A.val.dtype), np.empty(A.nrows, A.val.dtype),
-                       np.empty(A.nrows, A.val.dtype))
+    t0 = time.perf_counter()
+    threads = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(threads) as ex:
+        pool = list(ex.map(gen, range(npool)))
+    gen_s = time.perf_counter() - t0
+    log(f"serving: pool of {npool} matrices generated in {gen_s:.1f} s on {threads} threads")
+    import torch
+
+    def pinned(n, dt):   # a serving front end owns its request buffers: pinned host memory
+        return torch.empty(n, dtype=torch.float64 if dt == np.float64 else torch.float32, pin_memory=True).numpy()
+
+    xs_pool, ys_pool, ws_pool = [], [], []
+    for i, A in enumerate(pool):
+        x = pinned(A.ncols, A.val.dtype)
+        x[:] = I.uniform(52, 1 + i, A.ncols, A.val.dtype)
+        xs_pool.append(x)
+        ys_pool.append(pinned(A.nrows, A.val.dtype))
+        ws_pool.append(pinned(A.nrows, A.val.dtype))
+    # the same requests from pageable buffers, for one comparison point
+    pageable = ([np.array(x) for x in xs_pool], [np.empty(A.nrows, A.val.dtype) for A in pool],
+                [np.empty(A.nrows, A.val.dtype) for A in pool])
+    total = warm + nreq
+    mats = (I.u64(52, 0, 0, total) % np.uint64(npool)).astype(np.int64)
+    rows = np.array([A.nrows for A in pool], np.int64)
+    link_bytes = np.array([A.val.itemsize * (A.ncols + 2 * A.nrows) for A in pool], np.float64)
+    decade = np.minimum(np.floor(np.log10(rows[mats])).astype(np.int64), 5) - 3   # 0: 1e3.., 1: 1e4.., 2: 1e5..1e6
+    budget = int(200e9)
+    res = {"requests_measured": nreq, "requests_warmup": warm, "pool": npool,
+           "pool_rows_min_max": [int(rows.min()), int(rows.max())], "pool_rows_total": int(rows.sum()),
+           "pool_nnz_total": int(sum(A.nnz for A in pool)),
+           "pool_host_bytes": int(sum(A.row_ptr.nbytes + A.col_idx.nbytes + A.val.nbytes for A in pool)),
+           "pool_generation_s": round(gen_s, 1), "hbm_budget_bytes": budget}
+
+    # the host link's own rates: 256 MB copies between pinned host memory and
+    # HBM, each direction alone and both at once (two streams)
+    hb = torch.empty(1 << 25, dtype=torch.float64, pin_memory=True)
+    db = torch.empty(1 << 25, dtype=torch.float64, device="cuda")
+    hb2 = torch.empty_like(hb, pin_memory=True)
+    db2 = torch.empty_like(db)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def link(h2d, d2h, reps=5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            if h2d:
+                with torch.cuda.stream(s1):
+                    db.copy_(hb, non_blocking=True)
+            if d2h:
+                with torch.cuda.stream(s2):
+                    hb2.copy_(db2, non_blocking=True)
+        torch.cuda.synchronize()
+        return round(reps * hb.nbytes * (int(h2d) + int(d2h)) / (time.perf_counter() - t0) / 1e9, 1)
+
+    link(True, True, 1)
+    res["host_link_probe_gbs"] = {"h2d": link(True, False), "d2h": link(False, True), "both": link(True, True)}
+    del hb, db, hb2, db2
+    log(f"serving: host link {res['host_link_probe_gbs']}")
+
+    servers, ids, count = {}, {}, {}
+    for mode in (1, 0):
+        srv = spk.Server(streams=4, max_inflight=256, max_batch=64, mode=mode, hbm_budget=budget, alpha=0.5)
+        ids[mode] = [srv.add_matrix(A) for A in pool]
+        for i in range(npool):   # one request per matrix makes it resident
+            srv.submit(ids[mode][i], xs_pool[i], ys_pool[i], ws_pool[i])
         srv.drain()
-        return srv, ids
+        servers[mode], count[mode] = srv, npool
 
-    res = {"requests": nreq, "pool": npool}
-
-    def saturation(mode):
-        srv, ids = make(mode)
-        k = min(nreq, 1500)
+    def saturation(mode, bufs=None):
+        srv = servers[mode]
+        bx, by, bw = bufs or (xs_pool, ys_pool, ws_pool)
+        k = min(total, 3000)
         t0 = time.perf_counter()
         for i in range(k):
-            srv.submit(ids[mats[i]], xs[i], np.empty(pool[mats[i]].nrows, pool[mats[i]].val.dtype))
+            m = mats[i]
+            srv.submit(ids[mode][m], bx[m], by[m], bw[m])
         srv.drain()
-        rate = k / (time.perf_counter() - t0)
-        srv.close()
-        return rate
+        count[mode] += k
+        return k / (time.perf_counter() - t0)
 
-    sat = {1: saturation(1), 0: saturation(0)}
-    res["closed_loop_saturation_per_s"] = {"fifo_plain": round(sat[1], 1), "continuous_batching": round(sat[0], 1)}
-    # offered loads: 70% of what the FIFO server sustains closed-loop, and
-    # 50/70/90% of what the batching server sustains
-    for load_name, rate in (("load_0.7x_fifo_saturation", 0.7 * sat[1]),
-                            ("load_0.5x_batching_saturation", 0.5 * sat[0]),
-                            ("load_0.7x_batching_saturation", 0.7 * sat[0]),
-                            ("load_0.9x_batching_saturation", 0.9 * sat[0])):
-        arr = I.poisson_arrivals(nreq, rate, seed=51)
-        point = {"offered_rate_per_s": round(rate, 1)}
-        for mode, label in ((1, "fifo_plain"), (0, "continuous_batching")):
-            srv, ids = make(mode)
-            ys = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
-            ws = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
-            srv.replay(arr, [ids[m] for m in mats], xs, ys, ws)
-            st = srv.stats()
-            lat = srv.latencies()[npool:]
-            point[label] = {"p50_us": round(float(np.percentile(lat, 50)), 1),
-                            "p99_us": round(float(np.percentile(lat, 99)), 1),
-                            "mean_us": round(float(lat.mean()), 1), "launches": st["batches"],
-                            "gbs": round(st["bytes_moved"] / max(st["wall_s"], 1e-9) / 1e9, 2)}
-            log(f"serving {load_name} {label}: {point[label]}")
+    def pct(v, q):
+        return round(float(np.percentile(v, q)), 1) if v.size else None
+
+    def replay(mode, arr, bufs=None):
+        srv = servers[mode]
+        bx, by, bw = bufs or (xs_pool, ys_pool, ws_pool)
+        s0 = srv.stats()
+        t0 = time.perf_counter()
+        srv.replay(arr, [ids[mode][m] for m in mats], [bx[m] for m in mats], [by[m] for m in mats],
+                   [bw[m] for m in mats])
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        lo = count[mode] + warm
+        hi = count[mode] + total
+        count[mode] += total
+        lat = srv.latencies()[lo:hi]
+        wait, run = srv.latency_split()
+        wait, run = wait[lo:hi], run[lo:hi]
+        dec = decade[warm:]
+        return {"p50_us": pct(lat, 50), "p99_us": pct(lat, 99), "mean_us": round(float(lat.mean()), 1),
+                "p99_over_p50": round(float(np.percentile(lat, 99) / np.percentile(lat, 50)), 1),
+                "wait_p50_p99_us": [pct(wait, 50), pct(wait, 99)], "run_p50_p99_us": [pct(run, 50), pct(run, 99)],
+                "p50_p99_us_by_rows": {f"1e{d + 3}": [pct(lat[dec == d], 50), pct(lat[dec == d], 99)]
+                                       for d in range(3)},
+                "launches": st["batches"] - s0["batches"],
+                "per_launch_us": {k: round((st[f] - s0[f]) / max(st["batches"] - s0["batches"], 1) * 1e6, 1)
+                                  for k, f in (("stage_in", "stage_in_s"), ("device", "device_s"),
+                                               ("stage_out", "stage_out_s"))},
+                "direct_requests": st["direct"] - s0["direct"],
+                "gbs": round((st["bytes_moved"] - s0["bytes_moved"]) / wall / 1e9, 2),
+                "host_link_gbs": round(float(link_bytes[mats].sum()) / wall / 1e9, 2),
+                "wall_s": round(wall, 2), "evictions": st["evictions"], "peak_hbm_bytes": st["peak_bytes"]}
+
+    try:
+        sat = {1: saturation(1), 0: saturation(0)}
+        res["closed_loop_saturation_per_s"] = {"fifo_plain": round(sat[1], 1),
+                                               "continuous_batching": round(sat[0], 1),
+                                               "continuous_batching_pageable_buffers":
+                                                   round(saturation(0, pageable), 1)}
+        log(f"serving saturation: {res['closed_loop_saturation_per_s']}")
+        for load_name, rate in (("load_0.7x_fifo_saturation", 0.7 * sat[1]),
+                                ("load_0.5x_batching_saturation", 0.5 * sat[0]),
+                                ("load_0.7x_batching_saturation", 0.7 * sat[0]),
+                                ("load_0.9x_batching_saturation", 0.9 * sat[0])):
+            arr = I.poisson_arrivals(total, rate, seed=51)
+            point = {"offered_rate_per_s": round(rate, 1)}
+            for mode, label in ((1, "fifo_plain"), (0, "continuous_batching")):
+                point[label] = replay(mode, arr)
+                log(f"serving {load_name} {label}: {point[label]}")
+            if load_name == "load_0.7x_batching_saturation":
+                point["continuous_batching_pageable_buffers"] = replay(0, arr, pageable)
+                log(f"serving {load_name} pageable: {point['continuous_batching_pageable_buffers']}")
+            res[load_name] = point
+    finally:
+        for srv in servers.values():
             srv.close()
-        res[load_name] = point
     return res
 
 

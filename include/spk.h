@@ -603,6 +603,10 @@ typedef struct {
     int64_t hbm_budget;       /* bytes for resident matrices + in-flight vectors
                                * (0 -> 200 GB) */
     double alpha;             /* step coefficient (w = alpha*y + x) */
+    int32_t max_launches;     /* launches in flight (0 -> one per stream): while
+                               * they run, arrivals queue and are admitted
+                               * together into the next launch */
+    int32_t reserved;         /* 0 */
 } spk_serve_opts;
 
 typedef struct {
@@ -613,6 +617,14 @@ typedef struct {
     double p50_us, p99_us, mean_us, max_us;   /* arrival -> result on host */
     double wall_s;            /* first arrival -> last completion */
     double bytes_moved;       /* algorithmic bytes of completed requests */
+    /* where the scheduler thread's time goes, summed over launches: */
+    double stage_in_s;        /* copying requests' x into pinned staging */
+    double stage_out_s;       /* copying results out of pinned staging */
+    double device_s;          /* from a launch's first enqueued copy until its
+                               * completion is seen (stream queueing, copies
+                               * over the host link, kernel) */
+    int64_t direct;           /* requests whose vectors skipped the staging
+                               * copies (pinned caller buffers) */
 } spk_serve_stats;
 
 /* Starts a serving loop (not in the paper; the configured serving
@@ -638,7 +650,10 @@ spk_status spk_serve_add_matrix(spk_server s, const spk_csr *A, int32_t *id);
  * (Figure 1's update).  x is host memory of
  * ncols elements (copied at admission); y and w are host memory of nrows
  * elements filled in before the request is reported complete.  The buffers
- * stay borrowed until then.  *req receives the request id. */
+ * stay borrowed until then.  *req receives the request id.  Vectors of
+ * 128 KiB or more whose three buffers (two without w) are each inside one
+ * pinned host allocation (hipHostMalloc) move between those buffers and the
+ * device by the copy engines, without the server's staging copies. */
 spk_status spk_serve_submit(spk_server s, int32_t mat_id, const void *x, void *y, void *w,
                             int64_t *req);
 
@@ -663,6 +678,13 @@ spk_status spk_serve_stats_get(spk_server s, spk_serve_stats *out);
 /* Per-request latency in microseconds, by request id (cap entries).
  * Measurement, not in the paper. */
 spk_status spk_serve_latencies(spk_server s, double *out_us, int64_t cap, int64_t *n);
+
+/* Each request's latency split at its admission, by request id (cap
+ * entries): wait_us = from its arrival until the scheduler admitted it to a
+ * launch (queueing, including waits for memory), run_us = from admission
+ * until its results were in the caller's buffers (copies, launch, kernel).
+ * -1 for requests not finished.  Measurement, not in the paper. */
+spk_status spk_serve_latency_split(spk_server s, double *wait_us, double *run_us, int64_t cap, int64_t *n);
 
 /* Drains and stops the server, joins its threads and frees its device
  * memory.  Serving plumbing, not in the paper. */

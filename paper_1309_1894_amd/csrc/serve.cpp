@@ -2,14 +2,20 @@
 // (y = A*x, w = alpha*y + x) over a pool of matrices.
 //
 // A scheduler thread owns the GPU side.  Each turn it
-//   1. retires finished launches (event query): copies results to the
-//      callers' buffers, stamps completion times, frees slots and bytes;
-//   2. admits queued requests in arrival order while a request slot is free
+//   1. retires finished launches (event query): copies results from the
+//      pinned staging block to the callers' buffers, stamps completion
+//      times, frees slots and bytes;
+//   2. while fewer launches than max_launches are in flight, admits queued
+//      requests (all that arrived meanwhile, up to max_batch) in arrival
+//      order while a request slot is free
 //      and the HBM budget covers the request's vectors plus, if its matrix
 //      is not resident, the matrix (idle matrices are evicted least recently
 //      used first to make room; a matrix in use is never evicted);
 //   3. launches the admitted group as one batched tile kernel on the next of
-//      its streams, so groups admitted while others run overlap on the GPU.
+//      its streams, so groups admitted while others run overlap on the GPU:
+//      the requests' x are copied into one pinned staging block, moved to
+//      the device by one copy, and the results come back the same way
+//      (large vectors in pinned caller buffers skip the staging block).
 // The tile kernel is the batched one, with each matrix cut into tiles by the
 // kernel of its shape class (the tiles live on the device with the matrix;
 // a launch names them through a small request table), so a request's
@@ -104,15 +110,17 @@ struct Request {
     const void *x = nullptr;
     void *y = nullptr;
     void *w = nullptr;
-    double t_arrival = 0.0, t_done = -1.0;
+    double t_arrival = 0.0, t_admit = -1.0, t_done = -1.0;
 };
 
 struct Flight {
     std::vector<std::pair<int64_t, Request>> reqs;
     std::vector<int64_t> off;   // vector offset of each request
+    std::vector<char> direct;   // its vectors move between the caller's pinned buffers and the device
     void *dev = nullptr, *pin = nullptr;
     size_t y_off = 0, w_off = 0;
     int64_t vec_bytes = 0;
+    double t_enqueued = 0.0;   // when its input copy was enqueued
     hipEvent_t done = nullptr;
     int dtype = SPK_F64;
 };
@@ -142,6 +150,8 @@ struct spk_server_s {
     int64_t inflight = 0;
     int64_t completed = 0, rejected = 0, batches = 0, uploads = 0, evictions = 0;
     double first_arrival = -1.0, last_done = 0.0, bytes_moved = 0.0;
+    double stage_in_s = 0.0, stage_out_s = 0.0, device_s = 0.0;
+    int64_t direct = 0;
     std::vector<int64_t> done_ids;
     std::mutex mu;
     std::condition_variable cv_in, cv_done;
@@ -272,7 +282,36 @@ void set_error(Server *S, spk_status st)
     }
 }
 
-// Launches a group of admitted requests (all of one dtype).
+// Vectors of at least this many bytes skip the staging copies when the
+// caller's buffers are pinned host memory: the copy engines move them
+// between those buffers and the device directly.  Below it one memcpy into
+// the staging block costs less than a copy command of its own.
+constexpr size_t kDirectMin = 128 << 10;
+
+// Whether [p, p + n) lies inside one pinned host allocation of the HIP
+// runtime (hipHostMalloc).  Pageable memory, or a pointer the runtime does
+// not know, is not.
+bool pinned_range(const void *p, size_t n)
+{
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (a.type != hipMemoryTypeHost) return false;
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)const_cast<void *>(p)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const uintptr_t b = (uintptr_t)base, q = (uintptr_t)p;
+    return q >= b && q + n <= b + size;
+}
+
+// Launches a group of admitted requests (all of one dtype).  Requests whose
+// vectors are staged come first in the launch's vectors, then those copied
+// directly from and to the callers' pinned buffers.
 spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &group)
 {
     const int dtype = S->mats[group[0].second.mat].dtype;
@@ -284,13 +323,27 @@ spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &gro
     // batched launches name each request's resident tiles through a table
     // [request records | request of each launch tile] staged before x
     std::vector<BatchReq> rq;
-    int64_t ntiles = 0, total = 0;
+    int64_t ntiles = 0, total = 0, staged = 0;
+    F.direct.assign(group.size(), 0);
+    for (size_t k = 0; k < group.size(); ++k) {
+        const Request &R = group[k].second;
+        const PoolMat &M = S->mats[R.mat];
+        const size_t nb = vs * (size_t)M.m;
+        F.direct[k] = nb >= kDirectMin && pinned_range(R.x, nb) && pinned_range(R.y, nb) &&
+                      (!R.w || pinned_range(R.w, nb));
+        if (!F.direct[k]) staged += M.m;
+    }
+    F.off.assign(group.size(), 0);
+    for (int pass = 0; pass < 2; ++pass)
+        for (size_t k = 0; k < group.size(); ++k)
+            if ((bool)F.direct[k] == (pass == 1)) {
+                F.off[k] = total;
+                total += S->mats[group[k].second.mat].m;
+            }
     for (size_t k = 0; k < group.size(); ++k) {
         const PoolMat &M = S->mats[group[k].second.mat];
-        F.off.push_back(total);
-        if (batched) rq.push_back({M.d_tiles, total, (int32_t)ntiles, 0});
+        if (batched) rq.push_back({M.d_tiles, F.off[k], (int32_t)ntiles, 0});
         ntiles += (int64_t)M.tiles.size();
-        total += M.m;
     }
     // one staging block: [requests | tile map | x | y | w], 256-byte aligned parts
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -316,8 +369,9 @@ spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &gro
     for (size_t k = 0; k < group.size(); ++k) {
         const Request &R = group[k].second;
         const PoolMat &M = S->mats[R.mat];
-        cp.push_back({pin + head_b + vs * F.off[k], R.x, vs * (size_t)M.n});
+        if (!F.direct[k]) cp.push_back({pin + head_b + vs * F.off[k], R.x, vs * (size_t)M.n});
     }
+    const double t_stage = now_seconds();
     S->copies.copy(cp);
     hipStream_t s = S->streams[S->next_stream];
     S->next_stream = (S->next_stream + 1) % (int)S->streams.size();
@@ -332,7 +386,18 @@ spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &gro
         SPK_HIP(hipStreamWaitEvent(s, M.uploaded, 0));
     }
     char *dev = (char *)F.dev;
-    SPK_HIP(hipMemcpyAsync(dev, pin, in_b, hipMemcpyHostToDevice, s));
+    if (head_b + vs * (size_t)staged > 0)
+        SPK_HIP(hipMemcpyAsync(dev, pin, head_b + vs * (size_t)staged, hipMemcpyHostToDevice, s));
+    for (size_t k = 0; k < group.size(); ++k)
+        if (F.direct[k])
+            SPK_HIP(hipMemcpyAsync(dev + head_b + vs * F.off[k], group[k].second.x,
+                                   vs * (size_t)S->mats[group[k].second.mat].n, hipMemcpyHostToDevice, s));
+    F.t_enqueued = now_seconds();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stage_in_s += F.t_enqueued - t_stage;
+        S->direct += (int64_t)std::count(F.direct.begin(), F.direct.end(), (char)1);
+    }
     const void *x = dev + head_b;
     void *y = dev + F.y_off;
     void *w = dev + F.w_off;
@@ -351,7 +416,21 @@ spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &gro
         SPK_TRY(launch_tiles(S->entry, dtype, nullptr, ntiles, S->opts.alpha, x, y, w, kBatchGrid, nullptr, 0, s,
                              (const BatchReq *)dev, (const uint16_t *)(dev + req_b)));
     }
-    SPK_HIP(hipMemcpyAsync(pin + F.y_off, y, 2 * vec_b, hipMemcpyDeviceToHost, s));
+    if (staged == total) {
+        SPK_HIP(hipMemcpyAsync(pin + F.y_off, y, 2 * vec_b, hipMemcpyDeviceToHost, s));
+    } else {
+        if (staged > 0) {
+            SPK_HIP(hipMemcpyAsync(pin + F.y_off, y, vs * (size_t)staged, hipMemcpyDeviceToHost, s));
+            SPK_HIP(hipMemcpyAsync(pin + F.w_off, w, vs * (size_t)staged, hipMemcpyDeviceToHost, s));
+        }
+        for (size_t k = 0; k < group.size(); ++k) {
+            if (!F.direct[k]) continue;
+            const Request &R = group[k].second;
+            const size_t nb = vs * (size_t)S->mats[R.mat].m;
+            SPK_HIP(hipMemcpyAsync(R.y, dev + F.y_off + vs * F.off[k], nb, hipMemcpyDeviceToHost, s));
+            if (R.w) SPK_HIP(hipMemcpyAsync(R.w, dev + F.w_off + vs * F.off[k], nb, hipMemcpyDeviceToHost, s));
+        }
+    }
     F.done = take_event(S);
     SPK_HIP(hipEventRecord(F.done, s));
     F.vec_bytes = 0;
@@ -373,22 +452,23 @@ bool retire(Server *S)
         const size_t vs = dtype_size(F.dtype);
         const double t = now_seconds();
         const char *pin = (const char *)F.pin;
-        std::vector<std::pair<int64_t, double>> ids;
         std::vector<CopyPool::Chunk> cp;
         for (size_t k = 0; k < F.reqs.size(); ++k) {
+            if (F.direct[k]) continue;   // already in the caller's buffers
             const Request &R = F.reqs[k].second;
             const PoolMat &M = S->mats[R.mat];
             cp.push_back({R.y, pin + F.y_off + vs * F.off[k], vs * (size_t)M.m});
             if (R.w) cp.push_back({R.w, pin + F.w_off + vs * F.off[k], vs * (size_t)M.m});
         }
         S->copies.copy(cp);
+        const double t_out = now_seconds();   // the results are in the callers' buffers
+        double bytes = 0.0;
         for (size_t k = 0; k < F.reqs.size(); ++k) {
             const Request &R = F.reqs[k].second;
             PoolMat &M = S->mats[R.mat];
             M.refs--;
             M.last_use = t;
-            S->bytes_moved += (double)spmv_bytes(M.m, M.n, M.nnz, M.dtype, true);
-            ids.emplace_back(F.reqs[k].first, now_seconds());
+            bytes += (double)spmv_bytes(M.m, M.n, M.nnz, M.dtype, true);
         }
         S->dpool.put(F.dev);
         S->hpool.put(F.pin);
@@ -398,10 +478,13 @@ bool retire(Server *S)
             S->used_vec -= F.vec_bytes;
             S->inflight -= (int64_t)F.reqs.size();
             S->completed += (int64_t)F.reqs.size();
-            S->last_done = t;
-            for (const auto &d : ids) {
-                S->reqs[d.first].t_done = d.second;
-                S->done_ids.push_back(d.first);
+            S->last_done = t_out;
+            S->bytes_moved += bytes;
+            S->device_s += t - F.t_enqueued;
+            S->stage_out_s += t_out - t;
+            for (const auto &r : F.reqs) {
+                S->reqs[r.first].t_done = t_out;
+                S->done_ids.push_back(r.first);
             }
         }
         S->cv_done.notify_all();
@@ -414,6 +497,7 @@ bool retire(Server *S)
 bool admit(Server *S)
 {
     if (S->opts.mode == 1 && !S->flights.empty()) return false;
+    if ((int64_t)S->flights.size() >= S->opts.max_launches) return false;
     std::vector<std::pair<int64_t, Request>> group;
     std::vector<int32_t> keep;
     int group_dtype = -1;
@@ -452,6 +536,8 @@ bool admit(Server *S)
         S->inflight += (int64_t)group.size();
         S->used_vec += group_vec;
         S->peak = std::max(S->peak, S->used_mat + S->used_vec);
+        const double t = now_seconds();
+        for (const auto &g : group) S->reqs[g.first].t_admit = t;
     }
     spk_status st = launch_group(S, group);
     if (st != SPK_OK) {
@@ -537,6 +623,8 @@ spk_status spk_serve_create(spk_handle h, const spk_serve_opts *opts, spk_server
     if (o.hbm_budget <= 0) o.hbm_budget = 200ll * 1000 * 1000 * 1000;
     if (o.mode != 0 && o.mode != 1) return fail(SPK_ERR_ARG, "mode must be 0 or 1");
     if (o.streams > 16) return fail(SPK_ERR_ARG, "at most 16 streams");
+    if (o.max_launches < 0 || o.max_launches > 256) return fail(SPK_ERR_ARG, "max_launches must be in [0, 256]");
+    if (o.max_launches == 0) o.max_launches = o.streams;
     DeviceGuard g(h);
     Server *S = new Server();
     S->h = h;
@@ -737,6 +825,10 @@ spk_status spk_serve_stats_get(spk_server S, spk_serve_stats *out)
     out->max_us = mx;
     out->wall_s = S->first_arrival >= 0 ? S->last_done - S->first_arrival : 0.0;
     out->bytes_moved = S->bytes_moved;
+    out->stage_in_s = S->stage_in_s;
+    out->stage_out_s = S->stage_out_s;
+    out->device_s = S->device_s;
+    out->direct = S->direct;
     return SPK_OK;
 }
 
@@ -748,6 +840,21 @@ spk_status spk_serve_latencies(spk_server S, double *out_us, int64_t cap, int64_
     for (int64_t i = 0; i < k; ++i) {
         const Request &R = S->reqs[i];
         out_us[i] = R.t_done < 0 ? -1.0 : (R.t_done - R.t_arrival) * 1e6;
+    }
+    *n = k;
+    return SPK_OK;
+}
+
+spk_status spk_serve_latency_split(spk_server S, double *wait_us, double *run_us, int64_t cap, int64_t *n)
+{
+    if (!S || !n || (cap > 0 && (!wait_us || !run_us))) return fail(SPK_ERR_NULL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    const int64_t k = std::min<int64_t>(cap, (int64_t)S->reqs.size());
+    for (int64_t i = 0; i < k; ++i) {
+        const Request &R = S->reqs[i];
+        const bool done = R.t_done >= 0 && R.t_admit >= 0;
+        wait_us[i] = done ? (R.t_admit - R.t_arrival) * 1e6 : -1.0;
+        run_us[i] = done ? (R.t_done - R.t_admit) * 1e6 : -1.0;
     }
     *n = k;
     return SPK_OK;

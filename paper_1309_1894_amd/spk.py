@@ -90,14 +90,15 @@ class spk_batch_opts(C.Structure):
 
 class spk_serve_opts(C.Structure):
     _fields_ = [("streams", _I32), ("max_inflight", _I32), ("max_batch", _I32), ("mode", _I32),
-                ("hbm_budget", _I64), ("alpha", _D)]
+                ("hbm_budget", _I64), ("alpha", _D), ("max_launches", _I32), ("reserved", _I32)]
 
 
 class spk_serve_stats(C.Structure):
     _fields_ = [("submitted", _I64), ("completed", _I64), ("rejected", _I64), ("batches", _I64),
                 ("uploads", _I64), ("evictions", _I64), ("resident_bytes", _I64), ("peak_bytes", _I64),
                 ("p50_us", _D), ("p99_us", _D), ("mean_us", _D), ("max_us", _D), ("wall_s", _D),
-                ("bytes_moved", _D)]
+                ("bytes_moved", _D), ("stage_in_s", _D), ("stage_out_s", _D), ("device_s", _D),
+                ("direct", _I64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -150,6 +151,7 @@ _SIGS = {
     "spk_serve_replay": (_S, [_P, _I64, _P, _P, _P, _P, _P]),
     "spk_serve_stats_get": (_S, [_P, C.POINTER(spk_serve_stats)]),
     "spk_serve_latencies": (_S, [_P, _P, _I64, C.POINTER(_I64)]),
+    "spk_serve_latency_split": (_S, [_P, _P, _P, _I64, C.POINTER(_I64)]),
     "spk_serve_destroy": (_S, [_P]),
     "spk_stream_probe": (_S, [_P, _I32, _I64, _P, _P, _P, _P]),
     "spk_flush_cache": (_S, [_P, _P]),
@@ -626,9 +628,11 @@ class Batch:
 class Server:
     """Continuous-batching serving loop (library scheduler thread)."""
 
-    def __init__(self, streams=4, max_inflight=256, max_batch=64, mode=0, hbm_budget=0, alpha=0.5, handle=None):
+    def __init__(self, streams=4, max_inflight=256, max_batch=64, mode=0, hbm_budget=0, alpha=0.5, handle=None,
+                 max_launches=0):
         self.handle = handle or default_handle()
-        o = spk_serve_opts(int(streams), int(max_inflight), int(max_batch), int(mode), int(hbm_budget), float(alpha))
+        o = spk_serve_opts(int(streams), int(max_inflight), int(max_batch), int(mode), int(hbm_budget), float(alpha),
+                           int(max_launches), 0)
         s = _P()
         _ok(_lib.spk_serve_create(self.handle.ptr, C.byref(o), C.byref(s)), "spk_serve_create")
         self.ptr = s.value
@@ -682,6 +686,16 @@ class Server:
         n = _I64()
         _ok(_lib.spk_serve_latencies(self.ptr, out.ctypes.data, cap, C.byref(n)), "spk_serve_latencies")
         return out[:n.value].copy()
+
+    def latency_split(self):
+        """(wait_us, run_us) per request: arrival to admission, admission to completion."""
+        cap = 1 << 22
+        wait = np.zeros(cap, np.float64)
+        run = np.zeros(cap, np.float64)
+        n = _I64()
+        _ok(_lib.spk_serve_latency_split(self.ptr, wait.ctypes.data, run.ctypes.data, cap, C.byref(n)),
+            "spk_serve_latency_split")
+        return wait[:n.value].copy(), run[:n.value].copy()
 
     def close(self):
         if self.ptr:

@@ -48,6 +48,10 @@ def test_serve_matches_oracle_and_alone(spk, dev, mode):
         assert st["completed"] == nreq and st["rejected"] == 0
         lat = srv.latencies()
         assert np.all(lat > 0)
+        # arrival -> admission -> completion: the two parts add up to the latency
+        wait, run = srv.latency_split()
+        assert wait.shape == lat.shape and np.all(wait >= 0) and np.all(run > 0)
+        assert np.allclose(wait + run, lat, rtol=0, atol=1e-3)
         if mode == 0:
             assert st["batches"] < nreq   # requests were batched together
     finally:
@@ -135,3 +139,89 @@ def test_serve_large_vectors_chunked_copies(spk, dev, mode):
             assert np.array_equal(y1, ys[i]) and np.array_equal(w1, ws[i]), i
     finally:
         solo.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_serve_pinned_buffers_skip_staging(spk, dev, mode):
+    """Requests whose vectors are 128 KiB or more and whose x, y, w sit in
+    pinned host memory are copied by the copy engines straight between those
+    buffers and the device, in launches that also hold staged requests
+    (small vectors, or pageable buffers): every result matches the oracle
+    and equals, bit for bit, the same request with pageable buffers."""
+    import torch
+    pool = [I.banded(40000, 6, 0.6, seed_struct=80, seed_val=81),                       # 320 KB vectors
+            I.zipf(50000, kmax=2048, seed_struct=82, seed_val=83, dtype=np.float32),      # 200 KB
+            I.banded(3000, 4, 0.6, seed_struct=84, seed_val=85),                         # 24 KB: staged
+            I.banded(20000, 3, 0.6, seed_struct=86, seed_val=87, dtype=np.float32)]      # 80 KB: staged
+    nreq = 48
+    mats = [i % len(pool) for i in range(nreq)]
+
+    def pinned(n, dt):
+        t = torch.empty(n, dtype=torch.float64 if dt == np.float64 else torch.float32, pin_memory=True)
+        return t.numpy()
+
+    xs, ys, ws = [], [], []
+    for i, m in enumerate(mats):
+        A = pool[m]
+        dt = A.val.dtype
+        # every fourth request keeps pageable buffers
+        if i % 4 == 3:
+            x, y, w = np.empty(A.ncols, dt), np.empty(A.nrows, dt), np.empty(A.nrows, dt)
+        else:
+            x, y, w = pinned(A.ncols, dt), pinned(A.nrows, dt), pinned(A.nrows, dt)
+        x[:] = I.uniform(88, i, A.ncols, dt)
+        xs.append(x), ys.append(y), ws.append(w)
+    expect_direct = sum(1 for i, m in enumerate(mats) if i % 4 != 3 and m in (0, 1))
+    say(f"serve pinned buffers mode={mode}: {nreq} requests, {expect_direct} direct")
+    srv = spk.Server(streams=4, max_inflight=32, max_batch=12, mode=mode, alpha=0.5)
+    try:
+        ids = [srv.add_matrix(A) for A in pool]
+        srv.replay(I.poisson_arrivals(nreq, 20000.0, seed=89), [ids[m] for m in mats], xs, ys, ws)
+        st = srv.stats()
+        assert st["completed"] == nreq and st["rejected"] == 0
+        assert st["direct"] == expect_direct
+    finally:
+        srv.close()
+    for i in range(nreq):
+        _check(pool[mats[i]], xs[i], ys[i], ws[i])
+    solo = spk.Server(streams=1, max_inflight=1, max_batch=1, mode=mode, alpha=0.5)
+    try:
+        ids = [solo.add_matrix(A) for A in pool]
+        for i in range(nreq):
+            y1, w1 = np.empty_like(ys[i]), np.empty_like(ws[i])
+            solo.submit(ids[mats[i]], np.array(xs[i]), y1, w1)
+            solo.drain()
+            assert np.array_equal(y1, ys[i]) and np.array_equal(w1, ws[i]), i
+        assert solo.stats()["direct"] == 0
+    finally:
+        solo.close()
+
+
+def test_serve_rejects_bad_launch_cap(spk, dev):
+    with pytest.raises(spk.SpkError) as e:
+        spk.Server(max_launches=-1)
+    assert e.value.name == "SPK_ERR_ARG"
+
+
+def test_serve_one_launch_in_flight_batches_arrivals(spk, dev):
+    """With one launch in flight, requests that arrive while it runs are
+    admitted together into the next one; results still match the oracle."""
+    pool = pool_mats()
+    nreq = 120
+    mats = (I.u64(90, 0, 0, nreq) % np.uint64(len(pool))).astype(int)
+    xs = [I.uniform(91, i, pool[m].ncols, pool[m].val.dtype) for i, m in enumerate(mats)]
+    ys = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
+    ws = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
+    say("serve max_launches=1")
+    srv = spk.Server(streams=2, max_inflight=64, max_batch=16, mode=0, alpha=0.5, max_launches=1)
+    try:
+        ids = [srv.add_matrix(A) for A in pool]
+        for i, m in enumerate(mats):
+            srv.submit(ids[m], xs[i], ys[i], ws[i])
+        srv.drain()
+        st = srv.stats()
+        assert st["completed"] == nreq and st["batches"] < nreq
+    finally:
+        srv.close()
+    for i in range(nreq):
+        _check(pool[mats[i]], xs[i], ys[i], ws[i])
