@@ -67,7 +67,9 @@ typedef enum {
     SPK_ERR_VALIDATION = 9,  /* no variant reproduced the reference output */
     SPK_ERR_NOT_FOUND = 10,  /* unknown id or variant */
     SPK_ERR_ARG = 11,        /* other invalid argument (options, variant fields) */
-    SPK_ERR_STATE = 12       /* call not allowed in the object's current state */
+    SPK_ERR_STATE = 12,      /* call not allowed in the object's current state */
+    SPK_ERR_INTERRUPTED = 13 /* a search stopped after opts->stop_after new
+                              * points (those points are in the journal) */
 } spk_status;
 
 typedef enum { SPK_F32 = 0, SPK_F64 = 1 } spk_dtype;
@@ -431,6 +433,16 @@ typedef struct {
     int32_t verbose;         /* 1: print one line per variant to stderr */
     uint32_t formats;        /* SpMV: bitmask (1 << spk_format) of the formats to
                               * search; 0 = every format that applies to A */
+    int32_t resume;          /* spk_tune / spk_batch_tune: 1 = journal every timed
+                              * point (search key, variant, median) as one line
+                              * of the plan DB as soon as it is measured, and
+                              * take points journaled before (same search key,
+                              * arch and build) instead of running them again;
+                              * 0 = neither.  spk_cg_tune: must be 0 */
+    int32_t stop_after;      /* >0: validate and time at most this many points
+                              * not already journaled, then stop with
+                              * SPK_ERR_INTERRUPTED, recording no winner (a
+                              * search cut short); 0 = no limit */
 } spk_tune_opts;
 
 typedef struct {
@@ -441,6 +453,7 @@ typedef struct {
     int32_t rejected;        /* variants whose output failed validation */
     int32_t pruned;          /* variants skipped by the byte model */
     char class_key[96];      /* plan DB key the winner is filed under */
+    int32_t resumed;         /* points taken from the journal, not timed again */
 } spk_tune_report;
 
 /* The tuning loop of Section 2: for every variant of the (pruned) space run

@@ -712,10 +712,65 @@ void db_load(spk_handle h)
                                "\"v\": [%d, %d, %d, %d, %d, %d, %d, %d], \"us\": %lf}",
                                key, arch, build, &v.format, &v.block, &v.group, &v.unroll, &v.vec, &v.grid,
                                &v.streams, &v.lds, &us);
-        if (got != 12) continue;
-        if (strcmp(arch, h->arch) != 0 || strcmp(build, SPK_BUILD_ID) != 0) continue;
-        h->plans[key] = v;
+        if (got == 12) {
+            if (strcmp(arch, h->arch) != 0 || strcmp(build, SPK_BUILD_ID) != 0) continue;
+            h->plans[key] = v;
+            continue;
+        }
+        char point[256] = {0};
+        const int gp = sscanf(line.c_str(),
+                              "{\"point\": \"%255[^\"]\", \"arch\": \"%63[^\"]\", \"build\": \"%63[^\"]\", "
+                              "\"v\": [%d, %d, %d, %d, %d, %d, %d, %d], \"us\": %lf}",
+                              point, arch, build, &v.format, &v.block, &v.group, &v.unroll, &v.vec, &v.grid,
+                              &v.streams, &v.lds, &us);
+        if (gp != 12 || strcmp(arch, h->arch) != 0 || strcmp(build, SPK_BUILD_ID) != 0) continue;
+        h->points[point].emplace_back(v, us);
     }
+}
+
+uint64_t fnv1a(const void *p, size_t n, uint64_t seed)
+{
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) seed = (seed ^ b[i]) * 1099511628211ull;
+    return seed;
+}
+
+static bool same_variant(const spk_variant &a, const spk_variant &b)
+{
+    return a.format == b.format && a.block == b.block && a.group == b.group && a.unroll == b.unroll &&
+           a.vec == b.vec && a.grid == b.grid && a.streams == b.streams && a.lds == b.lds;
+}
+
+bool point_get(spk_handle h, const std::string &key, const spk_variant &v, double *us)
+{
+    std::lock_guard<std::mutex> lk(h->mu);
+    auto it = h->points.find(key);
+    if (it == h->points.end()) return false;
+    for (const auto &pv : it->second)
+        if (same_variant(pv.first, v)) {
+            *us = pv.second;
+            return true;
+        }
+    return false;
+}
+
+void point_put(spk_handle h, const std::string &key, const spk_variant &v, double us)
+{
+    {
+        std::lock_guard<std::mutex> lk(h->mu);
+        h->points[key].emplace_back(v, us);
+    }
+    if (h->db_path.empty()) return;
+    FILE *f = fopen(h->db_path.c_str(), "a");
+    if (!f) return;
+    // one line per point, written whole, so a search cut short keeps every
+    // point measured before the cut
+    fprintf(f,
+            "{\"point\": \"%s\", \"arch\": \"%s\", \"build\": \"%s\", \"v\": [%d, %d, %d, %d, %d, %d, %d, %d], "
+            "\"us\": %.17g}\n",
+            key.c_str(), h->arch, SPK_BUILD_ID, v.format, v.block, v.group, v.unroll, v.vec, v.grid, v.streams, v.lds,
+            us);
+    fclose(f);
 }
 
 void db_append(spk_handle h, const std::string &key, const spk_variant &v, double us)
@@ -781,6 +836,7 @@ const char *spk_status_str(spk_status s)
     case SPK_ERR_NOT_FOUND: return "SPK_ERR_NOT_FOUND";
     case SPK_ERR_ARG: return "SPK_ERR_ARG";
     case SPK_ERR_STATE: return "SPK_ERR_STATE";
+    case SPK_ERR_INTERRUPTED: return "SPK_ERR_INTERRUPTED";
     }
     return "SPK_ERR_UNKNOWN";
 }

@@ -569,8 +569,52 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
         ~EvFree() { for (auto x : e) (void)hipEventDestroy(x); }
     } ef{ev};
 
-    int tried = 0, rejected = 0;
+    int tried = 0, rejected = 0, resumed = 0, fresh = 0;
     double total_best = 0.0, total_plain = 0.0;
+
+    // The journal (opts->resume): every timed point is filed under a key
+    // naming the batch (its sizes, dtype and whether w is written) and the
+    // context the point was timed in -- the per-class modes for a launch
+    // shape, the launch shape for a class's mode.
+    std::string bkey;
+    if (o.resume) {
+        uint64_t f = fnv1a(&b->count, sizeof b->count);
+        f = fnv1a(b->m.data(), sizeof(int64_t) * b->m.size(), f);
+        f = fnv1a(b->nnz.data(), sizeof(int64_t) * b->nnz.size(), f);
+        f = fnv1a(b->vec_off.data(), sizeof(int64_t) * b->vec_off.size(), f);
+        char k[96];
+        snprintf(k, sizeof k, "batch|%s|%016llx|w%d", dtype_name(b->dtype), (unsigned long long)f, w ? 1 : 0);
+        bkey = k;
+    }
+    auto modes_key = [&]() {
+        std::string k;
+        for (const auto &kv : b->mode) k += std::to_string(kv.first) + ":" + std::to_string(kv.second) + ",";
+        return k;
+    };
+    // the state a search cut short leaves behind: the plan it started from
+    const BatchEntry *entry0 = b->entry;
+    const int pers0 = b->opts.persistent;
+    const std::map<int, int> mode0 = b->mode;
+    auto interrupted = [&]() -> spk_status {
+        b->entry = entry0;
+        b->opts.persistent = pers0;
+        b->mode = mode0;
+        SPK_TRY(occupancy(b));
+        SPK_TRY(replan(b));
+        report->tried = tried;
+        report->rejected = rejected;
+        report->resumed = resumed;
+        return fail(SPK_ERR_INTERRUPTED, "search stopped after %d new points", fresh);
+    };
+    // a point from the journal, or -- unless the search is to stop -- a fresh one
+    auto journaled = [&](const std::string &key, const spk_variant &v, double *med) {
+        if (o.resume && point_get(h, key, v, med)) {
+            ++resumed;
+            return true;
+        }
+        return false;
+    };
+    auto must_stop = [&]() { return o.stop_after > 0 && fresh >= o.stop_after; };
 
     // times `ntiles` tiles already uploaded; rejects (returns -1) when the
     // output disagrees with the reference
@@ -618,14 +662,25 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
         const BatchEntry *best_e = b->entry;
         int best_p = b->opts.persistent;
         double best_t = 1e300;
+        const std::string key = bkey + "|launch|" + modes_key();
         for (int i = 0; i < n; ++i) {
             for (int pers : {kBatchGrid, kBatchPersistent}) {
-                b->entry = &tab[i];
-                b->opts.persistent = pers;
-                SPK_TRY(occupancy(b));
-                SPK_TRY(replan(b));
+                spk_variant pv{};
+                pv.block = tab[i].block;
+                pv.lds = tab[i].tile;
+                pv.unroll = tab[i].xw;
+                pv.grid = pers;
                 double med = 0;
-                SPK_TRY(validate_and_time((int64_t)b->tiles.size(), &med));
+                if (!journaled(key, pv, &med)) {
+                    if (must_stop()) return interrupted();
+                    ++fresh;
+                    b->entry = &tab[i];
+                    b->opts.persistent = pers;
+                    SPK_TRY(occupancy(b));
+                    SPK_TRY(replan(b));
+                    SPK_TRY(validate_and_time((int64_t)b->tiles.size(), &med));
+                    if (o.resume && med > 0) point_put(h, key, pv, med);
+                }
                 if (o.verbose)
                     fprintf(stderr, "spk_batch_tune: block %d tile %d x window %d persistent %d: %.2f us\n",
                             tab[i].block, tab[i].tile, tab[i].xw, pers, med);
@@ -652,7 +707,25 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
         double best = 1e300;
         int best_mode = b->mode[c];
         double plain_time = -1.0;
+        char ctx[64];
+        snprintf(ctx, sizeof ctx, "|c%d|%d,%d,%d,%d", c, b->entry->block, b->entry->tile, b->entry->xw,
+                 b->opts.persistent);
+        const std::string key = bkey + ctx;
         for (int mode : {0, 1, 2, 4, 8, 16, 32, 64}) {
+            spk_variant pv{};
+            pv.group = mode;
+            double med = 0;
+            if (journaled(key, pv, &med)) {
+                if (o.verbose) fprintf(stderr, "spk_batch_tune: class %d mode %d: %.2f us (journal)\n", c, mode, med);
+                if (mode == batch_default_mode(c, batch_wave_entries(*b->entry))) plain_time = med;
+                if (med < best) {
+                    best = med;
+                    best_mode = mode;
+                }
+                continue;
+            }
+            if (must_stop()) return interrupted();
+            ++fresh;
             // mode 1 is timed with the kernel of the same shape that has
             // room for x (without that room it would run as mode 0)
             const BatchEntry *keep = b->entry;
@@ -666,7 +739,6 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
             for (int64_t i : kv.second) cut_instance(b, i, mode, tl);
             spk_status ts = upload_tiles(b, tl);
             // only this class's rows are rewritten by the trial launches
-            double med = 0;
             if (ts == SPK_OK) ts = validate_and_time((int64_t)tl.size(), &med);
             if (b->entry != keep) {
                 b->entry = keep;
@@ -674,6 +746,7 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
             }
             SPK_TRY(ts);
             if (med < 0) continue;
+            if (o.resume) point_put(h, key, pv, med);
             if (o.verbose) fprintf(stderr, "spk_batch_tune: class %d mode %d: %.2f us\n", c, mode, med);
             if (mode == batch_default_mode(c, batch_wave_entries(*b->entry))) plain_time = med;
             if (med < best) {
@@ -688,9 +761,25 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
     }
     SPK_TRY(replan(b));
     SPK_TRY(pick_launch());
-    if (tried == 0) {
+    if (tried + resumed == 0) {
         report->rejected = rejected;
         return fail(SPK_ERR_VALIDATION, "no tile kernel reproduced the reference (%d rejected)", rejected);
+    }
+    if (resumed > 0) {
+        // a plan built from journaled points is checked against this batch's reference
+        const int tried0 = tried, rejected0 = rejected;
+        double med = 0;
+        SPK_TRY(validate_and_time((int64_t)b->tiles.size(), &med));
+        tried = tried0;
+        rejected = rejected0;
+        if (med < 0) {
+            b->entry = entry0;
+            b->opts.persistent = pers0;
+            b->mode = mode0;
+            SPK_TRY(occupancy(b));
+            SPK_TRY(replan(b));
+            return fail(SPK_ERR_VALIDATION, "the plan from journaled points does not reproduce this batch's reference");
+        }
     }
     if (o.record) {
         for (const auto &kv : class_best) {
@@ -719,6 +808,7 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
     SPK_HIP(hipStreamSynchronize(s));
     report->tried = tried;
     report->rejected = rejected;
+    report->resumed = resumed;
     report->best_us = total_best;
     report->plain_us = total_plain;
     report->best.block = b->entry->block;

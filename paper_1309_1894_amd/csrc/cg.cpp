@@ -251,6 +251,8 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
     if (A->nrows == 0) return fail(SPK_ERR_SHAPE, "empty matrix");
     if (!b) return fail(SPK_ERR_NULL, "b is NULL");
     if ((uintptr_t)b % sizeof(double)) return fail(SPK_ERR_ARG, "b must be 8-byte aligned");
+    if (opts && (opts->resume != 0 || opts->stop_after != 0))
+        return fail(SPK_ERR_ARG, "spk_cg_tune keeps no journal: resume and stop_after must be 0");
     const int64_t n = A->nrows;
     const int reps = opts && opts->reps > 0 ? opts->reps : 10;
     const int warmup = opts && opts->warmup > 0 ? opts->warmup : 2;

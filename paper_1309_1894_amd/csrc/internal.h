@@ -188,6 +188,8 @@ struct spk_ctx {
     std::string db_path;
     std::mutex mu;
     std::map<std::string, spk_variant> plans;
+    // measured search points (the tuners' journal): point key -> (variant, median us)
+    std::map<std::string, std::vector<std::pair<spk_variant, double>>> points;
     std::map<hipStream_t, spk::DotScratch> dot;
     double *noalloc_scratch = nullptr;   // this device's copy of spk_dot_noalloc's static scratch
     std::map<hipStream_t, spk::CgScratch> cg;
@@ -280,6 +282,13 @@ int64_t sell_padded_entries(const spk_mat *A, int C);
 // Plan DB persistence.
 void db_load(spk_handle h);
 void db_append(spk_handle h, const std::string &key, const spk_variant &v, double us);
+// The search journal: point_get finds a point measured before (this
+// process, or a journal line of the same arch and build in the plan DB);
+// point_put records one and appends its line to the DB.
+bool point_get(spk_handle h, const std::string &key, const spk_variant &v, double *us);
+void point_put(spk_handle h, const std::string &key, const spk_variant &v, double us);
+// 64-bit FNV-1a over a byte range, chained through `seed`.
+uint64_t fnv1a(const void *p, size_t n, uint64_t seed = 1469598103934665603ull);
 
 // Algorithmic bytes of one SpMV (+ step) on a matrix.
 int64_t spmv_bytes(int64_t m, int64_t n, int64_t nnz, int dtype, bool fused);

@@ -314,8 +314,22 @@ extern "C" spk_status spk_tune(spk_handle h, const spk_problem *problem, const s
     const bool flush = o.flush != 0;
     double best = 1e300, plain_best = 1e300;
     spk_variant bestv{};
-    int tried = 0, rejected = 0;
-    auto consider = [&](const spk_variant &v) -> spk_status {
+    int tried = 0, rejected = 0, resumed = 0, fresh = 0;
+    bool best_journaled = false;
+    // the journal's key for this search: the class plus the problem's sizes
+    std::string pkey;
+    if (o.resume) {
+        char fp[160];
+        if (spmv)
+            snprintf(fp, sizeof fp, "|op%d|m%lld|n%lld|nnz%lld", op, (long long)c.p.A->nrows, (long long)c.p.A->ncols,
+                     (long long)c.p.A->nnz);
+        else
+            snprintf(fp, sizeof fp, "|op%d|n%lld", op, (long long)c.p.n);
+        pkey = "tune|" + class_key(c.p, nullptr) + fp;
+    }
+    // validates, then times one point (*us = -1 when rejected)
+    auto measure = [&](const spk_variant &v, double *us_out) -> spk_status {
+        *us_out = -1.0;
         bool ok = false;
         SPK_TRY(validate(c, v, &ok));
         if (!ok) {
@@ -328,22 +342,45 @@ extern "C" spk_status spk_tune(spk_handle h, const spk_problem *problem, const s
         double us = 0;
         SPK_TRY(time_variant(c, v, warmup, reps, flush, &us));
         ++tried;
+        if (o.verbose)
+            fprintf(stderr, "spk_tune: %9.2f us fmt=%d bs=%d g=%d u=%d vec=%d grid=%d s=%d lds=%d\n", us, v.format,
+                    v.block, v.group, v.unroll, v.vec, v.grid, v.streams, v.lds);
+        *us_out = us;
+        return SPK_OK;
+    };
+    auto consider = [&](const spk_variant &v) -> spk_status {
+        double us = 0;
+        bool journaled = false;
+        if (o.resume && point_get(h, pkey, v, &us)) {
+            // measured (and validated) before: take its median
+            ++resumed;
+            journaled = true;
+        } else {
+            if (o.stop_after > 0 && fresh >= o.stop_after) {
+                report->tried = tried;
+                report->rejected = rejected;
+                report->resumed = resumed;
+                return fail(SPK_ERR_INTERRUPTED, "search stopped after %d new points", fresh);
+            }
+            ++fresh;
+            SPK_TRY(measure(v, &us));
+            if (us < 0) return SPK_OK;   // rejected
+            if (o.resume) point_put(h, pkey, v, us);
+        }
         const bool is_plain = spmv ? ((v.format == SPK_FMT_SCALAR && v.block == 256 && v.unroll == 1 && v.streams == 1) ||
                                       (v.format == SPK_FMT_VECTOR && v.block == 256 && v.group == 64 && v.unroll == 1 &&
                                        v.lds == 0 && v.streams == 1))
                                    : (v.block == 256 && v.vec == 1 && v.unroll == 1 && v.grid == 0);
         if (is_plain) plain_best = std::min(plain_best, us);
-        if (o.verbose)
-            fprintf(stderr, "spk_tune: %9.2f us fmt=%d bs=%d g=%d u=%d vec=%d grid=%d s=%d lds=%d\n", us, v.format,
-                    v.block, v.group, v.unroll, v.vec, v.grid, v.streams, v.lds);
         if (us < best) {
             best = us;
             bestv = v;
+            best_journaled = journaled;
         }
         return SPK_OK;
     };
     for (const spk_variant &v : space) SPK_TRY(consider(v));
-    if (spmv && tried > 0 && bestv.format != SPK_FMT_DIA && bestv.format != SPK_FMT_STENCIL &&
+    if (spmv && tried + resumed > 0 && bestv.format != SPK_FMT_DIA && bestv.format != SPK_FMT_STENCIL &&
         bestv.format != SPK_FMT_COLBLOCK && bestv.format != SPK_FMT_XWIN) {
         // refinement: the winner split over 2 and 4 streams
         for (int s2 : {2, 4}) {
@@ -355,7 +392,16 @@ extern "C" spk_status spk_tune(spk_handle h, const spk_problem *problem, const s
     report->tried = tried;
     report->rejected = rejected;
     report->pruned = pruned;
-    if (tried == 0) return fail(SPK_ERR_VALIDATION, "no variant reproduced the reference output (%d rejected)", rejected);
+    report->resumed = resumed;
+    if (tried + resumed == 0)
+        return fail(SPK_ERR_VALIDATION, "no variant reproduced the reference output (%d rejected)", rejected);
+    if (best_journaled) {
+        // a winner taken from the journal is checked against this problem's reference
+        bool ok = false;
+        SPK_TRY(validate(c, bestv, &ok));
+        if (!ok)
+            return fail(SPK_ERR_VALIDATION, "the journaled winner does not reproduce this problem's reference output");
+    }
     report->best = bestv;
     report->best_us = best;
     report->plain_us = plain_best < 1e300 ? plain_best : -1.0;

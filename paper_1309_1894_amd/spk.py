@@ -34,7 +34,7 @@ CSR_FORMATS = ((1 << SPK_FMT_SCALAR) | (1 << SPK_FMT_VECTOR) | (1 << SPK_FMT_SEL
                (1 << SPK_FMT_COLBLOCK) | (1 << SPK_FMT_XWIN))
 STATUS = {0: "SPK_OK", 1: "SPK_ERR_NULL", 2: "SPK_ERR_SHAPE", 3: "SPK_ERR_DTYPE", 4: "SPK_ERR_ALIAS",
           5: "SPK_ERR_CSR", 6: "SPK_ERR_OOM", 7: "SPK_ERR_BUDGET", 8: "SPK_ERR_HIP", 9: "SPK_ERR_VALIDATION",
-          10: "SPK_ERR_NOT_FOUND", 11: "SPK_ERR_ARG", 12: "SPK_ERR_STATE"}
+          10: "SPK_ERR_NOT_FOUND", 11: "SPK_ERR_ARG", 12: "SPK_ERR_STATE", 13: "SPK_ERR_INTERRUPTED"}
 
 _P = C.c_void_p
 _I32 = C.c_int32
@@ -65,7 +65,7 @@ class spk_problem(C.Structure):
 class spk_tune_opts(C.Structure):
     _fields_ = [("reps", _I32), ("warmup", _I32), ("flush", _I32), ("max_variants", _I32), ("tau", _D),
                 ("ref_host", _P), ("ref_scale", _P), ("record", _I32), ("verbose", _I32),
-                ("formats", C.c_uint32)]
+                ("formats", C.c_uint32), ("resume", _I32), ("stop_after", _I32)]
 
 
 class spk_structure(C.Structure):
@@ -75,7 +75,7 @@ class spk_structure(C.Structure):
 
 class spk_tune_report(C.Structure):
     _fields_ = [("best", spk_variant), ("best_us", _D), ("plain_us", _D), ("tried", _I32),
-                ("rejected", _I32), ("pruned", _I32), ("class_key", C.c_char * 96)]
+                ("rejected", _I32), ("pruned", _I32), ("class_key", C.c_char * 96), ("resumed", _I32)]
 
 
 class spk_batch_desc(C.Structure):
@@ -440,7 +440,7 @@ def spk_cg(A: Matrix, b, x, iters: int, hist=None, stream=None):
 
 
 def spk_cg_tune(A: Matrix, b, iters: int, *, reps=10, warmup=2, tau=0.0, max_variants=0, record=True,
-                verbose=False, formats=0) -> "spk_tune_report":
+                verbose=False, formats=0, resume=False, stop_after=0) -> "spk_tune_report":
     """Tunes the SpMV+dot kernel of spk_cg on A (tile shapes, and the
     matrix-free form for grid stencils), each validated against the default
     shape's solve; records the winner for A's class."""
@@ -448,6 +448,7 @@ def spk_cg_tune(A: Matrix, b, iters: int, *, reps=10, warmup=2, tau=0.0, max_var
     o.reps, o.warmup, o.tau, o.max_variants = reps, warmup, tau, max_variants
     o.formats = int(formats)
     o.record, o.verbose = int(record), int(verbose)
+    o.resume, o.stop_after = int(resume), int(stop_after)
     rep = spk_tune_report()
     _need(b, A.nrows, "b")
     _ok(_lib.spk_cg_tune(A.handle.ptr, A.ptr, _dev(b, "b"), int(iters), C.byref(o), C.byref(rep)), "spk_cg_tune")
@@ -518,10 +519,11 @@ def make_variant(**kw) -> spk_variant:
 
 
 def spk_tune(p: spk_problem, *, reps=10, warmup=2, flush=False, max_variants=0, tau=0.0, ref=None, ref_scale=None,
-             record=True, verbose=False, formats=0, handle=None) -> spk_tune_report:
+             record=True, verbose=False, formats=0, handle=None, resume=False, stop_after=0) -> spk_tune_report:
     o = spk_tune_opts()
     o.reps, o.warmup, o.flush, o.max_variants, o.tau = reps, warmup, int(flush), max_variants, tau
     o.formats = int(formats)
+    o.resume, o.stop_after = int(resume), int(stop_after)
     keep = []
     if ref is not None:
         r = np.ascontiguousarray(ref, dtype=np.float64)
@@ -591,12 +593,14 @@ class Batch:
         _ok(_lib.spk_batch_run(self.handle.ptr, self.ptr, float(alpha), _dev(x, "x"), _dev(y, "y"), _dev(w, "w"),
                                _stream(stream)), "spk_batch_run")
 
-    def tune(self, alpha, x, y, w=None, reps=10, warmup=2, flush=False, record=True, verbose=False, ref=None):
+    def tune(self, alpha, x, y, w=None, reps=10, warmup=2, flush=False, record=True, verbose=False, ref=None,
+             resume=False, stop_after=0):
         """spk_batch_tune; ``ref`` (optional, host FP64, one entry per vector
         element) replaces the plain kernels' y as the reference."""
         self._check(x, y, w)
         o = spk_tune_opts()
         o.reps, o.warmup, o.flush, o.record, o.verbose = reps, warmup, int(flush), int(record), int(verbose)
+        o.resume, o.stop_after = int(resume), int(stop_after)
         if ref is not None:
             r = np.ascontiguousarray(ref, dtype=np.float64)
             if r.size < int(self._host[0].sum()):

@@ -2,6 +2,7 @@
 instances matches the oracle per instance, and gives every instance the same
 bits as running it alone."""
 import dataclasses
+import json
 
 import numpy as np
 import pytest
@@ -315,3 +316,55 @@ def test_batch_x_window_mode(spk, dev, dt):
             b.free()
             h.close()
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_batch_tune_resume(spk, dev, tmp_path):
+    """spk_batch_tune journals every timed point: a search cut short after k
+    new points leaves them in the DB and the batch on the plan it started
+    from (still correct); a new handle resumes the search and times only
+    the rest; a third search takes every point from the journal."""
+    B = mixed_batch()
+    x = I.batch_vector(B, seed=19)
+    arrs = _dev_batch(B, dev)
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(x.size, dtype=torch.float64, device=dev)
+    w = torch.empty_like(y)
+    db = str(tmp_path / "plans.spkdb")
+
+    def points():
+        # every journal line is a distinct (search key, variant): nothing was timed twice
+        with open(db) as f:
+            pts = [json.loads(ln) for ln in f if ln.startswith('{"point": ')]
+        assert len({(p["point"], tuple(p["v"])) for p in pts}) == len(pts)
+        return len(pts)
+
+    k = 5
+    reps = []
+    for run in range(3):
+        h = spk.Handle(0, db)
+        b = spk.Batch(B, arrs, handle=h)
+        try:
+            say(f"batch tune resume run {run}")
+            if run == 0:
+                with pytest.raises(spk.SpkError, match="SPK_ERR_INTERRUPTED"):
+                    b.tune(0.5, xd, y, w, reps=2, warmup=1, record=False, resume=True, stop_after=k)
+                assert points() == k
+                assert spk.spk_plan_get("batch:f64:launch", handle=h) is None
+            else:
+                # no winners recorded: every search starts from the same plan
+                reps.append(b.tune(0.5, xd, y, w, reps=2, warmup=1, record=False, resume=True))
+            y.fill_(float("nan"))
+            w.fill_(float("nan"))
+            b.run(0.5, xd, y, w)
+            torch.cuda.synchronize()
+            _check_batch(B, x, y, w, 0.5)
+        finally:
+            b.free()
+            h.close()
+    first, second = reps
+    # the resumed search takes the k points from the journal (and reuses
+    # points of its own when a context repeats) and times only the rest
+    assert first.resumed >= k and first.tried > 0 and first.rejected == 0
+    assert points() == k + first.tried
+    assert second.tried == 0 and second.resumed == first.resumed + first.tried
+    assert second.best_us == first.best_us

@@ -1,5 +1,6 @@
 """The tuner: validate-then-time over the compiled variant space, rejection of
 variants whose output disagrees with the reference, plan DB round trip."""
+import json
 import os
 
 import numpy as np
@@ -103,6 +104,86 @@ def test_tune_spmv(spk, dev, which):
         rep2 = spk.spk_tune(spk.problem(spk.SPK_OP_SPMV_WAXPY, A=M, x=xd, y=y, w=w, alpha=0.5), reps=3, handle=h)
         assert rep2.rejected == 0
         assert O.max_ulp(w.cpu().numpy(), O.waxpy(0.5, y.cpu().numpy(), x))[0] == 0
+    finally:
+        M.release()
+        h.close()
+
+
+def _journal_points(db):
+    """The journal's point lines; each is a distinct (search key, variant)."""
+    with open(db) as f:
+        pts = [json.loads(ln) for ln in f if ln.startswith('{"point": ')]
+    assert len({(p["point"], tuple(p["v"])) for p in pts}) == len(pts)
+    return pts
+
+
+def test_tune_resume_times_only_the_rest(spk, dev, tmp_path):
+    """A search cut short after k new points leaves exactly those k points in
+    the journal; a new handle on the same DB resumes it, takes the k points
+    from the journal and times only the rest; a third search times nothing,
+    picks the same winner from the journal and still checks it against the
+    reference."""
+    db = str(tmp_path / "plans.spkdb")
+    A = I.banded(30000, 8, 0.6, seed_struct=120, seed_val=121)
+    x = I.uniform(122, 0, A.ncols)
+    ref, absum = O.spmv(A, x)
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+    k = 5
+    reps = []
+    for run in range(3):
+        h = spk.Handle(0, db)
+        M = spk.Matrix(A, handle=h)
+        try:
+            p = spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y)
+            say(f"tune resume run {run}")
+            if run == 0:
+                with pytest.raises(spk.SpkError) as e:
+                    spk.spk_tune(p, reps=3, warmup=1, max_variants=16, resume=True, stop_after=k, handle=h)
+                assert e.value.name == "SPK_ERR_INTERRUPTED"
+                assert len(_journal_points(db)) == k
+                assert spk.spk_plan_get(spk.spk_class_key(p, handle=h), handle=h) is None
+                continue
+            rep = spk.spk_tune(p, reps=3, warmup=1, max_variants=16, resume=True, handle=h)
+            reps.append(rep)
+            assert rep.rejected == 0
+            assert O.check_rows(y.cpu().numpy(), ref, absum, O.TAU_F64)[0] == 0
+        finally:
+            M.release()
+            h.close()
+    first, second = reps
+    assert first.resumed >= k and first.tried >= 16 - k
+    assert len(_journal_points(db)) == k + first.tried
+    assert second.tried == 0 and second.resumed == first.resumed + first.tried
+    assert second.best.as_dict() == first.best.as_dict() and second.best_us == first.best_us
+
+
+def test_tune_resume_needs_a_matching_problem(spk, dev, tmp_path):
+    """Journal points are filed under the problem's sizes: a problem of the
+    same class but other sizes does not take them."""
+    db = str(tmp_path / "plans.spkdb")
+    h = spk.Handle(0, db)
+    try:
+        for n in (1 << 20, (1 << 20) + 4096):
+            x = torch.from_numpy(I.uniform(123, 0, n)).to(dev)
+            yv = torch.from_numpy(I.uniform(124, 0, n)).to(dev)
+            w = torch.empty_like(x)
+            rep = spk.spk_tune(spk.problem(spk.SPK_OP_WAXPY, x=x, y=yv, w=w, alpha=0.5), reps=2, max_variants=8,
+                               resume=True, handle=h)
+            assert rep.resumed == 0 and rep.tried == 8
+    finally:
+        h.close()
+
+
+def test_cg_tune_rejects_journal_options(spk, dev):
+    A = I.lap2d(32)
+    h = spk.Handle(0)
+    M = spk.Matrix(A, handle=h)
+    try:
+        b = torch.ones(A.nrows, dtype=torch.float64, device=dev)
+        with pytest.raises(spk.SpkError) as e:
+            spk.spk_cg_tune(M, b, 4, resume=True)
+        assert e.value.name == "SPK_ERR_ARG"
     finally:
         M.release()
         h.close()
