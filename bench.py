@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="headline only")
     ap.add_argument("--extras", default="all",
                     help="comma list of extra legs (vector_sweep, spmv_large, krylov_step_lap2d, "
-                         "cg_lap3d_128, serving, host_simd) or 'all'")
+                         "cg_lap3d_128, serving, host_simd; zipf_forms for counter runs) or 'all'")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain per-instance baseline")
     ap.add_argument("--verbose", action="store_true", help="print every tuning candidate")
@@ -65,9 +65,9 @@ EXTRA_LEGS = ("vector_sweep", "spmv_large", "krylov_step_lap2d", "cg_lap3d_128",
 def main():
     args = parse()
     if args.extras != "all":
-        bad = [e for e in args.extras.split(",") if e.strip() and e.strip() not in EXTRA_LEGS]
+        bad = [e for e in args.extras.split(",") if e.strip() and e.strip() not in EXTRA_LEGS + ("zipf_forms",)]
         if bad:
-            sys.exit(f"unknown extra leg(s) {bad}; known: {', '.join(EXTRA_LEGS)}")
+            sys.exit(f"unknown extra leg(s) {bad}; known: {', '.join(EXTRA_LEGS + ('zipf_forms',))}")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -171,8 +171,11 @@ def main():
                 "krylov_step_lap2d": lambda: lap2d_step(spk, torch, I, dev),
                 "cg_lap3d_128": lambda: cg_lap3d(spk, torch, I, dev),
                 "serving": lambda: serving(spk, I, args.serve_requests, args.serve_warmup, args.serve_pool),
-                "host_simd": lambda: host_simd()}
-        want = list(legs) if args.extras == "all" else [e.strip() for e in args.extras.split(",") if e.strip()]
+                "host_simd": lambda: host_simd(),
+                "zipf_forms": lambda: zipf_forms(spk, torch, I, dev)}
+        # zipf_forms is a counter-run aid, named explicitly only
+        want = [k for k in legs if k in EXTRA_LEGS] if args.extras == "all" else \
+            [e.strip() for e in args.extras.split(",") if e.strip()]
         for name in want:
             out[name] = legs[name]()
 
@@ -393,6 +396,54 @@ def spmv_large(spk, torch, I, dev):
         res[name]["best_us_per_format"] = per_format(spk, torch, M, xd, y)
         log(f"spmv {name}: {res[name]}")
         M.release()
+    return res
+
+
+def zipf_forms(spk, torch, I, dev, reps=5):
+    """The 1M-row Zipf SpMV in three of its forms, for counter runs: one
+    fixed variant of each (the tuner's usual pick for this matrix, fixed so
+    that every profiling run launches the same kernels), `reps` cold-cache
+    runs each, form after form -- row-block tiles in one pass
+    (k_spmv_adaptive), column blocks (one k_spmv_adaptive pass per block,
+    then k_colblock_sum), x windows in LDS (k_xwin, then k_xwin_sum) --
+    timed with HIP events on the stream they run on.  These runs are the
+    last dispatches of those kernels in the process."""
+    import numpy as np
+    A = I.zipf(1000000)
+    M = spk.Matrix(A)
+    xd = torch.from_numpy(I.uniform(34, 0, A.ncols)).to(dev)
+    y = torch.empty(A.nrows, dtype=torch.float64, device=dev)
+    p = spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y)
+    forms = (("csr_lds_tiles", spk.make_variant(format=spk.SPK_FMT_ADAPTIVE, block=512, group=256, unroll=1,
+                                                streams=1, lds=256)),
+             ("csr_column_blocks", spk.make_variant(format=spk.SPK_FMT_COLBLOCK, block=128, group=2, unroll=1,
+                                                    streams=1, lds=256)),
+             ("csr_x_windows_in_lds", spk.make_variant(format=spk.SPK_FMT_XWIN, block=1024, group=128, unroll=1,
+                                                       grid=1, streams=1, lds=128)))
+    nbytes = A.nnz * 12 + 4 * (A.nrows + 1) + 8 * A.ncols + 8 * A.nrows
+    res = {"bytes": nbytes, "nnz": A.nnz, "rows": A.nrows, "reps": reps}
+    ref, absum = None, None
+    s = torch.cuda.current_stream()
+    for name, v in forms:
+        spk.spk_run(p, v)   # first use: plans the form's layout on the device
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            spk.spk_flush_cache()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            spk.spk_run(p, v)
+            e1.record(s)
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1) * 1e3)
+        yh = y.cpu().numpy()
+        if ref is None:   # every form gives the same y up to rounding
+            ref = yh
+        res[name] = {"variant": v.as_dict(), "us_median": round(float(np.median(t)), 2),
+                     "gbs": round(nbytes / (float(np.median(t)) * 1e-6) / 1e9, 1),
+                     "max_rel_diff_vs_first_form": float(np.max(np.abs(yh - ref) / (np.abs(ref) + 1e-300)))}
+        log(f"zipf form {name}: {res[name]}")
+    M.release()
     return res
 
 
