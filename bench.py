@@ -817,6 +817,31 @@ def serving(spk, I, nreq, warm, npool):
                 point["continuous_batching_pageable_buffers"] = replay(0, arr, pageable)
                 log(f"serving {load_name} pageable: {point['continuous_batching_pageable_buffers']}")
             res[load_name] = point
+        # budget pressure: a batching server whose budget holds about 60% of
+        # the pool's matrices, so admission evicts idle matrices (least
+        # recently used first) and uploads them again from its host copy
+        for k in (0, 1):
+            servers.pop(k).close()
+        budget_small = int(0.6 * res["pool_host_bytes"])
+        srv = spk.Server(streams=4, max_inflight=256, max_batch=64, mode=0, hbm_budget=budget_small, alpha=0.5)
+        servers["pressure"] = srv
+        ids["pressure"] = [srv.add_matrix(A) for A in pool]
+        count["pressure"] = 0
+        small = min(total, 5000 + warm)
+        rate = 0.2 * sat[0]
+        arr = I.poisson_arrivals(small, rate, seed=53)
+        s0 = srv.stats()
+        t0 = time.perf_counter()
+        srv.replay(arr, [ids["pressure"][m] for m in mats[:small]], [xs_pool[m] for m in mats[:small]],
+                   [ys_pool[m] for m in mats[:small]], [ws_pool[m] for m in mats[:small]])
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        lat = srv.latencies()[warm:small]
+        res["budget_pressure"] = {"hbm_budget_bytes": budget_small, "offered_rate_per_s": round(rate, 1),
+                                  "requests_measured": small - warm, "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
+                                  "uploads": st["uploads"] - s0["uploads"], "evictions": st["evictions"] - s0["evictions"],
+                                  "peak_hbm_bytes": st["peak_bytes"], "wall_s": round(wall, 2)}
+        log(f"serving budget pressure: {res['budget_pressure']}")
     finally:
         for srv in servers.values():
             srv.close()

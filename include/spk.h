@@ -614,7 +614,11 @@ typedef struct {
     int32_t mode;             /* 0 = continuous batching; 1 = FIFO, one request per
                                * launch with the plain kernels (baseline) */
     int64_t hbm_budget;       /* bytes for resident matrices + in-flight vectors
-                               * (0 -> 200 GB) */
+                               * (0 -> 200 GB), counted at their exact sizes;
+                               * the device blocks behind them are pooled by
+                               * power-of-two size, and the pool keeps idle
+                               * blocks up to a quarter of the budget for
+                               * later uploads */
     double alpha;             /* step coefficient (w = alpha*y + x) */
     int32_t max_launches;     /* launches in flight (0 -> one per stream): while
                                * they run, arrivals queue and are admitted

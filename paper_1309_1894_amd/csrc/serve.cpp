@@ -49,12 +49,13 @@ size_t round_pow2(size_t n)
     return p;
 }
 
-// Recycles device or pinned host blocks by power-of-two size.
+// Recycles device or pinned host blocks by power-of-two size (a free
+// goes back to the pool: hipFree would wait for the whole device).
 struct Pool {
     bool device;
     std::multimap<size_t, void *> free_;
     std::map<void *, size_t> size_of;
-    int64_t held = 0;
+    int64_t held = 0, idle = 0;   // bytes allocated / of them in free_
     hipError_t get(size_t n, void **out)
     {
         const size_t sz = round_pow2(n);
@@ -62,6 +63,7 @@ struct Pool {
         if (it != free_.end()) {
             *out = it->second;
             free_.erase(it);
+            idle -= (int64_t)sz;
             return hipSuccess;
         }
         hipError_t e = device ? hipMalloc(out, sz) : hipHostMalloc(out, sz, hipHostMallocDefault);
@@ -73,7 +75,25 @@ struct Pool {
     }
     void put(void *p)
     {
-        if (p) free_.emplace(size_of[p], p);
+        if (!p) return;
+        const size_t sz = size_of[p];
+        free_.emplace(sz, p);
+        idle += (int64_t)sz;
+    }
+    // releases idle blocks, largest first, until at most max_idle bytes stay
+    void trim(int64_t max_idle)
+    {
+        while (idle > max_idle && !free_.empty()) {
+            auto it = std::prev(free_.end());
+            void *p = it->second;
+            const size_t sz = it->first;
+            free_.erase(it);
+            size_of.erase(p);
+            idle -= (int64_t)sz;
+            held -= (int64_t)sz;
+            if (device) (void)hipFree(p);
+            else (void)hipHostFree(p);
+        }
     }
     void release_all()
     {
@@ -84,6 +104,7 @@ struct Pool {
         free_.clear();
         size_of.clear();
         held = 0;
+        idle = 0;
     }
 };
 
@@ -145,6 +166,7 @@ struct spk_server_s {
     std::vector<spk::Flight> flights;
     std::vector<hipEvent_t> spare_events;
     spk::Pool dpool{true}, hpool{false};
+    spk::Pool mpool{true};                  // device arrays of resident matrices
     spk::CopyPool copies;                   // used by the scheduler thread only
     int64_t used_mat = 0, used_vec = 0, peak = 0;
     int64_t inflight = 0;
@@ -181,15 +203,20 @@ hipEvent_t take_event(Server *S)
 
 int64_t vec_bytes_of(const PoolMat &M) { return (M.n + 2 * M.m) * (int64_t)dtype_size(M.dtype); }
 
-void free_device_copy(PoolMat &M)
+// The matrix's device arrays go back to the server's matrix pool, where a
+// later upload (on the same upload stream, so in order after this
+// matrix's own copies) reuses them; idle blocks beyond a quarter of the
+// budget are released.
+void free_device_copy(Server *S, PoolMat &M)
 {
-    if (M.d_rp) (void)hipFree(M.d_rp);
-    if (M.d_ci) (void)hipFree(M.d_ci);
-    if (M.d_val) (void)hipFree(M.d_val);
-    if (M.d_tiles) (void)hipFree(M.d_tiles);
+    S->mpool.put(M.d_rp);
+    S->mpool.put(M.d_ci);
+    S->mpool.put(M.d_val);
+    S->mpool.put(M.d_tiles);
     M.d_rp = M.d_ci = nullptr;
     M.d_val = nullptr;
     M.d_tiles = nullptr;
+    S->mpool.trim(S->opts.hbm_budget / 4);
 }
 
 spk_status upload(Server *S, PoolMat &M);
@@ -200,7 +227,7 @@ spk_status make_resident(Server *S, PoolMat &M)
     if (st != SPK_OK) {
         // nothing of a failed upload stays allocated (copies already queued finish first)
         (void)hipStreamSynchronize(S->upload);
-        free_device_copy(M);
+        free_device_copy(S, M);
         return st;
     }
     M.resident = true;
@@ -213,9 +240,9 @@ spk_status make_resident(Server *S, PoolMat &M)
 spk_status upload(Server *S, PoolMat &M)
 {
     const size_t vs = dtype_size(M.dtype);
-    SPK_HIP(hipMalloc(&M.d_rp, sizeof(int32_t) * (M.m + 1)));
-    SPK_HIP(hipMalloc(&M.d_ci, sizeof(int32_t) * std::max<int64_t>(1, M.nnz)));
-    SPK_HIP(hipMalloc(&M.d_val, vs * std::max<int64_t>(1, M.nnz)));
+    SPK_HIP(S->mpool.get(sizeof(int32_t) * (M.m + 1), (void **)&M.d_rp));
+    SPK_HIP(S->mpool.get(sizeof(int32_t) * std::max<int64_t>(1, M.nnz), (void **)&M.d_ci));
+    SPK_HIP(S->mpool.get(vs * std::max<int64_t>(1, M.nnz), &M.d_val));
     SPK_HIP(hipMemcpyAsync(M.d_rp, M.h_rp, sizeof(int32_t) * (M.m + 1), hipMemcpyHostToDevice, S->upload));
     if (M.nnz) {
         SPK_HIP(hipMemcpyAsync(M.d_ci, M.h_ci, sizeof(int32_t) * M.nnz, hipMemcpyHostToDevice, S->upload));
@@ -228,7 +255,7 @@ spk_status upload(Server *S, PoolMat &M)
             t.val = M.d_val;
             t.vec_off = 0;
         }
-        SPK_HIP(hipMalloc(&M.d_tiles, sizeof(BatchTile) * M.tiles.size()));
+        SPK_HIP(S->mpool.get(sizeof(BatchTile) * M.tiles.size(), (void **)&M.d_tiles));
         // pageable source: the call returns once the tiles are staged
         SPK_HIP(hipMemcpyAsync(M.d_tiles, M.tiles.data(), sizeof(BatchTile) * M.tiles.size(), hipMemcpyHostToDevice,
                                S->upload));
@@ -244,8 +271,7 @@ spk_status upload(Server *S, PoolMat &M)
 void evict(Server *S, PoolMat &M)
 {
     // idle: no launch references it (refs == 0 and its last launch retired)
-    (void)hipEventSynchronize(M.uploaded);
-    free_device_copy(M);
+    free_device_copy(S, M);
     M.resident = false;
     S->used_mat -= M.dev_bytes;
     ++S->evictions;
@@ -880,7 +906,7 @@ spk_status spk_serve_destroy(spk_server S)
         (void)hipStreamDestroy(S->upload);
     }
     for (PoolMat &M : S->mats) {
-        free_device_copy(M);
+        free_device_copy(S, M);
         if (M.uploaded) (void)hipEventDestroy(M.uploaded);
         if (M.h_pinned) {
             (void)hipHostFree(M.h_rp);
@@ -896,6 +922,7 @@ spk_status spk_serve_destroy(spk_server S)
     for (hipEvent_t e : S->spare_events) hipEventDestroy(e);
     S->dpool.release_all();
     S->hpool.release_all();
+    S->mpool.release_all();
     delete S;
     return SPK_OK;
 }
