@@ -249,6 +249,7 @@ __global__ __launch_bounds__(BS) void k_xwin(XwinArgs a)
 template <typename T, bool FUSED>
 __global__ __launch_bounds__(256) void k_xwin_sum(XsumArgs a)
 {
+    constexpr int RPT = (int)(kXwinMaxRb / 256);   // rows per thread at most
     __shared__ double stage[kXwinStage];     // the block's partials in row order
     __shared__ uint16_t wof[kXwinStage];     // window of each slot
     __shared__ int pre[kXwinMaxWin + 1];
@@ -257,13 +258,16 @@ __global__ __launch_bounds__(256) void k_xwin_sum(XsumArgs a)
     const int t = (int)threadIdx.x;
     const int S = a.nwin;
     const int64_t r0 = (int64_t)b * a.rb;
-    const int64_t i = r0 + t;
-    const bool mine = t < a.rb && i < a.m;
-    // the row's own pair range (a clamped row for threads without one: no
-    // load here sits in a branch, so none is waited for early), in flight
-    // during the staging
-    const int64_t ic = min(i, a.m - 1);
-    const int s = a.pos_ptr[ic], e = a.pos_ptr[ic + 1];
+    // the pair ranges of the thread's rows r0 + t + 256q (clamped rows for
+    // threads without one: no load here sits in a branch, so none is waited
+    // for early), in flight during the staging
+    int s[RPT], e[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t ic = min(r0 + t + 256 * q, a.m - 1);
+        s[q] = a.pos_ptr[ic];
+        e[q] = a.pos_ptr[ic + 1];
+    }
     const int base = a.pos_ptr[r0];
     const int *bpre = a.pre + (int64_t)b * (S + 1);
     const int *bfirst = a.first + (int64_t)b * S;
@@ -300,25 +304,29 @@ __global__ __launch_bounds__(256) void k_xwin_sum(XsumArgs a)
             if (j0 + u * 256 + t < total) stage[q[u]] = v[u];
     }
     __syncthreads();
-    if (!mine) return;
-    // the row's partials are contiguous: four interleaved sums (a fixed
+    // each row's partials are contiguous: four interleaved sums (a fixed
     // order, so the result is reproducible)
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int k = s - base;
-    const int ke = e - base;
-    for (; k + 4 <= ke; k += 4) {
-        a0 += stage[k];
-        a1 += stage[k + 1];
-        a2 += stage[k + 2];
-        a3 += stage[k + 3];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t i = r0 + t + 256 * q;
+        if (t + 256 * q >= a.rb || i >= a.m) break;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int k = s[q] - base;
+        const int ke = e[q] - base;
+        for (; k + 4 <= ke; k += 4) {
+            a0 += stage[k];
+            a1 += stage[k + 1];
+            a2 += stage[k + 2];
+            a3 += stage[k + 3];
+        }
+        if (k < ke) a0 += stage[k];
+        if (k + 1 < ke) a1 += stage[k + 1];
+        if (k + 2 < ke) a2 += stage[k + 2];
+        const double acc = (a0 + a1) + (a2 + a3);
+        const T yt = (T)acc;
+        ((T *)a.y)[i] = yt;
+        if constexpr (FUSED) ((T *)a.w)[i] = fma_t((T)a.alpha, yt, ((const T *)a.x)[i]);
     }
-    if (k < ke) a0 += stage[k];
-    if (k + 1 < ke) a1 += stage[k + 1];
-    if (k + 2 < ke) a2 += stage[k + 2];
-    const double acc = (a0 + a1) + (a2 + a3);
-    const T yt = (T)acc;
-    ((T *)a.y)[i] = yt;
-    if constexpr (FUSED) ((T *)a.w)[i] = fma_t((T)a.alpha, yt, ((const T *)a.x)[i]);
 }
 
 namespace {

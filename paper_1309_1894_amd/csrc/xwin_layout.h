@@ -22,8 +22,10 @@ namespace spk {
 // copies those runs -- window order, each run in pair order -- into an LDS
 // staging area of at most kXwinStage partials, then each row adds its own
 // staged partials in window order.  rb is the largest power of two up to
-// 256 whose blocks all fit the staging area.
-constexpr int64_t kXwinStage = 2048;      // FP64 partials staged per block
+// kXwinMaxRb whose blocks all fit the staging area: the larger the block,
+// the longer its runs, and the fewer 128-byte lines two blocks share.
+constexpr int64_t kXwinStage = 7168;      // FP64 partials staged per block (56 KiB of LDS)
+constexpr int64_t kXwinMaxRb = 1024;      // rows per block at most (four per thread)
 constexpr int64_t kXwinMaxWin = 1023;     // windows one matrix may have
 constexpr int64_t kXwinMaxTable = (int64_t)1 << 26;   // block table entries
 
@@ -108,7 +110,7 @@ inline XwinLayoutStatus xwin_layout(int64_t m, int64_t n, int64_t nnz, const int
     }
     d.ent[d.npairs] = (int32_t)nnz;
     // row blocks of the second pass
-    d.rb = 256;
+    d.rb = kXwinMaxRb;
     for (;;) {
         int64_t worst = 0;
         for (int64_t r0 = 0; r0 < m; r0 += d.rb)

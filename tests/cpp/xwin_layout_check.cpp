@@ -128,7 +128,7 @@ static void check_one(const Csr &A, int64_t wc, int E, int64_t target, const cha
     }
     for (int64_t p = 0; p < d.npairs; ++p) CHECK(done[p], "%s pair %lld in no tile", name, (long long)p);
     // second pass as the kernel runs it: stage each block's runs, then each row sums its slots
-    CHECK(d.rb >= 1 && d.rb <= 256 && (d.rb & (d.rb - 1)) == 0 && d.nblk == (m + d.rb - 1) / d.rb, "%s rb", name);
+    CHECK(d.rb >= 1 && d.rb <= kXwinMaxRb && (d.rb & (d.rb - 1)) == 0 && d.nblk == (m + d.rb - 1) / d.rb, "%s rb", name);
     CHECK((int64_t)d.first.size() == d.nblk * d.nwin && (int64_t)d.pre.size() == d.nblk * (d.nwin + 1) &&
           (int64_t)d.lpos.size() == d.npairs, "%s table sizes", name);
     std::vector<double> y((size_t)m, 0.0);
