@@ -1,5 +1,8 @@
 // device_rows.h -- per-row work of wavefront tiles, shared by the
-// single-matrix row-block kernel and the batched tile kernel.
+// single-matrix row-block kernel and the batched tile kernel.  The row
+// stream (short rows' products staged in on-chip memory, then summed per
+// row) is the CSR-Stream idea of Greathouse and Daga's CSR-Adaptive
+// (SC 2014), applied per wavefront.
 #pragma once
 
 #include "device_common.h"

@@ -14,7 +14,11 @@
 //            fit a wavefront's LDS slice are streamed into LDS with
 //            coalesced loads and summed per row from LDS; runs of medium
 //            rows, and single long rows, get a wavefront (64 lanes per row,
-//            eight loads and gathers in flight per lane).
+//            eight loads and gathers in flight per lane).  Streaming short
+//            rows through on-chip memory and giving long rows a vector of
+//            their own is the CSR-Stream / CSR-Adaptive scheme published by
+//            Greathouse and Daga (SC 2014); here each wavefront streams its
+//            own tile, with no workgroup barrier.
 // Products are formed and accumulated in FP64 (FP32 operands are widened
 // first, so their products are exact) and each output is rounded once.
 #include "device_common.h"
