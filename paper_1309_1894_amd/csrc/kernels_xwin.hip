@@ -241,8 +241,8 @@ __global__ __launch_bounds__(BS) void k_xwin(XwinArgs a)
 
 // Second pass: workgroup b reads block b's partials run by run (window w's
 // run of pairs from first[b][w] fills slots pre[b][w]..pre[b][w+1]; the
-// window of a slot comes from a map built in LDS; eight loads in flight per
-// lane) and places each in LDS in row order, so that each of the block's
+// window of a slot comes from a map built in LDS; all of a lane's loads in
+// one round) and places each in LDS in row order, so that each of the block's
 // rows then adds its own contiguous partials (its windows in order, four
 // interleaved sums; 0 for a row with no entries), rounds once and, fused,
 // forms w = alpha*y + x.
@@ -277,31 +277,32 @@ __global__ __launch_bounds__(256) void k_xwin_sum(XsumArgs a)
     }
     __syncthreads();
     const int total = pre[S];
+    // every slot of the block in one round of loads (U per lane; slots
+    // clamped to the last one, so the loads are issued unconditionally):
+    // first the slots' places in row order, which need nothing else, then,
+    // once the map of windows is built, the partials
+    constexpr int U = (int)(kXwinStage / 256);
+    static_assert(U * 256 == kXwinStage, "staging area is a whole number of rounds");
+    uint16_t place[U];
+    if (total > 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            place[u] = __builtin_nontemporal_load(a.rowpos + base + min(u * 256 + t, total - 1));
+    }
     for (int w = t; w < S; w += 256)
         for (int j = pre[w]; j < pre[w + 1]; ++j) wof[j] = (uint16_t)w;
     __syncthreads();
-    // staging: slot j's partial and its place in row order, eight of each
-    // in flight per lane (slots clamped to the last one, so the loads are
-    // issued unconditionally)
-    constexpr int U = 8;
-    for (int j0 = 0; j0 < total; j0 += 256 * U) {
-        int jj[U], src[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = min(j0 + u * 256 + t, total - 1);
+    if (total > 0) {
+        double v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int w = wof[jj[u]];
-            src[u] = first[w] + (jj[u] - pre[w]);
+            const int jj = min(u * 256 + t, total - 1);
+            const int w = wof[jj];
+            v[u] = __builtin_nontemporal_load(a.part + first[w] + (jj - pre[w]));
         }
-        double v[U];
-        uint16_t q[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(a.part + src[u]);
-#pragma unroll
-        for (int u = 0; u < U; ++u) q[u] = __builtin_nontemporal_load(a.rowpos + base + jj[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (j0 + u * 256 + t < total) stage[q[u]] = v[u];
+            if (u * 256 + t < total) stage[place[u]] = v[u];
     }
     __syncthreads();
     // each row's partials are contiguous: four interleaved sums (a fixed

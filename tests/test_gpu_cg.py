@@ -291,3 +291,34 @@ def test_cg_full_size_lap3d_128(spk, dev):
     finally:
         M.release()
         h.close()
+
+
+def test_cg_irregular_spd_long_run(spk, dev):
+    """Past the first iterations two correct CGs on the irregular SPD matrix
+    part ways in their iterates (rounding amplified once orthogonality is
+    lost), so that matrix is compared with the oracle over 8 iterations
+    above; over a long run both must still reach the solution. After 250
+    iterations the GPU's x equals a direct sparse solve (an independent
+    method) and the oracle's x within 1e-12 of max|x|, its true residual
+    b - Ax is at rounding level, and its recurrence r.r fell by 1e-30 (the
+    oracle reaches these levels by 200 iterations on the same inputs)."""
+    import scipy.sparse as sps
+    import scipy.sparse.linalg as spla
+    A = I.spd_zipf(3000)
+    b, x0 = _vecs(A, 7)
+    iters = 250
+    say("cg long run spd_zipf_3000", iters)
+    M = spk.Matrix(A)
+    try:
+        x, hist = _run(spk, M, b, x0, iters, dev)
+    finally:
+        M.release()
+    xo, ho = O.cg(A, b, iters, x0)
+    S = sps.csr_matrix((A.val, A.col_idx, A.row_ptr), shape=(A.nrows, A.ncols))
+    xd = spla.spsolve(S.tocsc(), b)
+    scale = np.abs(xd).max()
+    assert np.all(np.isfinite(x)) and np.all(np.isfinite(hist))
+    assert np.abs(x - xd).max() <= 1e-12 * scale
+    assert np.abs(x - xo).max() <= 1e-12 * scale
+    assert np.linalg.norm(b - S @ x) <= 1e-12 * np.linalg.norm(b)
+    assert hist[-1] <= 1e-30 * hist[0] and ho[-1] <= 1e-30 * ho[0]
