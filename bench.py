@@ -828,7 +828,7 @@ def serving(spk, I, nreq, warm, npool):
         ids["pressure"] = [srv.add_matrix(A) for A in pool]
         count["pressure"] = 0
         small = min(total, 5000 + warm)
-        rate = 0.2 * sat[0]
+        rate = 0.12 * sat[0]
         arr = I.poisson_arrivals(small, rate, seed=53)
         s0 = srv.stats()
         t0 = time.perf_counter()

@@ -141,6 +141,7 @@ struct Flight {
     void *dev = nullptr, *pin = nullptr;
     size_t y_off = 0, w_off = 0;
     int64_t vec_bytes = 0;
+    int stream = 0;            // index of the stream it runs on
     double t_enqueued = 0.0;   // when its input copy was enqueued
     hipEvent_t done = nullptr;
     int dtype = SPK_F64;
@@ -156,7 +157,7 @@ struct spk_server_s {
     const spk::BatchEntry *entry = nullptr;
     std::vector<hipStream_t> streams;
     hipStream_t upload = nullptr;
-    int next_stream = 0;
+    std::vector<int> stream_load;           // launches in flight per stream
     std::deque<spk::PoolMat> mats;          // guarded by mats_mu
     std::mutex mats_mu;                     // held by the scheduler for a whole turn
     std::atomic<int32_t> nmats{0};
@@ -399,8 +400,21 @@ spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &gro
     }
     const double t_stage = now_seconds();
     S->copies.copy(cp);
-    hipStream_t s = S->streams[S->next_stream];
-    S->next_stream = (S->next_stream + 1) % (int)S->streams.size();
+    // the stream with the fewest launches in flight (the lowest index among
+    // equals): a launch does not queue behind another while a stream is idle
+    F.stream = (int)(std::min_element(S->stream_load.begin(), S->stream_load.end()) - S->stream_load.begin());
+    ++S->stream_load[(size_t)F.stream];
+    // a launch that fails before it becomes a flight gives its stream back
+    struct Unload {
+        Server *S;
+        int stream;
+        bool keep = false;
+        ~Unload()
+        {
+            if (!keep) --S->stream_load[(size_t)stream];
+        }
+    } unload{S, F.stream};
+    hipStream_t s = S->streams[(size_t)F.stream];
     // order the launch after uploads still in flight (each matrix once)
     for (const auto &g : group) {
         PoolMat &M = S->mats[g.second.mat];
@@ -463,6 +477,7 @@ spk_status launch_group(Server *S, std::vector<std::pair<int64_t, Request>> &gro
     for (const auto &g : group) F.vec_bytes += vec_bytes_of(S->mats[g.second.mat]);
     ++S->batches;
     S->flights.push_back(std::move(F));
+    unload.keep = true;
     return SPK_OK;
 }
 
@@ -499,6 +514,7 @@ bool retire(Server *S)
         S->dpool.put(F.dev);
         S->hpool.put(F.pin);
         S->spare_events.push_back(F.done);
+        --S->stream_load[(size_t)F.stream];
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->used_vec -= F.vec_bytes;
@@ -665,6 +681,7 @@ spk_status spk_serve_create(spk_handle h, const spk_serve_opts *opts, spk_server
         }
         S->streams.push_back(s);
     }
+    S->stream_load.assign(S->streams.size(), 0);
     if (hipStreamCreateWithFlags(&S->upload, hipStreamNonBlocking) != hipSuccess) {
         spk_serve_destroy(S);
         return fail(SPK_ERR_HIP, "stream creation failed");
