@@ -151,6 +151,8 @@ __device__ __forceinline__ void window_pairs(const XwinArgs &a, const T *win, in
 // window chunk_w[c]; wavefront v takes tiles v, v + NW, ...  The window's
 // x values (WB bytes at most) are copied to LDS once, eight loads in flight
 // per lane.
+constexpr int kRing = 4;   // tiles in the window pass's software pipeline
+
 template <typename T, int BS, int WB, int E>
 __global__ __launch_bounds__(BS) void k_xwin(XwinArgs a)
 {
@@ -185,8 +187,10 @@ __global__ __launch_bounds__(BS) void k_xwin(XwinArgs a)
     // The wavefront's tiles are t0, t0 + NW, ...; their records are read 64
     // at a time with one vector load per lane (kept in registers and taken
     // out with readlane, so no scalar load stands between a tile and its
-    // data), then the tiles run as a software pipeline over a ring of four:
-    // the loads of the next three tiles are in flight while one is summed.
+    // data), then the tiles run as a software pipeline over a ring of
+    // kRing: the loads of the next kRing - 1 tiles are in flight while one
+    // is summed (seven loads per tile: within the 63 a wavefront may have
+    // outstanding; a ring of eight ran slower).
     using Tile = WinTile<T, E / kWave>;
     const int l = threadIdx.x & (kWave - 1);
     const int tw0 = a.chunk_t[c] + wv;
@@ -214,19 +218,17 @@ __global__ __launch_bounds__(BS) void k_xwin(XwinArgs a)
         auto run = [&](const Tile &tl) {
             if (tl.stream) window_stream(a, win, tl, my_sp, my_srp);
         };
-        Tile b0, b1, b2, b3;
-        load(0, b0);
-        load(1, b1);
-        load(2, b2);
-        for (int i = 0; i < nb; i += 4) {
-            load(i + 3, b3);
-            run(b0);
-            load(i + 4, b0);
-            if (i + 1 < nb) run(b1);
-            load(i + 5, b1);
-            if (i + 2 < nb) run(b2);
-            load(i + 6, b2);
-            if (i + 3 < nb) run(b3);
+        // ring slots are indexed by constants once the inner loop is
+        // unrolled, so the ring stays in registers
+        Tile ring[kRing];
+#pragma unroll
+        for (int r = 0; r < kRing - 1; ++r) load(r, ring[r]);
+        for (int i = 0; i < nb; i += kRing) {
+#pragma unroll
+            for (int r = 0; r < kRing; ++r) {
+                load(i + r + kRing - 1, ring[(r + kRing - 1) % kRing]);
+                if (r == 0 || i + r < nb) run(ring[r]);
+            }
         }
         // ... then the tiles of pairs too long for the row stream, one
         // wavefront per pair
