@@ -193,6 +193,13 @@ def test_serve_pinned_buffers_skip_staging(spk, dev, mode):
             solo.drain()
             assert np.array_equal(y1, ys[i]) and np.array_equal(w1, ws[i]), i
         assert solo.stats()["direct"] == 0
+        # the step without w (SpMV only), pinned x and y: direct, same y
+        for i in (0, 1):
+            y2 = pinned(pool[mats[i]].nrows, pool[mats[i]].val.dtype)
+            solo.submit(ids[mats[i]], xs[i], y2)
+            solo.drain()
+            assert np.array_equal(y2, ys[i]), i
+        assert solo.stats()["direct"] == 2
     finally:
         solo.close()
 

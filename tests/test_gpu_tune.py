@@ -160,11 +160,22 @@ def test_tune_resume_times_only_the_rest(spk, dev, tmp_path):
 
 def test_tune_resume_needs_a_matching_problem(spk, dev, tmp_path):
     """Journal points are filed under the problem's sizes: a problem of the
-    same class but other sizes does not take them."""
+    same class but other sizes does not take them; nor does a search take a
+    point journaled by another library build."""
     db = str(tmp_path / "plans.spkdb")
+    n0 = 1 << 20
+    h = spk.Handle(0)
+    arch = h.info()[1].rsplit("(", 1)[1].rstrip(")")
+    h.close()
+    # journal lines of another library build, for every variant under the
+    # first problem's key, are ignored
+    with open(db, "w") as f:
+        for v in spk.variants(spk.SPK_OP_WAXPY, spk.SPK_F64):
+            f.write(json.dumps({"point": f"tune|waxpy:f64:n20|op{spk.SPK_OP_WAXPY}|n{n0}", "arch": arch,
+                                "build": "another-build", "v": list(v.as_dict().values()), "us": 0.001}) + "\n")
     h = spk.Handle(0, db)
     try:
-        for n in (1 << 20, (1 << 20) + 4096):
+        for n in (n0, n0 + 4096):
             x = torch.from_numpy(I.uniform(123, 0, n)).to(dev)
             yv = torch.from_numpy(I.uniform(124, 0, n)).to(dev)
             w = torch.empty_like(x)
@@ -173,6 +184,11 @@ def test_tune_resume_needs_a_matching_problem(spk, dev, tmp_path):
             assert rep.resumed == 0 and rep.tried == 8
     finally:
         h.close()
+    # the planted lines carried the key this build files the first problem under
+    with open(db) as f:
+        pts = [json.loads(ln) for ln in f if ln.startswith('{"point": ')]
+    mine = {p["point"] for p in pts if p["build"] != "another-build"}
+    assert f"tune|waxpy:f64:n20|op{spk.SPK_OP_WAXPY}|n{n0}" in mine and len(mine) == 2
 
 
 def test_cg_tune_rejects_journal_options(spk, dev):
