@@ -208,13 +208,14 @@ hipError_t L_batch(const void *p, dim3 g, hipStream_t s)
      {occ_batch<float, BS, TILE, XW>, occ_batch<double, BS, TILE, XW>}}
 
 // (threads per workgroup, LDS products per workgroup, LDS room for x per
-// wavefront): a wavefront's row stream holds TILE/(BS/64) entries: 256,
-// 512 or 1024; the kernels with room for x run mode-1 tiles from LDS
+// wavefront): a wavefront's row stream holds TILE/(BS/64) entries: 256
+// to 2048; the kernels with room for x run mode-1 tiles from LDS
 const BatchEntry kBatch[] = {
     BENTRY(256, 2048, 0), BENTRY(256, 1024, 0), BENTRY(256, 4096, 0),
     BENTRY(128, 1024, 0), BENTRY(128, 2048, 0),
     BENTRY(512, 2048, 0), BENTRY(512, 4096, 0),
     BENTRY(256, 2048, 256), BENTRY(256, 4096, 256), BENTRY(128, 2048, 256),
+    BENTRY(128, 1024, 256), BENTRY(64, 1024, 256), BENTRY(64, 512, 256), BENTRY(64, 2048, 256),
 };
 
 }  // namespace
