@@ -326,6 +326,8 @@ const SpmvEntry kSpmv[] = {
     ADAPT(256, 256), ADAPT(256, 512), ADAPT(256, 1024),
     ADAPT(512, 256), ADAPT(512, 512), ADAPT(512, 1024),
     ADAPT_X(128, 256), ADAPT_X(256, 256), ADAPT_X(256, 512), ADAPT_X(512, 256),
+    // one-wavefront workgroups
+    ADAPT(64, 256), ADAPT(64, 512), ADAPT(64, 1024), ADAPT_X(64, 256), ADAPT_X(64, 512), ADAPT_X(64, 1024),
     // wider accesses: two entries (16 bytes of FP64 values, 8 of FP32) or
     // four (16 bytes of FP32 values) per access
     SCALAR_V(256, 2), SCALAR_V(256, 4),
