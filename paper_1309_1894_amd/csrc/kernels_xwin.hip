@@ -349,6 +349,7 @@ hipError_t L_xwin(const XwinArgs &a, hipStream_t s)
 const XwinEntry kXwin[] = {
     XENTRY(512, 128, 256),
     XENTRY(1024, 128, 128),
+    XENTRY(768, 128, 256),   // 161,840 bytes of LDS: twelve wavefronts of 256-entry tiles
     XENTRY(256, 64, 256),
     XENTRY(512, 64, 256),
 };

@@ -18,7 +18,7 @@ from test_gpu_spmv import CASES, NP, _check, csr_from_entries
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = [(512, 128, 256), (1024, 128, 128), (256, 64, 256), (512, 64, 256)]
+KERNELS = [(512, 128, 256), (1024, 128, 128), (768, 128, 256), (256, 64, 256), (512, 64, 256)]
 
 
 def _variants(spk):
