@@ -533,16 +533,19 @@ typedef struct {
     int32_t x_window;        /* LDS room for x per wavefront (entries; 0 or 256)
                               * of the kernel used with an explicit block; a
                               * kernel with room runs the tiles of classes
-                              * tuned to mode 1 with the tile's window of x
-                              * staged in LDS (block 0 takes the recorded
-                              * value) */
+                              * tuned to mode 1 (or 3) with the tile's window
+                              * of x staged in LDS (block 0 takes the
+                              * recorded value) */
 } spk_batch_opts;
 
 /* Plans the batch (not in the paper; the configured batched workload):
  * instances -> shape classes -> tiles, each class served by
  * the variant recorded for it (see spk_batch_tune), tiles ordered largest
  * first.  The descriptor arrays are copied; the device arrays are borrowed
- * for the batch's lifetime.  Each instance's row_ptr is checked (starts at
+ * for the batch's lifetime.  Classes planned with compact columns (mode 3)
+ * read a one-byte copy of their column indices (each entry's place in its
+ * tile's window of x) that the plan makes from col_idx and owns: col_idx
+ * must not change while the plan lives.  Each instance's row_ptr is checked (starts at
  * 0, never decreases, ends at nnz: SPK_ERR_CSR otherwise); column indices
  * are not (as in spk_spmv_csr, one outside [0, m_i) reads outside the
  * instance's x).  A batch runs as one launch of at most 2^24
@@ -569,7 +572,10 @@ spk_status spk_batch_run(spk_handle h, spk_batch b, double alpha, const void *x,
  * LDS tile per workgroup, room for x in LDS, grid or persistent kind) on
  * the whole batch, then the tile kernel of each shape class under it (LDS
  * row stream, the same with the tile's x window staged in LDS when the
- * kernel has room for it, or G lanes per row), then the launch shape again
+ * kernel has room for it, the same again with compact columns -- one byte
+ * per entry, its offset in the window, instead of four: a storage-format
+ * choice of the tuner, not a knob the paper lists -- or G lanes per row),
+ * then the launch shape again
  * with the tuned kernels.  Every candidate is validated before it is timed
  * against the unannotated program's output: the plain kernel (one lane per
  * row, fused with the update when w is given) run instance by instance,
@@ -591,6 +597,14 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
  * Library plumbing, not in the paper. */
 spk_status spk_batch_info(spk_handle h, spk_batch b, int64_t *tiles, int32_t *classes,
                           int64_t *bytes);
+
+/* Tiles and matrix entries per kernel mode as planned on the device (after
+ * the x windows are found, so a mode-3 tile whose window did not fit counts
+ * as mode 1): tiles[mode] and entries[mode] for mode 0..64 (host arrays of
+ * 65; entries nullable; 0 = LDS row stream, 1 = with the tile's window of x
+ * in LDS, 3 = the same with compact columns, G = G lanes per row).
+ * Synchronises with the device.  Library plumbing, not in the paper. */
+spk_status spk_batch_tile_modes(spk_handle h, spk_batch b, int64_t *tiles, int64_t *entries);
 
 /* The launch configuration the batch currently uses (after planning or
  * tuning, Section 3's threads per block and blocks per grid): persistence,

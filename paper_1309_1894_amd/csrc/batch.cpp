@@ -45,6 +45,8 @@ struct spk_batch_s {
     std::vector<spk::BatchTile> tiles;
     spk::BatchTile *d_tiles = nullptr;
     int64_t d_tiles_cap = 0;
+    uint8_t *c8 = nullptr;                // compact columns of mode-3 tiles (laid out like the caller's col_idx)
+    int64_t c8_len = 0;
     int64_t grid_persistent = 0;
     std::mutex mu;                        // guards `streams`
     std::map<hipStream_t, BatchStream> streams;
@@ -94,7 +96,7 @@ const BatchEntry *batch_entry(int block, int tile, int xw)
     return nullptr;
 }
 
-bool is_stream_mode(int mode) { return mode == 0 || mode == 1; }
+bool is_stream_mode(int mode) { return mode == 0 || mode == 1 || mode == 3; }
 
 void cut_rows(const int32_t *rp, int64_t m, int mode, int entries, int64_t target, std::vector<BatchTile> &out)
 {
@@ -222,9 +224,15 @@ spk_status stream_state(spk_batch b, hipStream_t s, BatchStream **out)
     return SPK_OK;
 }
 
-// Tiles of instance i under `mode`.
+// Whether the batch's kernel can run mode-3 tiles (compact columns index a
+// window of at most 256 entries of x in LDS).
+bool compact_ok(const spk_batch b) { return b->entry->xw > 0 && b->entry->xw <= 256; }
+
+// Tiles of instance i under `mode` (mode 3 on a kernel that cannot run it
+// is cut as mode 1).
 void cut_instance(const spk_batch b, int64_t i, int mode, std::vector<BatchTile> &out)
 {
+    if (mode == 3 && !compact_ok(b)) mode = 1;
     const size_t first = out.size();
     cut_rows(b->rp_host.data() + b->rp_off[i], b->m[i], mode, batch_wave_entries(*b->entry), b->opts.tile_nnz,
              out);
@@ -246,13 +254,26 @@ spk_status upload_tiles(spk_batch b, const std::vector<BatchTile> &tiles)
         SPK_HIP(hipMalloc(&b->d_tiles, sizeof(BatchTile) * cap));
         b->d_tiles_cap = cap;
     }
+    // the compact-column array of mode-3 tiles, sized like the caller's
+    // col_idx span plus one 16-byte group (the kernel reads whole aligned
+    // groups), allocated at the first plan that has such tiles
+    bool any3 = false;
+    for (const BatchTile &t : tiles) any3 = any3 || t.mode == 3;
+    if (any3 && !b->c8) {
+        int64_t len = 0;
+        for (int64_t i = 0; i < b->count; ++i) len = std::max<int64_t>(len, b->nz_off[i] + b->nnz[i]);
+        len = (len + 15) / 16 * 16 + 16;
+        SPK_HIP(hipMalloc(&b->c8, (size_t)len));
+        b->c8_len = len;
+    }
     // ordered after any launch already queued on the work stream that reads the old tiles
     if (!tiles.empty()) {
         SPK_HIP(hipMemcpyAsync(b->d_tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice,
                                b->h->work));
-        // the x windows of mode-1 tiles, for a kernel with room for them
+        // the x windows of mode-1 and mode-3 tiles, for a kernel with room
+        // for them; mode-3 tiles get their compact columns
         if (b->entry->xw > 0)
-            SPK_HIP(launch_tile_windows(b->d_tiles, (int64_t)tiles.size(), b->entry->xw, b->h->work));
+            SPK_HIP(launch_tile_windows(b->d_tiles, (int64_t)tiles.size(), b->entry->xw, b->h->work, b->ci, b->c8));
         SPK_HIP(hipStreamSynchronize(b->h->work));
     }
     return SPK_OK;
@@ -711,7 +732,7 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
         snprintf(ctx, sizeof ctx, "|c%d|%d,%d,%d,%d", c, b->entry->block, b->entry->tile, b->entry->xw,
                  b->opts.persistent);
         const std::string key = bkey + ctx;
-        for (int mode : {0, 1, 2, 4, 8, 16, 32, 64}) {
+        for (int mode : {0, 1, 3, 2, 4, 8, 16, 32, 64}) {
             spk_variant pv{};
             pv.group = mode;
             double med = 0;
@@ -726,10 +747,11 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
             }
             if (must_stop()) return interrupted();
             ++fresh;
-            // mode 1 is timed with the kernel of the same shape that has
-            // room for x (without that room it would run as mode 0)
+            // modes 1 and 3 are timed with the kernel of the same shape
+            // that has room for x (without that room mode 1 would run as
+            // mode 0, and mode 3 as mode 1)
             const BatchEntry *keep = b->entry;
-            if (mode == 1) {
+            if (mode == 1 || mode == 3) {
                 const BatchEntry *xe = keep->xw > 0 ? keep : batch_entry(keep->block, keep->tile, 256);
                 if (!xe) continue;
                 b->entry = xe;
@@ -818,6 +840,27 @@ spk_status spk_batch_tune(spk_handle h, spk_batch b, double alpha, const void *x
     return SPK_OK;
 }
 
+spk_status spk_batch_tile_modes(spk_handle h, spk_batch b, int64_t *tiles, int64_t *entries)
+{
+    if (!h || !b || !tiles) return fail(SPK_ERR_NULL, "NULL argument");
+    if (b->h != h) return fail(SPK_ERR_ARG, "batch belongs to another handle");
+    for (int i = 0; i <= 64; ++i) {
+        tiles[i] = 0;
+        if (entries) entries[i] = 0;
+    }
+    if (b->tiles.empty()) return SPK_OK;
+    DeviceGuard g(h);
+    std::vector<BatchTile> t(b->tiles.size());
+    SPK_HIP(hipStreamSynchronize(h->work));
+    SPK_HIP(hipMemcpy(t.data(), b->d_tiles, sizeof(BatchTile) * t.size(), hipMemcpyDeviceToHost));
+    for (const BatchTile &x : t) {
+        if (x.mode < 0 || x.mode > 64) continue;
+        ++tiles[x.mode];
+        if (entries) entries[x.mode] += (int64_t)x.k1 - x.k0;
+    }
+    return SPK_OK;
+}
+
 spk_status spk_batch_config(spk_handle h, spk_batch b, spk_batch_opts *out)
 {
     if (!h || !b || !out) return fail(SPK_ERR_NULL, "NULL argument");
@@ -836,6 +879,7 @@ spk_status spk_batch_free(spk_handle h, spk_batch b)
     (void)hipDeviceSynchronize();
     invalidate_graph(b);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->c8) (void)hipFree(b->c8);
     for (auto &kv : b->streams)
         if (kv.second.ctr) (void)hipFree(kv.second.ctr);
     delete b;

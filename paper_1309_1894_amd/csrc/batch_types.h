@@ -11,11 +11,14 @@ namespace spk {
 // 1 = the same with the tile's window of x staged in LDS too (columns
 // [xlo, xlo + xn), found on the device after planning; xn = 0 when the
 // window is wider than the kernel's room for it, and then x is gathered
-// from memory as in mode 0), G in {2, 4, ..., 64} = G lanes per row
-// straight from memory.  The tile
-// carries its matrix's arrays and the offset of the matrix's vectors inside
-// the launch's x / y / w, so a wavefront needs one 64-byte descriptor load
-// before it can start streaming.
+// from memory as in mode 0), 3 = mode 1 with compact columns (once the
+// window is found and fits, ci points to one byte per entry, the entry's
+// column minus xlo, written by the planner; a tile whose window does not
+// fit is turned into a mode-1 tile), G in {2, 4, ..., 64} = G lanes per
+// row straight from memory.  The tile carries its matrix's arrays and the
+// offset of the matrix's vectors inside the launch's x / y / w, so a
+// wavefront needs one 64-byte descriptor load before it can start
+// streaming.
 struct BatchTile {
     const int32_t *rp;
     const int32_t *ci;

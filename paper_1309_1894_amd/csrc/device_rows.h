@@ -64,15 +64,24 @@ __device__ __forceinline__ gptr_mut<T> as_global_mut(T *p) { return (gptr_mut<T>
 // wavefront's LDS slice xs with coalesced loads issued together with the
 // entry loads (they do not wait for the column indices), and the gathers
 // read LDS.
-template <typename T, int ITEMS, bool DOT = false, int XW = 0>
+// With C8 (compact columns; needs XW > 0 and 0 < xn <= XW <= 256), ci_
+// points to one byte per entry, the entry's column minus xlo: its place in
+// the window.  The bytes travel in the same 16-byte groups (sixteen entries
+// each instead of four) and through the same LDS staging, so an entry costs
+// 1 byte of index traffic instead of 4; everything else, the order of the
+// arithmetic included, is as with 4-byte columns.
+template <typename T, int ITEMS, bool DOT = false, int XW = 0, bool C8 = false>
 __device__ __forceinline__ double wave_stream(const int32_t *rp_, const int32_t *ci_, const T *val_, const T *x_,
                                               T *y_, T *w_, T alpha, int r0, int r1, int k0, int k1, double *sp,
                                               int *srp, int xlo = 0, int xn = 0, T *xs = nullptr)
 {
-    constexpr int STEPS = (ITEMS * kWave + 3 + 4 * kWave - 1) / (4 * kWave);
-    static_assert(STEPS * 4 * kWave <= 2 * kWave * ITEMS, "staged index groups must fit the product slice");
+    static_assert(!C8 || (XW > 0 && XW <= 256), "compact columns index a window of at most 256 entries");
+    constexpr int IB = C8 ? 1 : 4;            // bytes per stored column
+    constexpr int GE = 16 / IB;               // entries per 16-byte group
+    constexpr int STEPS = (ITEMS * kWave + GE - 1 + GE * kWave - 1) / (GE * kWave);
+    static_assert(STEPS * 16 * kWave <= 8 * kWave * ITEMS, "staged index groups must fit the product slice");
     const gptr<int32_t> rp = as_global(rp_);
-    const gptr<int32_t> ci = as_global(ci_);
+    const gptr<uint8_t> cb = as_global(reinterpret_cast<const uint8_t *>(ci_));
     const gptr<T> val = as_global(val_);
     const gptr<T> x = as_global(x_);
     const gptr_mut<T> y = as_global_mut(y_);
@@ -81,17 +90,18 @@ __device__ __forceinline__ double wave_stream(const int32_t *rp_, const int32_t 
     const int nr = r1 - r0;
     const int nk = k1 - k0;
     if (nr <= 0) return 0.0;
-    int *sci = reinterpret_cast<int *>(sp);   // 2*64*ITEMS ints of room
-    const int off = (int)(((uintptr_t)(ci_ + k0) >> 2) & 3u);   // entries before k0 in the first group
+    uint8_t *scb = reinterpret_cast<uint8_t *>(sp);   // 8*64*ITEMS bytes of room
+    // entries before k0 in the first group
+    const int off = (int)(((uintptr_t)ci_ + (uintptr_t)k0 * IB) & 15u) / IB;
     const int klast = nk > 0 ? nk - 1 : 0;
     int4v g[STEPS];
     T v[ITEMS];
     if (nk > 0) {
-        const gptr<int32_t> cg = ci + k0 - off;
-        const int glast = (off + klast) & ~3;   // start of the last group holding an entry
+        const gptr<uint8_t> cg = cb + ((int64_t)k0 - off) * IB;
+        const int glast = (off + klast) & ~(GE - 1);   // start of the last group holding an entry
 #pragma unroll
         for (int s = 0; s < STEPS; ++s)
-            g[s] = __builtin_nontemporal_load((gptr<int4v>)(cg + min(4 * (l + kWave * s), glast)));
+            g[s] = __builtin_nontemporal_load((gptr<int4v>)(cg + IB * min(GE * (l + kWave * s), glast)));
         // matrix entries are read exactly once: non-temporal, so the cache
         // keeps the x entries that neighbouring rows share
 #pragma unroll
@@ -116,7 +126,7 @@ __device__ __forceinline__ double wave_stream(const int32_t *rp_, const int32_t 
     }
     if (nk > 0) {
 #pragma unroll
-        for (int s = 0; s < STEPS; ++s) *(int4v *)(sci + 4 * (l + kWave * s)) = g[s];
+        for (int s = 0; s < STEPS; ++s) *(int4v *)(scb + 16 * (l + kWave * s)) = g[s];
         if constexpr (XW > 0) {
             if (win) {
 #pragma unroll
@@ -127,10 +137,17 @@ __device__ __forceinline__ double wave_stream(const int32_t *rp_, const int32_t 
         wave_lds_sync();
         int c[ITEMS];
 #pragma unroll
-        for (int j = 0; j < ITEMS; ++j) c[j] = sci[min(l + j * kWave, klast) + off];
+        for (int j = 0; j < ITEMS; ++j) {
+            const int q = min(l + j * kWave, klast) + off;
+            if constexpr (C8) c[j] = scb[q];
+            else c[j] = reinterpret_cast<const int *>(scb)[q];
+        }
         wave_lds_sync();   // the staged indices are read before products overwrite them
         T xv[ITEMS];
-        if (win) {
+        if constexpr (C8) {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) xv[j] = xs[c[j]];
+        } else if (win) {
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) xv[j] = xs[c[j] - xlo];
         } else {

@@ -54,6 +54,12 @@ __device__ __forceinline__ void run_wave_tile(const BatchArgs<T> &a, const Batch
                                                                  td.k0, td.k1, sp, srp, td.xlo,
                                                                  XW > 0 && td.xn <= XW ? td.xn : 0, xs);
         break;
+    case 3:  // mode 1 with compact columns: ci holds each entry's byte offset in the window (which fits)
+        if constexpr (XW > 0 && XW <= 256)
+            wave_stream<T, WaveTiles<T, BS, TILE>::ITEMS, false, XW, true>(rp, ci, val, x, y, w, a.alpha, td.r0,
+                                                                           td.r1, td.k0, td.k1, sp, srp, td.xlo,
+                                                                           td.xn, xs);
+        break;
     case 2: wave_group_rows<T, 2>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
     case 4: wave_group_rows<T, 4>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
     case 8: wave_group_rows<T, 8>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
@@ -152,18 +158,26 @@ __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs<T> a)
     }
 }
 
-// The x windows of mode-1 tiles (see launch_tile_windows).
-__global__ __launch_bounds__(256) void k_tile_windows(BatchTile *tiles, int64_t ntiles, int cap)
+// The x windows of mode-1 and mode-3 tiles (see launch_tile_windows), one
+// wavefront per tile.  A mode-3 tile whose window fits writes its entries'
+// offsets in the window to c8 (at the entries' own positions: instance
+// arrays at ci + d map to c8 + d) and takes c8 as its column array; one
+// whose window does not fit becomes a mode-1 tile that gathers x from
+// memory.
+__global__ __launch_bounds__(256) void k_tile_windows(BatchTile *tiles, int64_t ntiles, int cap, const int32_t *ci0,
+                                                      uint8_t *c8)
 {
     const int64_t t = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
     if (t >= ntiles) return;
     const int l = threadIdx.x & (kWave - 1);
     BatchTile &td = tiles[t];
-    if (td.mode != 1) return;
+    const int mode = td.mode;
+    if (mode != 1 && mode != 3) return;
+    const int32_t *ci = td.ci;
     const int k0 = td.k0, k1 = td.k1;
     int lo = INT32_MAX, hi = -1;
     for (int k = k0 + l; k < k1; k += kWave) {
-        const int c = td.ci[k];
+        const int c = ci[k];
         lo = min(lo, c);
         hi = max(hi, c);
     }
@@ -172,10 +186,18 @@ __global__ __launch_bounds__(256) void k_tile_windows(BatchTile *tiles, int64_t 
         lo = min(lo, __shfl_xor(lo, d));
         hi = max(hi, __shfl_xor(hi, d));
     }
+    const bool fits = hi >= lo && (int64_t)hi - lo + 1 <= cap;
+    const bool compact = mode == 3 && fits && cap <= 256 && c8 != nullptr;
+    uint8_t *cb = compact ? c8 + (ci - ci0) : nullptr;
+    if (compact)
+        for (int k = k0 + l; k < k1; k += kWave) cb[k] = (uint8_t)(ci[k] - lo);
     if (l == 0) {
-        const bool fits = hi >= lo && (int64_t)hi - lo + 1 <= cap;
         td.xlo = fits ? lo : 0;
         td.xn = fits ? hi - lo + 1 : 0;
+        if (mode == 3) {
+            td.mode = compact ? 3 : 1;
+            if (compact) td.ci = reinterpret_cast<const int32_t *>(cb);
+        }
     }
 }
 
@@ -226,10 +248,12 @@ const BatchEntry *batch_table(int *count)
     return kBatch;
 }
 
-hipError_t launch_tile_windows(BatchTile *tiles, int64_t ntiles, int cap, hipStream_t s)
+hipError_t launch_tile_windows(BatchTile *tiles, int64_t ntiles, int cap, hipStream_t s, const int32_t *ci0,
+                               uint8_t *c8)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tile_windows, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, tiles, ntiles, cap);
+    hipLaunchKernelGGL(k_tile_windows, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, tiles, ntiles, cap, ci0,
+                       c8);
     return hipGetLastError();
 }
 

@@ -87,9 +87,14 @@ __global__ __launch_bounds__(kBS) void k_tiles_absum(const BatchTile *tiles, con
     const BatchTile td = tiles[blockIdx.x];
     const T *val = (const T *)td.val;
     const T *xi = x + td.vec_off;
+    // mode-3 tiles hold each entry's column as a byte offset from xlo
+    const uint8_t *c8 = td.mode == 3 ? reinterpret_cast<const uint8_t *>(td.ci) : nullptr;
     for (int r = td.r0 + (int)threadIdx.x; r < td.r1; r += kBS) {
         double s = 0.0;
-        for (int k = td.rp[r]; k < td.rp[r + 1]; ++k) s += __builtin_fabs((double)val[k] * (double)xi[td.ci[k]]);
+        for (int k = td.rp[r]; k < td.rp[r + 1]; ++k) {
+            const int c = c8 ? td.xlo + c8[k] : td.ci[k];
+            s += __builtin_fabs((double)val[k] * (double)xi[c]);
+        }
         scale[td.vec_off + r] = s;
     }
 }

@@ -711,6 +711,7 @@ spk_status spk_serve_add_matrix(spk_server S, const spk_csr *A, int32_t *id)
     int mode = batch_default_mode(cls, batch_wave_entries(*S->entry));
     spk_variant v{};
     if (spk_plan_get(S->h, batch_key(A->dtype, cls).c_str(), &v) == SPK_OK) mode = v.group;
+    if (mode == 3) mode = 1;   // resident matrices keep 4-byte columns only
     cut_rows(rp, A->nrows, mode, batch_wave_entries(*S->entry), 1024, M.tiles);
     if ((int64_t)M.tiles.size() > kMaxLaunchTiles)
         return fail(SPK_ERR_SHAPE, "the matrix needs %lld tiles, more than one launch takes",

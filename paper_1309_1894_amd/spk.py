@@ -141,6 +141,7 @@ _SIGS = {
     "spk_batch_run": (_S, [_P, _P, _D, _P, _P, _P, _P]),
     "spk_batch_tune": (_S, [_P, _P, _D, _P, _P, _P, C.POINTER(spk_tune_opts), C.POINTER(spk_tune_report)]),
     "spk_batch_info": (_S, [_P, _P, C.POINTER(_I64), C.POINTER(_I32), C.POINTER(_I64)]),
+    "spk_batch_tile_modes": (_S, [_P, _P, C.POINTER(_I64), C.POINTER(_I64)]),
     "spk_batch_config": (_S, [_P, _P, C.POINTER(spk_batch_opts)]),
     "spk_batch_free": (_S, [_P, _P]),
     "spk_serve_create": (_S, [_P, C.POINTER(spk_serve_opts), C.POINTER(_P)]),
@@ -615,6 +616,15 @@ class Batch:
         t, c, b = _I64(), _I32(), _I64()
         _ok(_lib.spk_batch_info(self.handle.ptr, self.ptr, C.byref(t), C.byref(c), C.byref(b)), "spk_batch_info")
         return {"tiles": int(t.value), "classes": int(c.value), "bytes": int(b.value)}
+
+    def tile_modes(self, entries=False) -> dict:
+        """Tiles per kernel mode as planned on the device ({mode: tiles}, modes with tiles only);
+        with ``entries``, {mode: (tiles, matrix entries)}."""
+        t, e = (_I64 * 65)(), (_I64 * 65)()
+        _ok(_lib.spk_batch_tile_modes(self.handle.ptr, self.ptr, t, e), "spk_batch_tile_modes")
+        if entries:
+            return {m: (int(t[m]), int(e[m])) for m in range(65) if t[m]}
+        return {m: int(t[m]) for m in range(65) if t[m]}
 
     def config(self) -> dict:
         o = spk_batch_opts()

@@ -287,16 +287,18 @@ def test_full_batched_workload(spk, dev):
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 def test_batch_x_window_mode(spk, dev, dt):
     """Every class planned to the row stream with the tile's x window staged
-    in LDS (mode 1, a kernel with room for 256 entries of x per wavefront):
-    each instance matches the oracle, and the bits equal the plain row
-    stream's (mode 0; only where x is read from differs), also for tiles
-    whose window is too wide for the room (x then read from memory)."""
+    in LDS (mode 1, a kernel with room for 256 entries of x per wavefront),
+    and the same with compact columns (mode 3: one byte per entry, its place
+    in the window): each instance matches the oracle, and the bits equal
+    the plain row stream's (mode 0; only where x and the columns are read
+    from differs), also for tiles whose window is too wide for the room
+    (x then read from memory; a mode-3 tile becomes a mode-1 tile)."""
     B = mixed_batch(dt)
     x = I.batch_vector(B, seed=21, dtype=dt)
     arrs = _dev_batch(B, dev)
     xd = torch.from_numpy(x).to(dev)
     outs = {}
-    for mode, xw in ((0, 0), (1, 256)):
+    for mode, xw in ((0, 0), (1, 256), (3, 256)):
         h = spk.Handle(0)
         for c in range(20):
             spk.spk_plan_put(f"batch:{'f64' if dt == np.float64 else 'f32'}:c{c}",
@@ -308,6 +310,11 @@ def test_batch_x_window_mode(spk, dev, dt):
         say(f"batch x window: mode {mode} room {xw} dtype={np.dtype(dt).name}")
         try:
             assert b.config()["x_window"] == xw
+            modes = b.tile_modes()
+            say(f"  tiles per mode: {modes}")
+            if mode == 3:
+                # windows that fit take compact columns; the Zipf instance's do not
+                assert modes.get(3, 0) > 0 and modes.get(1, 0) > 0
             b.run(0.5, xd, y, w)
             torch.cuda.synchronize()
             _check_batch(B, x, y, w, 0.5, dt)
@@ -315,7 +322,8 @@ def test_batch_x_window_mode(spk, dev, dt):
         finally:
             b.free()
             h.close()
-    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    for mode in (1, 3):
+        assert torch.equal(outs[0][0], outs[mode][0]) and torch.equal(outs[0][1], outs[mode][1]), mode
 
 
 def test_batch_tune_resume(spk, dev, tmp_path):

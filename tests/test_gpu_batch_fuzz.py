@@ -90,3 +90,51 @@ def test_random_batches(spk, dev, seed):
         assert np.array_equal(y.cpu().numpy(), yg) and np.array_equal(w.cpu().numpy(), wg)
     finally:
         b.free()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_batches_compact_columns(spk, dev, seed):
+    """The random batches with every class planned to compact columns (mode
+    3) on kernels with room for x, one to four wavefronts per workgroup:
+    each instance against the oracle, and bit for bit the result of the
+    plain row stream (mode 0) on the same batch."""
+    insts, dtype = random_batch(seed)
+    B = I.batch_from_instances(insts)
+    nv = int(B.m.sum())
+    x = I.batch_vector(B, seed=86 + seed, dtype=dtype)
+    arrays = (torch.from_numpy(B.row_ptr).to(dev), torch.from_numpy(B.col_idx).to(dev),
+              torch.from_numpy(B.val).to(dev))
+    xd = torch.from_numpy(x).to(dev)
+    block = (64, 128, 256)[seed % 3]
+    persistent = seed % 2
+    dname = "f64" if dtype == np.float64 else "f32"
+    outs = {}
+    for mode, xw in ((0, 256), (3, 256)):
+        h = spk.Handle(0)
+        for c in range(21):
+            spk.spk_plan_put(f"batch:{dname}:c{c}",
+                             spk.make_variant(format=spk.SPK_FMT_ADAPTIVE, block=block, group=mode, unroll=1,
+                                              streams=1, lds=2048), handle=h)
+        b = spk.Batch(B, arrays, handle=h, block=block, x_window=xw, persistent=bool(persistent))
+        say(f"fuzz compact seed={seed}: {B.count} instances, {nv} rows, mode {mode}, block {block}, "
+            f"persistent={persistent}, dtype={dname}, tiles per mode {b.tile_modes()}")
+        try:
+            y = torch.full((max(nv, 1),), float("nan"), dtype=xd.dtype, device=dev)[:nv]
+            w = torch.full((max(nv, 1),), float("nan"), dtype=xd.dtype, device=dev)[:nv]
+            b.run(0.5, xd, y, w)
+            torch.cuda.synchronize()
+            outs[mode] = (y.cpu().numpy().copy(), w.cpu().numpy().copy())
+        finally:
+            b.free()
+            h.close()
+    yg, wg = outs[3]
+    for i in range(B.count):
+        A = B.instance(i)
+        o = int(B.vec_off[i])
+        xi = x[o:o + A.nrows]
+        ref, absum = O.spmv(A, xi)
+        bad, worst, at = O.check_rows(yg[o:o + A.nrows].astype(np.float64), ref, absum, O.tau_for(dtype))
+        assert bad == 0, f"seed {seed} instance {i}: {bad} rows (worst {worst:g} at {at})"
+        d, at = O.max_ulp(wg[o:o + A.nrows], O.waxpy(0.5, yg[o:o + A.nrows], xi))
+        assert d <= (0 if dtype == np.float64 else 1), (seed, i, d, at)
+    assert np.array_equal(outs[0][0], yg) and np.array_equal(outs[0][1], wg)
