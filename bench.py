@@ -116,6 +116,17 @@ def main():
     log(f"batch tune: {rep.tried} candidates timed, {rep.rejected} rejected, {info['classes']} classes, "
         f"{info['tiles']} tiles ({time.time() - t0:.1f}s)")
 
+    # the bytes the tuned plan's own form moves: tiles with compact columns
+    # (mode 3) read one byte per entry for its column instead of four
+    modes = batch.tile_modes(entries=True)
+    form_bytes = step_bytes - 3 * modes.get(3, (0, 0))[1]
+    log(f"batched tiles per mode (tiles, entries): {modes}; form bytes {form_bytes} of {step_bytes} algorithmic")
+    # the same plan with 4-byte columns, timed before the headline so that
+    # the headline's steps are the last launches of its kernel
+    four_byte = tuned_four_byte_columns(spk, B, (d_rp, d_ci, d_val), d_x, d_y, d_w, alpha, stream, torch, np,
+                                        step_bytes, args.steps, args.warmup)
+    log(f"batched tuned with 4-byte columns only: {four_byte}")
+
     # timed region: exactly K steps, synchronised on both sides
     for _ in range(args.warmup):
         batch.run(alpha, d_x, d_y, d_w)
@@ -135,14 +146,6 @@ def main():
     value = step_bytes / (ms_per_step * 1e-3) / 1e9
     achieved = step_bytes / (kern_ms * 1e-3) / 1e9
     log(f"batched tuned: {ms_per_step:.3f} ms/step, {value:.1f} GB/s (kernel {kern_ms:.3f} ms, {achieved:.1f} GB/s)")
-    # the bytes the tuned plan's own form moves: tiles with compact columns
-    # (mode 3) read one byte per entry for its column instead of four
-    modes = batch.tile_modes(entries=True)
-    form_bytes = step_bytes - 3 * modes.get(3, (0, 0))[1]
-    log(f"batched tiles per mode (tiles, entries): {modes}; form bytes {form_bytes} of {step_bytes} algorithmic")
-    four_byte = tuned_four_byte_columns(spk, B, (d_rp, d_ci, d_val), d_x, d_y, d_w, alpha, stream, torch, np,
-                                        step_bytes, args.steps, args.warmup)
-    log(f"batched tuned with 4-byte columns only: {four_byte}")
 
     # plain baseline on the same batch: per-instance plain kernels, unfused
     cfg = batch.config()
@@ -472,8 +475,8 @@ def zipf_forms(spk, torch, I, dev, reps=5):
                                                 streams=1, lds=256)),
              ("csr_column_blocks", spk.make_variant(format=spk.SPK_FMT_COLBLOCK, block=128, group=2, unroll=1,
                                                     streams=1, lds=256)),
-             ("csr_x_windows_in_lds", spk.make_variant(format=spk.SPK_FMT_XWIN, block=1024, group=128, unroll=1,
-                                                       grid=1, streams=1, lds=128)))
+             ("csr_x_windows_in_lds", spk.make_variant(format=spk.SPK_FMT_XWIN, block=768, group=128, unroll=1,
+                                                       grid=1, streams=1, lds=256)))
     nbytes = A.nnz * 12 + 4 * (A.nrows + 1) + 8 * A.ncols + 8 * A.nrows
     res = {"bytes": nbytes, "nnz": A.nnz, "rows": A.nrows, "reps": reps}
     ref, absum = None, None
