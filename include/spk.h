@@ -155,7 +155,12 @@ typedef struct {
  *   block   threads per workgroup (64..1024, power of two)
  *   group   SpMV VECTOR: lanes per row (2..64); SELL: rows per slice
  *   unroll  independent loads in flight per lane (1, 2, 4 or 8)
- *   vec     vector ops: elements per lane load (1, 2 or 4; at most 16 bytes)
+ *   vec     vector ops: elements per lane load (1, 2 or 4; at most 16 bytes);
+ *           SpMV SCALAR/VECTOR: entries per value/index access (0 = one);
+ *           ADAPTIVE: 2 = two-byte columns (each row-stream block whose
+ *           columns span at most 65,536 reads its columns as offsets from
+ *           its first column, a copy the matrix keeps once made; 0 = the
+ *           CSR's four-byte columns)
  *   grid    vector ops: 0 = one pass, else workgroups per compute unit of a
  *           grid-stride launch (either way at most 2^30 work-items: past
  *           that the kernels loop over the grid, so any n is covered)

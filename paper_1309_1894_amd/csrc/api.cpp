@@ -380,7 +380,8 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
     const int32_t *rp = p.mat ? p.mat->rp : p.csr->row_ptr;
     const int32_t *ci = p.mat ? p.mat->ci : p.csr->col_idx;
     const void *val = p.mat ? p.mat->val : p.csr->val;
-    if (e->vec > 1 && ((uintptr_t)val % ((size_t)e->vec * dtype_size(dtype)) != 0 ||
+    if (e->vec > 1 && e->format != SPK_FMT_ADAPTIVE &&
+        ((uintptr_t)val % ((size_t)e->vec * dtype_size(dtype)) != 0 ||
                        (uintptr_t)ci % ((size_t)e->vec * 4) != 0)) {
         // wider accesses need arrays aligned to their width: one entry at a time
         spk_variant v1 = v;
@@ -398,6 +399,7 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
     if (v.format == SPK_FMT_ADAPTIVE) {
         SPK_TRY(get_blocks(h, p.mat, v.lds, &bd));
         if (v.group > 1) SPK_TRY(get_block_windows(h, p.mat, bd));
+        if (e->vec == 2) SPK_TRY(get_block_c16(h, p.mat, bd));
     }
 
     const int parts = std::max(1, v.streams);
@@ -432,6 +434,8 @@ spk_status run_spmv(spk_handle h, const SpmvProblem &p, const spk_variant &v, hi
                 a.blocks = bd->blk;
                 a.block_k = bd->bk;
                 a.block_x = v.group > 1 ? bd->bx : nullptr;
+                a.c16 = e->vec == 2 ? bd->c16 : nullptr;
+                a.block_c16 = e->vec == 2 ? bd->cbase : nullptr;
                 a.blk0 = (int32_t)lo;
                 a.nblk = (int32_t)(hi - lo);   // one wavefront tile per wavefront
             } else {
@@ -564,6 +568,31 @@ spk_status get_block_windows(spk_handle h, spk_mat *A, BlockData *bd)
     return SPK_OK;
 }
 
+// Two-byte columns of a matrix's row-stream blocks, made on the device when
+// a variant that reads them first needs them (nnz + 8 entries: the kernel
+// reads whole aligned 16-byte groups).
+spk_status get_block_c16(spk_handle h, spk_mat *A, BlockData *bd)
+{
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (bd->cbase) return SPK_OK;
+    uint16_t *c16 = nullptr;
+    int32_t *base = nullptr;
+    const size_t nc = (size_t)std::max<int64_t>(0, A->nnz) + 8;
+    SPK_HIP(hipMalloc(&c16, sizeof(uint16_t) * nc));
+    hipError_t e = hipMalloc(&base, sizeof(int32_t) * (size_t)std::max(1, bd->nblk));
+    if (e == hipSuccess) e = launch_block_c16(bd->blk, bd->bk, A->ci, bd->nblk, c16, base, h->work);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->work);
+    if (e != hipSuccess) {
+        (void)hipFree(c16);
+        if (base) (void)hipFree(base);
+        return hip_fail(e, "two-byte columns");
+    }
+    bd->c16 = c16;
+    bd->cbase = base;
+    A->bytes += (int64_t)(sizeof(uint16_t) * nc + sizeof(int32_t) * (size_t)bd->nblk);
+    return SPK_OK;
+}
+
 // ------------------------------------------------------- column blocks --
 
 // Frees a matrix and everything derived from it.
@@ -582,6 +611,8 @@ static void free_mat(spk_mat *A)
         (void)hipFree(kv.second.blk);
         (void)hipFree(kv.second.bk);
         if (kv.second.bx) (void)hipFree(kv.second.bx);
+        if (kv.second.c16) (void)hipFree(kv.second.c16);
+        if (kv.second.cbase) (void)hipFree(kv.second.cbase);
     }
     if (A->dia.val) (void)hipFree(A->dia.val);
     if (A->dia.mask) (void)hipFree(A->dia.mask);

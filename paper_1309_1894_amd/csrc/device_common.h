@@ -163,6 +163,8 @@ struct SpmvArgs {
     const uint32_t *blocks;
     const int32_t *block_k;
     const int32_t *block_x;   // row-stream blocks' x windows (first column, length; length 0 = none), or null
+    const uint16_t *c16;      // two-byte columns: each row-stream entry's column minus its block's base
+    const int32_t *block_c16; // base (first column) of each block with two-byte columns, -1 = none
     int32_t blk0, nblk;
 };
 

@@ -64,19 +64,23 @@ __device__ __forceinline__ gptr_mut<T> as_global_mut(T *p) { return (gptr_mut<T>
 // wavefront's LDS slice xs with coalesced loads issued together with the
 // entry loads (they do not wait for the column indices), and the gathers
 // read LDS.
-// With C8 (compact columns; needs XW > 0 and 0 < xn <= XW <= 256), ci_
-// points to one byte per entry, the entry's column minus xlo: its place in
-// the window.  The bytes travel in the same 16-byte groups (sixteen entries
-// each instead of four) and through the same LDS staging, so an entry costs
-// 1 byte of index traffic instead of 4; everything else, the order of the
-// arithmetic included, is as with 4-byte columns.
-template <typename T, int ITEMS, bool DOT = false, int XW = 0, bool C8 = false>
+// With CB < 4 (compact columns), ci_ points to CB bytes per entry holding
+// the entry's column minus xlo: with CB = 1 (needs XW > 0 and
+// 0 < xn <= XW <= 256) its place in the window in LDS; with CB = 2 the
+// same, or, when the window is not in LDS (xn = 0), the offset from xlo of
+// the x entry gathered from memory.  The bytes travel in the same 16-byte
+// groups (16/CB entries each instead of four) and through the same LDS
+// staging, so an entry costs CB bytes of index traffic instead of 4;
+// everything else, the order of the arithmetic included, is as with
+// 4-byte columns.
+template <typename T, int ITEMS, bool DOT = false, int XW = 0, int CB = 4>
 __device__ __forceinline__ double wave_stream(const int32_t *rp_, const int32_t *ci_, const T *val_, const T *x_,
                                               T *y_, T *w_, T alpha, int r0, int r1, int k0, int k1, double *sp,
                                               int *srp, int xlo = 0, int xn = 0, T *xs = nullptr)
 {
-    static_assert(!C8 || (XW > 0 && XW <= 256), "compact columns index a window of at most 256 entries");
-    constexpr int IB = C8 ? 1 : 4;            // bytes per stored column
+    static_assert(CB == 4 || CB == 2 || CB == 1, "columns of 4, 2 or 1 bytes");
+    static_assert(CB != 1 || (XW > 0 && XW <= 256), "one-byte columns index a window of at most 256 entries");
+    constexpr int IB = CB;                    // bytes per stored column
     constexpr int GE = 16 / IB;               // entries per 16-byte group
     constexpr int STEPS = (ITEMS * kWave + GE - 1 + GE * kWave - 1) / (GE * kWave);
     static_assert(STEPS * 16 * kWave <= 8 * kWave * ITEMS, "staged index groups must fit the product slice");
@@ -139,14 +143,23 @@ __device__ __forceinline__ double wave_stream(const int32_t *rp_, const int32_t 
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const int q = min(l + j * kWave, klast) + off;
-            if constexpr (C8) c[j] = scb[q];
+            if constexpr (CB == 1) c[j] = scb[q];
+            else if constexpr (CB == 2) c[j] = reinterpret_cast<const uint16_t *>(scb)[q];
             else c[j] = reinterpret_cast<const int *>(scb)[q];
         }
         wave_lds_sync();   // the staged indices are read before products overwrite them
         T xv[ITEMS];
-        if constexpr (C8) {
+        if constexpr (CB == 1) {
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) xv[j] = xs[c[j]];
+        } else if constexpr (CB == 2) {
+            if (win) {
+#pragma unroll
+                for (int j = 0; j < ITEMS; ++j) xv[j] = xs[c[j]];
+            } else {
+#pragma unroll
+                for (int j = 0; j < ITEMS; ++j) xv[j] = x[xlo + c[j]];
+            }
         } else if (win) {
 #pragma unroll
             for (int j = 0; j < ITEMS; ++j) xv[j] = xs[c[j] - xlo];

@@ -106,6 +106,8 @@ struct BlockData {
     uint32_t *blk = nullptr;    // nblk + 1 entries (start row | mode << 30)
     int32_t *bk = nullptr;      // nblk + 1 entries (first entry of each block)
     int32_t *bx = nullptr;      // 2 * nblk: x window of each row-stream block (made when first needed)
+    uint16_t *c16 = nullptr;    // two-byte columns (nnz entries, made when first needed)
+    int32_t *cbase = nullptr;   // nblk: base column of each block's two-byte columns, -1 = none
     int32_t nblk = 0;
     std::vector<uint32_t> host;
     std::vector<int32_t> host_k;
@@ -272,6 +274,7 @@ int64_t format_bytes(const spk_mat *A, int format, bool fused);
 spk_status get_sell(spk_handle h, spk_mat *A, int C, SellData **out);
 spk_status get_blocks(spk_handle h, spk_mat *A, int entries, BlockData **out);
 spk_status get_block_windows(spk_handle h, spk_mat *A, BlockData *bd);
+spk_status get_block_c16(spk_handle h, spk_mat *A, BlockData *bd);
 
 // SPK_FMT_XWIN: kernel entry, validity, run and release.
 const XwinEntry *find_xwin_entry(int block, int window_kib, int entries);

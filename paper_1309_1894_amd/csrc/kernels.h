@@ -84,7 +84,8 @@ using SpmvFn = hipError_t (*)(const void *args, dim3 grid, hipStream_t);
 struct SpmvEntry {
     int format, block, group, unroll, lds;
     SpmvFn fn[2][2];     // [dtype][fused]
-    int vec = 1;         // entries per value/index access (SCALAR, VECTOR): 1, 2 or 4
+    int vec = 1;         // entries per value/index access (SCALAR, VECTOR): 1, 2 or 4; ADAPTIVE: 2 =
+                         // two-byte columns in the row-stream blocks
 };
 
 const SpmvEntry *spmv_table(int *count);
@@ -233,6 +234,13 @@ hipError_t launch_tile_windows(BatchTile *tiles, int64_t ntiles, int cap, hipStr
 // for other blocks and for windows wider than `cap`).
 hipError_t launch_block_windows(const uint32_t *blocks, const int32_t *block_k, const int32_t *ci, int32_t nblk,
                                 int cap, int32_t *bx, hipStream_t s);
+
+// Two-byte columns of the row-block kernel: for each row-stream block with
+// entries whose columns span at most 65,536, base[b] = its smallest column
+// and c16[k] = ci[k] - base[b] over its entries; base[b] = -1 for every
+// other block (c16 is then not written for its entries).
+hipError_t launch_block_c16(const uint32_t *blocks, const int32_t *block_k, const int32_t *ci, int32_t nblk,
+                            uint16_t *c16, int32_t *base, hipStream_t s);
 
 // ------------------------------------------------------ conjugate gradients
 

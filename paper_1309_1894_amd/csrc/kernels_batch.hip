@@ -56,7 +56,7 @@ __device__ __forceinline__ void run_wave_tile(const BatchArgs<T> &a, const Batch
         break;
     case 3:  // mode 1 with compact columns: ci holds each entry's byte offset in the window (which fits)
         if constexpr (XW > 0 && XW <= 256)
-            wave_stream<T, WaveTiles<T, BS, TILE>::ITEMS, false, XW, true>(rp, ci, val, x, y, w, a.alpha, td.r0,
+            wave_stream<T, WaveTiles<T, BS, TILE>::ITEMS, false, XW, 1>(rp, ci, val, x, y, w, a.alpha, td.r0,
                                                                            td.r1, td.k0, td.k1, sp, srp, td.xlo,
                                                                            td.xn, xs);
         break;

@@ -185,8 +185,12 @@ __global__ __launch_bounds__(BS) void k_spmv_sell(SpmvArgs<T> a)
 // wavefront capacity of E entries): each wavefront of a workgroup runs its
 // own block with a private LDS slice, without workgroup barriers.
 // With XW > 0, row-stream blocks whose x window fits XW entries take x from
-// LDS (the window copied there beside the entry loads).
-template <typename T, int BS, int E, int XW, bool FUSED>
+// LDS (the window copied there beside the entry loads).  With CB = 2,
+// row-stream blocks whose columns span at most 65,536 read two-byte column
+// offsets from the block's first column (which is also its window's first
+// column) instead of the CSR's four-byte columns; the other blocks read
+// the CSR's.
+template <typename T, int BS, int E, int XW, int CB, bool FUSED>
 __global__ __launch_bounds__(BS) void k_spmv_adaptive(SpmvArgs<T> a)
 {
     constexpr int NW = BS / kWave;
@@ -209,6 +213,16 @@ __global__ __launch_bounds__(BS) void k_spmv_adaptive(SpmvArgs<T> a)
             xlo = a.block_x[2 * b];
             xn = a.block_x[2 * b + 1];
             xn = xn <= XW ? xn : 0;
+        }
+        if constexpr (CB == 2) {
+            const int base = a.block_c16[b];
+            if (base >= 0) {
+                wave_stream<T, E / kWave, false, XW, 2>(a.rp, reinterpret_cast<const int32_t *>(a.c16), a.val, a.x,
+                                                        a.y, w, a.alpha, r0, r1, a.block_k[b], a.block_k[b + 1],
+                                                        sp + wv * E, srp + wv * (kWaveTileRows + 1), base, xn,
+                                                        xs + wv * (XW > 0 ? XW : 1));
+                return;
+            }
         }
         wave_stream<T, E / kWave, false, XW>(a.rp, a.ci, a.val, a.x, a.y, w, a.alpha, r0, r1, a.block_k[b],
                                              a.block_k[b + 1], sp + wv * E, srp + wv * (kWaveTileRows + 1), xlo, xn,
@@ -256,6 +270,45 @@ hipError_t launch_block_windows(const uint32_t *blocks, const int32_t *block_k, 
     return hipGetLastError();
 }
 
+// Two-byte columns of the row-stream blocks, one wavefront per block: a
+// block with entries whose columns span at most 65,536 gets base = its
+// smallest column and c16[k] = ci[k] - base for its entries; any other
+// block gets base = -1 (and keeps reading the CSR's columns).
+__global__ __launch_bounds__(256) void k_block_c16(const uint32_t *blocks, const int32_t *block_k,
+                                                   const int32_t *ci, int32_t nblk, uint16_t *c16, int32_t *base)
+{
+    const int b = (int)blockIdx.x * 4 + (int)threadIdx.x / kWave;
+    if (b >= nblk) return;
+    const int l = threadIdx.x & (kWave - 1);
+    const int k0 = block_k[b], k1 = block_k[b + 1];
+    const bool stream = (blocks[b] >> 30) == kBlkStream;
+    int lo = INT32_MAX, hi = -1;
+    if (stream)
+        for (int k = k0 + l; k < k1; k += kWave) {
+            const int c = ci[k];
+            lo = min(lo, c);
+            hi = max(hi, c);
+        }
+#pragma unroll
+    for (int d = 1; d < kWave; d *= 2) {
+        lo = min(lo, __shfl_xor(lo, d));
+        hi = max(hi, __shfl_xor(hi, d));
+    }
+    const bool fits = hi >= lo && (int64_t)hi - lo < 65536;
+    if (fits)
+        for (int k = k0 + l; k < k1; k += kWave) c16[k] = (uint16_t)(ci[k] - lo);
+    if (l == 0) base[b] = fits ? lo : -1;
+}
+
+hipError_t launch_block_c16(const uint32_t *blocks, const int32_t *block_k, const int32_t *ci, int32_t nblk,
+                            uint16_t *c16, int32_t *base, hipStream_t s)
+{
+    if (nblk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_block_c16, dim3((unsigned)((nblk + 3) / 4)), dim3(256), 0, s, blocks, block_k, ci, nblk, c16,
+                       base);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ registry --
 
 namespace {
@@ -281,10 +334,10 @@ hipError_t L_sell(const void *p, dim3 g, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename T, int BS, int E, int XW, bool F>
+template <typename T, int BS, int E, int XW, int CB, bool F>
 hipError_t L_adaptive(const void *p, dim3 g, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_spmv_adaptive<T, BS, E, XW, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
+    hipLaunchKernelGGL((k_spmv_adaptive<T, BS, E, XW, CB, F>), g, dim3(BS), 0, s, *(const SpmvArgs<T> *)p);
     return hipGetLastError();
 }
 
@@ -300,8 +353,11 @@ hipError_t L_adaptive(const void *p, dim3 g, hipStream_t s)
 #define SELL(C, U) {3, 256, C, U, 0, FN4(L_sell, 256, C, U)}
 // lds = row-stream entries per wavefront tile; group = LDS room for x per
 // wavefront (1 = none)
-#define ADAPT(BS, E) {4, BS, 1, 1, E, FN4(L_adaptive, BS, E, 0)}
-#define ADAPT_X(BS, E) {4, BS, 256, 1, E, FN4(L_adaptive, BS, E, 256)}
+#define ADAPT(BS, E) {4, BS, 1, 1, E, FN4(L_adaptive, BS, E, 0, 4)}
+#define ADAPT_X(BS, E) {4, BS, 256, 1, E, FN4(L_adaptive, BS, E, 256, 4)}
+// vec = 2: two-byte columns in the row-stream blocks
+#define ADAPT_C16(BS, E) {4, BS, 1, 1, E, FN4(L_adaptive, BS, E, 0, 2), 2}
+#define ADAPT_C16_X(BS, E) {4, BS, 256, 1, E, FN4(L_adaptive, BS, E, 256, 2), 2}
 
 #define VECTOR_U(BS, G) VECTOR(BS, G, 1), VECTOR(BS, G, 2), VECTOR(BS, G, 4)
 #define VECTOR_G(BS) VECTOR_U(BS, 2), VECTOR_U(BS, 4), VECTOR_U(BS, 8), VECTOR_U(BS, 16), \
@@ -333,6 +389,9 @@ const SpmvEntry kSpmv[] = {
     SCALAR_V(256, 2), SCALAR_V(256, 4),
     VECTOR_V(256, 4, 2, 2), VECTOR_V(256, 8, 2, 2), VECTOR_V(256, 16, 2, 2), VECTOR_V(256, 32, 2, 2),
     VECTOR_V(256, 64, 2, 2), VECTOR_V(256, 8, 4, 4), VECTOR_V(256, 16, 4, 4), VECTOR_V(256, 64, 4, 4),
+    // row blocks with two-byte columns
+    ADAPT_C16(64, 256), ADAPT_C16(64, 512), ADAPT_C16(128, 256), ADAPT_C16(256, 256), ADAPT_C16(256, 512),
+    ADAPT_C16_X(256, 256), ADAPT_C16_X(64, 256),
 };
 
 }  // namespace

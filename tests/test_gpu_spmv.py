@@ -352,3 +352,42 @@ def test_row_blocks_with_x_window_equal_plain_row_blocks(spk, dev, dt):
                 assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1]), (bs, e)
         finally:
             M.release()
+
+
+@pytest.mark.parametrize("dt", [1, 0])
+def test_row_blocks_two_byte_columns_equal_four_byte(spk, dev, dt):
+    """The row-block kernel reading two-byte column offsets (vec 2) gives the
+    bits of the same kernel reading the CSR's columns, plain and fused, with
+    and without room for x in LDS: on a banded matrix (every block's window
+    fits the room), a 3-D Laplacian (blocks span one grid plane each way:
+    offsets fit two bytes, windows do not fit the room), and a random-column
+    matrix over 200,000 columns (most blocks span more than 65,536 columns
+    and keep the four-byte columns; a few short ones take offsets)."""
+    cases = (I.banded(20000, 12, 0.6, stream=5), I.lap3d(40),
+             I.zipf(30000, n=200000, kmax=600, seed_struct=61, seed_val=62))
+    for A in cases:
+        A = A.astype(NP[dt])
+        M = spk.Matrix(A)
+        x = I.uniform(43, 0, A.ncols, NP[dt])
+        xd = torch.from_numpy(x).to(dev)
+        say(f"row blocks, two-byte columns: m={A.nrows} n={A.ncols} nnz={A.nnz} dtype={dt}")
+        try:
+            for bs, g, e in ((64, 1, 256), (64, 1, 512), (128, 1, 256), (256, 1, 256), (256, 1, 512),
+                             (256, 256, 256), (64, 256, 256)):
+                outs = []
+                for vec in (0, 2):
+                    v = spk.make_variant(format=spk.SPK_FMT_ADAPTIVE, block=bs, group=g, unroll=1, streams=1, lds=e,
+                                         vec=vec)
+                    y = torch.full((A.nrows,), float("nan"), dtype=M.torch_dtype, device=dev)
+                    if A.nrows == A.ncols:
+                        w = torch.full_like(y, float("nan"))
+                        spk.spk_run(spk.problem(spk.SPK_OP_SPMV_WAXPY, A=M, x=xd, y=y, w=w, alpha=0.5), v)
+                        _check(A, x, y, w, 0.5, dt)
+                    else:   # the fused step needs a square matrix
+                        w = y
+                        spk.spk_run(spk.problem(spk.SPK_OP_SPMV, A=M, x=xd, y=y), v)
+                        _check(A, x, y, None, None, dt)
+                    outs.append((y, w))
+                assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1]), (bs, g, e)
+        finally:
+            M.release()
