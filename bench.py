@@ -685,7 +685,8 @@ def cg_lap3d(spk, torch, I, dev, iters=100):
            "fused_gbs": round(fused_bytes / (fused_us * 1e-6) / 1e9, 1),
            "unfused_gbs_same_bytes": round(fused_bytes / (unfused_us * 1e-6) / 1e9, 1),
            "rr_ratio_end": float(rr[-1] / rr[0]),
-           "tuned_shape": {"block": tune.best.block, "entries": tune.best.lds},
+           "tuned_shape": {"block": tune.best.block, "entries": tune.best.lds,
+                           "two_byte_columns": tune.best.vec == 2},
            "tune_10_iters_us": {"tuned": round(tune.best_us, 1), "default_shape": round(tune.plain_us, 1),
                                 "shapes_timed": tune.tried, "rejected": tune.rejected},
            "matrix_free_stencil": st}

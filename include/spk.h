@@ -482,7 +482,8 @@ spk_status spk_plan_put(spk_handle h, const char *class_key, const spk_variant *
 /* Section 2's search applied to the solve.  The knob is the SpMV+dot
  * kernel: a CSR wavefront-tile shape (threads per workgroup and row-stream
  * entries per wavefront, reported as an SPK_FMT_ADAPTIVE variant with
- * `block` and `lds`), which sets the number of partial sums every workgroup
+ * `block` and `lds`; `vec` 2 = the tiles read two-byte columns, as the
+ * SpMV row-block kernel with vec 2), which sets the number of partial sums every workgroup
  * of the residual kernel adds, so the solve's best shape can differ from a
  * lone SpMV's; or, when A is a grid stencil (spk_matrix_formats), the
  * matrix-free kernel (SPK_FMT_STENCIL, `block` threads, `unroll` rows per

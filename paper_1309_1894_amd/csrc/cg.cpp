@@ -30,12 +30,13 @@ namespace {
 constexpr int kCgDefaultBlock = 512;
 constexpr int kCgDefaultEntries = 512;
 
-const CgEntry *find_cg_entry(int format, int block, int entries, int lds)
+const CgEntry *find_cg_entry(int format, int block, int entries, int lds, int vec = 0)
 {
     int n = 0;
     const CgEntry *t = cg_table(&n);
     for (int i = 0; i < n; ++i)
-        if (t[i].format == format && t[i].block == block && t[i].entries == entries && t[i].lds == lds)
+        if (t[i].format == format && t[i].block == block && t[i].entries == entries && t[i].lds == lds &&
+            t[i].vec == (vec == 2 ? 2 : 0))
             return &t[i];
     return nullptr;
 }
@@ -74,7 +75,7 @@ const CgEntry *cg_entry_for(spk_handle h, spk_mat *A)
         if (it != h->plans.end()) {
             const spk_variant &v = it->second;
             const bool st = v.format == SPK_FMT_STENCIL;
-            const CgEntry *e = find_cg_entry(v.format, v.block, st ? v.unroll : v.lds, st ? v.lds : 0);
+            const CgEntry *e = find_cg_entry(v.format, v.block, st ? v.unroll : v.lds, st ? v.lds : 0, v.vec);
             if (e && cg_entry_fits(A, *e)) return e;
         }
     }
@@ -142,6 +143,11 @@ spk_status run_cg(spk_handle h, spk_mat *A, const CgEntry *e, const double *b, d
         c.blocks = bd->blk;
         c.block_k = bd->bk;
         c.nblk = bd->nblk;
+        if (e->vec == 2) {
+            SPK_TRY(get_block_c16(h, A, bd));
+            c.c16 = bd->c16;
+            c.block_c16 = bd->cbase;
+        }
     }
     CgScratch *cs = nullptr;
     SPK_TRY(cg_scratch(h, s, n, std::max(spmv_grid, grid), &cs));
@@ -335,8 +341,8 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
         SPK_TRY(time_entry(e, &us));
         ++report->tried;
         if (verbose)
-            fprintf(stderr, "spk_cg_tune: format %d block %d entries %d lds %d: %.2f us\n", e->format, e->block,
-                    e->entries, e->lds, us);
+            fprintf(stderr, "spk_cg_tune: format %d block %d entries %d lds %d vec %d: %.2f us\n", e->format,
+                    e->block, e->entries, e->lds, e->vec, us);
         if (e == ref) report->plain_us = us;
         if (us < best_us) {
             best_us = us;
@@ -353,6 +359,7 @@ spk_status spk_cg_tune(spk_handle h, spk_matrix A, const void *b, int32_t iters,
     // matrix-free kernel its rows per lane as `unroll`
     v.unroll = best->format == SPK_FMT_STENCIL ? best->entries : 1;
     v.lds = best->format == SPK_FMT_STENCIL ? best->lds : best->entries;
+    v.vec = best->vec;   // 2: two-byte columns
     report->best = v;
     report->best_us = best_us;
     const std::string key = cg_key(A);

@@ -267,6 +267,8 @@ struct CgLaunch {
     double *part2;             // r.r partials, one per vector workgroup
     double *sc;                // kCgScalars doubles
     double *hist;              // where this launch records r.r
+    const uint16_t *c16;       // two-byte columns of the tiles (entries with vec 2), else null
+    const int32_t *block_c16;  // base column of each tile's two-byte columns, -1 = none
     int32_t slot;              // iteration parity
     int64_t grid;              // workgroups of the vector kernels (slots of part2)
     StencilArgs st;            // stencil form of the matrix (SpMV+dot of a STENCIL entry)
@@ -281,6 +283,7 @@ struct CgEntry {
     int format, block, entries;
     int lds;                   // matrix-free: 1 = p staged through LDS
     CgFn spmv_dot;
+    int vec = 0;               // tiles: 2 = two-byte columns in the row-stream tiles
 };
 
 const CgEntry *cg_table(int *count);

@@ -48,8 +48,10 @@ __device__ __forceinline__ double sum_partials(const double *part, int64_t n, do
 // q = A p over wavefront tiles: wavefront w of workgroup b runs tile w of
 // tile group xcd_remap(b) (runs of neighbouring groups per XCD, so groups in
 // flight on an XCD share their x entries in its L2), and the workgroup
-// leaves its part of p.q at that group's index.
-template <int BS, int E>
+// leaves its part of p.q at that group's index.  With CB = 2 the row-stream
+// tiles that have two-byte columns read those (offsets from the tile's
+// first column) instead of the CSR's.
+template <int BS, int E, int CB>
 __global__ __launch_bounds__(BS) void k_cg_spmv_dot(CgLaunch c)
 {
     constexpr int NW = BS / kWave;
@@ -64,7 +66,13 @@ __global__ __launch_bounds__(BS) void k_cg_spmv_dot(CgLaunch c)
     if (bl < c.nblk) {
         const uint32_t e0 = c.blocks[bl], e1 = c.blocks[bl + 1];
         const int r0 = (int)(e0 & kBlkRowMask), r1 = (int)(e1 & kBlkRowMask);
-        if ((e0 >> 30) == kBlkStream)
+        const int base = CB == 2 ? c.block_c16[bl] : -1;
+        if ((e0 >> 30) == kBlkStream && CB == 2 && base >= 0)
+            d = wave_stream<double, E / kWave, true, 0, 2>(c.rp, reinterpret_cast<const int32_t *>(c.c16), c.val,
+                                                           p, c.q, nullptr, 0.0, r0, r1, c.block_k[bl],
+                                                           c.block_k[bl + 1], sp + wv * E,
+                                                           srp + wv * (kWaveTileRows + 1), base, 0);
+        else if ((e0 >> 30) == kBlkStream)
             d = wave_stream<double, E / kWave, true>(c.rp, c.ci, c.val, p, c.q, nullptr, 0.0, r0, r1,
                                                      c.block_k[bl], c.block_k[bl + 1], sp + wv * E,
                                                      srp + wv * (kWaveTileRows + 1));
@@ -358,10 +366,10 @@ __global__ __launch_bounds__(256) void k_cg_zero(double *hist, int64_t count)
 
 namespace {
 
-template <int BS, int E>
+template <int BS, int E, int CB>
 hipError_t L_spmv_dot(const CgLaunch &c, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_cg_spmv_dot<BS, E>), dim3((unsigned)c.spmv_grid), dim3(BS), 0, s, c);
+    hipLaunchKernelGGL((k_cg_spmv_dot<BS, E, CB>), dim3((unsigned)c.spmv_grid), dim3(BS), 0, s, c);
     return hipGetLastError();
 }
 
@@ -392,11 +400,14 @@ hipError_t L_stencil_lds(const CgLaunch &c, hipStream_t s)
     return hipGetLastError();
 }
 
-#define TILES(BS, E) {4, BS, E, 0, L_spmv_dot<BS, E>}
+#define TILES(BS, E) {4, BS, E, 0, L_spmv_dot<BS, E, 4>}
+#define TILES16(BS, E) {4, BS, E, 0, L_spmv_dot<BS, E, 2>, 2}
 const CgEntry kCg[] = {
     TILES(128, 256), TILES(128, 512), TILES(128, 1024),
     TILES(256, 256), TILES(256, 512), TILES(256, 1024),
     TILES(512, 256), TILES(512, 512), TILES(512, 1024),
+    // two-byte columns
+    TILES16(256, 256), TILES16(256, 512), TILES16(512, 256), TILES16(512, 512),
     // matrix-free: `entries` = rows per lane; lds = p staged through LDS
     {6, 256, 1, 0, L_stencil_dot<256, 1>}, {6, 256, 2, 0, L_stencil_dot<256, 2>},
     {6, 256, 4, 0, L_stencil_dot<256, 4>}, {6, 512, 1, 0, L_stencil_dot<512, 1>},
@@ -405,6 +416,7 @@ const CgEntry kCg[] = {
     {6, 512, 2, 1, L_stencil_lds<512, 2>}, {6, 512, 4, 1, L_stencil_lds<512, 4>},
 };
 #undef TILES
+#undef TILES16
 
 }  // namespace
 

@@ -82,13 +82,19 @@ def test_cg_every_tile_shape(spk, dev):
     try:
         M = spk.Matrix(A, handle=H)
         key = "cg:" + spk.spk_class_key(spk.problem(spk.SPK_OP_SPMV, A=M), handle=H)
-        for bs in (128, 256, 512):
-            for e in (256, 512, 1024):
-                say("cg tile shape", bs, e)
-                v = spk.make_variant(format=spk.SPK_FMT_ADAPTIVE, block=bs, group=1, unroll=1, lds=e, streams=1)
-                spk.spk_plan_put(key, v, handle=H)
-                x, hist = _run(spk, M, b, x0, 8, dev)
-                _compare(x, hist, xo, ho)
+        shapes = [(bs, e, 0) for bs in (128, 256, 512) for e in (256, 512, 1024)]
+        shapes += [(bs, e, 2) for bs in (256, 512) for e in (256, 512)]   # two-byte columns
+        got = {}
+        for bs, e, vec in shapes:
+            say("cg tile shape", bs, e, vec)
+            v = spk.make_variant(format=spk.SPK_FMT_ADAPTIVE, block=bs, group=1, unroll=1, lds=e, streams=1,
+                                 vec=vec)
+            spk.spk_plan_put(key, v, handle=H)
+            x, hist = _run(spk, M, b, x0, 8, dev)
+            _compare(x, hist, xo, ho)
+            got[(bs, e, vec)] = (x, hist)
+            if vec == 2:   # the same arithmetic as the shape's four-byte kernel: the same bits
+                assert np.array_equal(x, got[(bs, e, 0)][0]) and np.array_equal(hist, got[(bs, e, 0)][1])
         M.release()
     finally:
         H.close()
@@ -106,13 +112,13 @@ def test_cg_tune_records_a_validated_shape(spk, dev):
         bd = torch.from_numpy(b).to(dev)
         say("cg tune lap3d 24")
         rep = spk.spk_cg_tune(M, bd, 10, reps=3, warmup=1)
-        # nine tile shapes and ten matrix-free stencil kernels (four of them
-        # staging p through LDS)
-        assert rep.tried == 19 and rep.rejected == 0
+        # nine tile shapes, four more with two-byte columns, and ten
+        # matrix-free stencil kernels (four of them staging p through LDS)
+        assert rep.tried == 23 and rep.rejected == 0
         assert rep.best.format in (spk.SPK_FMT_ADAPTIVE, spk.SPK_FMT_STENCIL)
         assert rep.best_us > 0 and rep.plain_us > 0
         tiles = spk.spk_cg_tune(M, bd, 10, reps=2, warmup=1, record=False, formats=1 << spk.SPK_FMT_ADAPTIVE)
-        assert tiles.tried == 9 and tiles.best.format == spk.SPK_FMT_ADAPTIVE
+        assert tiles.tried == 13 and tiles.best.format == spk.SPK_FMT_ADAPTIVE
         key = "cg:" + spk.spk_class_key(spk.problem(spk.SPK_OP_SPMV, A=M), handle=H)
         assert rep.class_key.decode() == key
         got = spk.spk_plan_get(key, handle=H)
