@@ -25,7 +25,7 @@ namespace spk {
 // kXwinMaxRb whose blocks all fit the staging area: the larger the block,
 // the longer its runs, and the fewer 128-byte lines two blocks share.
 constexpr int64_t kXwinStage = 7168;      // FP64 partials staged per block (56 KiB of LDS)
-constexpr int64_t kXwinMaxRb = 1024;      // rows per block at most (four per thread)
+constexpr int64_t kXwinMaxRb = 1024;      // rows per block at most (one per thread of the adding pass)
 constexpr int64_t kXwinMaxWin = 1023;     // windows one matrix may have
 constexpr int64_t kXwinMaxTable = (int64_t)1 << 26;   // block table entries
 
