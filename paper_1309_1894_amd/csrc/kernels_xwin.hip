@@ -76,15 +76,14 @@ __device__ __forceinline__ void window_stream(const XwinArgs &a, const T *win, c
     const gptr_mut<double> part = as_global_mut(a.part);
     const int l = threadIdx.x & (kWave - 1);
     const int np = tl.p1 - tl.p0;
-    const int nk = tl.k1 - tl.k0;
+    // stores without branches where the slice has room: products of lanes
+    // past the tile's end (loaded from the clamped last entry) and pair
+    // starts past np land in slots no pair sum reads
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const int k = l + j * kWave;
-        if (k < nk) sp[k] = (double)tl.v[j] * (double)win[tl.c[j]];
-    }
+    for (int j = 0; j < ITEMS; ++j) sp[l + j * kWave] = (double)tl.v[j] * (double)win[tl.c[j]];
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
-        if (l + q * kWave <= np) srp[l + q * kWave] = tl.rpv[q] - tl.k0;
+    for (int q = 0; q < 2; ++q) srp[l + q * kWave] = tl.rpv[q] - tl.k0;
+    if (l + 2 * kWave <= np) srp[l + 2 * kWave] = tl.rpv[2] - tl.k0;
     wave_lds_sync();
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
