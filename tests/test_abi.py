@@ -60,6 +60,7 @@ def test_null_handle_rejected_before_hip(lib):
     assert L.spk_cg(None, None, None, None, 0, None, None) == 1
     assert L.spk_destroy(None) == 1
     assert L.spk_batch_free(None, None) == 1
+    assert L.spk_batch_tile_modes(None, None, None, None) == 1
     assert L.spk_serve_destroy(None) == 1
     assert b"NULL" in L.spk_last_error()
 
