@@ -550,8 +550,10 @@ typedef struct {
  * first.  The descriptor arrays are copied; the device arrays are borrowed
  * for the batch's lifetime.  Classes planned with compact columns (mode 3)
  * read a one-byte copy of their column indices (each entry's place in its
- * tile's window of x) that the plan makes from col_idx and owns: col_idx
- * must not change while the plan lives.  Each instance's row_ptr is checked (starts at
+ * tile's window of x; two bytes, the offset from the tile's first column,
+ * for tiles whose window is wider than the kernel's room for x) that the
+ * plan makes from col_idx and owns: col_idx must not change while the plan
+ * lives.  Each instance's row_ptr is checked (starts at
  * 0, never decreases, ends at nnz: SPK_ERR_CSR otherwise); column indices
  * are not (as in spk_spmv_csr, one outside [0, m_i) reads outside the
  * instance's x).  A batch runs as one launch of at most 2^24
@@ -606,9 +608,11 @@ spk_status spk_batch_info(spk_handle h, spk_batch b, int64_t *tiles, int32_t *cl
 
 /* Tiles and matrix entries per kernel mode as planned on the device (after
  * the x windows are found, so a mode-3 tile whose window did not fit counts
- * as mode 1): tiles[mode] and entries[mode] for mode 0..64 (host arrays of
- * 65; entries nullable; 0 = LDS row stream, 1 = with the tile's window of x
- * in LDS, 3 = the same with compact columns, G = G lanes per row).
+ * as mode 5 or 1): tiles[mode] and entries[mode] for mode 0..64 (host
+ * arrays of 65; entries nullable; 0 = LDS row stream, 1 = with the tile's
+ * window of x in LDS, 3 = the same with one-byte compact columns, 5 = the
+ * row stream with two-byte compact columns and x from memory, G = G lanes
+ * per row).
  * Synchronises with the device.  Library plumbing, not in the paper. */
 spk_status spk_batch_tile_modes(spk_handle h, spk_batch b, int64_t *tiles, int64_t *entries);
 

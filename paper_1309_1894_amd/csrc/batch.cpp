@@ -45,7 +45,9 @@ struct spk_batch_s {
     std::vector<spk::BatchTile> tiles;
     spk::BatchTile *d_tiles = nullptr;
     int64_t d_tiles_cap = 0;
-    uint8_t *c8 = nullptr;                // compact columns of mode-3 tiles (laid out like the caller's col_idx)
+    uint8_t *c8 = nullptr;                // one-byte compact columns (laid out like the caller's col_idx)
+    uint16_t *c16 = nullptr;              // two-byte compact columns (the same layout), made when needed
+    int *d_need16 = nullptr;              // tiles that would take two-byte columns, while c16 is absent
     int64_t c8_len = 0;
     int64_t grid_persistent = 0;
     std::mutex mu;                        // guards `streams`
@@ -254,27 +256,43 @@ spk_status upload_tiles(spk_batch b, const std::vector<BatchTile> &tiles)
         SPK_HIP(hipMalloc(&b->d_tiles, sizeof(BatchTile) * cap));
         b->d_tiles_cap = cap;
     }
-    // the compact-column array of mode-3 tiles, sized like the caller's
+    // the compact-column arrays of mode-3 tiles, sized like the caller's
     // col_idx span plus one 16-byte group (the kernel reads whole aligned
-    // groups), allocated at the first plan that has such tiles
+    // groups): one byte per entry at the first plan that has such tiles,
+    // two bytes per entry once a tile needs them (a tile whose window is
+    // wider than the kernel's room)
     bool any3 = false;
     for (const BatchTile &t : tiles) any3 = any3 || t.mode == 3;
+    int64_t len = 0;
+    for (int64_t i = 0; i < b->count; ++i) len = std::max<int64_t>(len, b->nz_off[i] + b->nnz[i]);
+    len = (len + 15) / 16 * 16 + 16;
     if (any3 && !b->c8) {
-        int64_t len = 0;
-        for (int64_t i = 0; i < b->count; ++i) len = std::max<int64_t>(len, b->nz_off[i] + b->nnz[i]);
-        len = (len + 15) / 16 * 16 + 16;
         SPK_HIP(hipMalloc(&b->c8, (size_t)len));
+        SPK_HIP(hipMalloc(&b->d_need16, sizeof(int)));
         b->c8_len = len;
     }
-    // ordered after any launch already queued on the work stream that reads the old tiles
-    if (!tiles.empty()) {
+    if (tiles.empty()) return SPK_OK;
+    // the x windows of mode-1 and mode-3 tiles, for a kernel with room for
+    // them; mode-3 tiles get their compact columns.  Ordered after any
+    // launch already queued on the work stream that reads the old tiles.
+    auto place = [&]() -> spk_status {
         SPK_HIP(hipMemcpyAsync(b->d_tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice,
                                b->h->work));
-        // the x windows of mode-1 and mode-3 tiles, for a kernel with room
-        // for them; mode-3 tiles get their compact columns
+        if (b->d_need16) SPK_HIP(hipMemsetAsync(b->d_need16, 0, sizeof(int), b->h->work));
         if (b->entry->xw > 0)
-            SPK_HIP(launch_tile_windows(b->d_tiles, (int64_t)tiles.size(), b->entry->xw, b->h->work, b->ci, b->c8));
+            SPK_HIP(launch_tile_windows(b->d_tiles, (int64_t)tiles.size(), b->entry->xw, b->h->work, b->ci, b->c8,
+                                        b->c16, b->d_need16));
         SPK_HIP(hipStreamSynchronize(b->h->work));
+        return SPK_OK;
+    };
+    SPK_TRY(place());
+    if (any3 && !b->c16 && b->entry->xw > 0) {
+        int need = 0;
+        SPK_HIP(hipMemcpy(&need, b->d_need16, sizeof(int), hipMemcpyDeviceToHost));
+        if (need > 0) {
+            SPK_HIP(hipMalloc(&b->c16, sizeof(uint16_t) * (size_t)len));
+            SPK_TRY(place());
+        }
     }
     return SPK_OK;
 }
@@ -880,6 +898,8 @@ spk_status spk_batch_free(spk_handle h, spk_batch b)
     invalidate_graph(b);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->c8) (void)hipFree(b->c8);
+    if (b->c16) (void)hipFree(b->c16);
+    if (b->d_need16) (void)hipFree(b->d_need16);
     for (auto &kv : b->streams)
         if (kv.second.ctr) (void)hipFree(kv.second.ctr);
     delete b;

@@ -14,7 +14,9 @@ namespace spk {
 // from memory as in mode 0), 3 = mode 1 with compact columns (once the
 // window is found and fits, ci points to one byte per entry, the entry's
 // column minus xlo, written by the planner; a tile whose window does not
-// fit is turned into a mode-1 tile), G in {2, 4, ..., 64} = G lanes per
+// fit becomes a mode-5 tile when its columns span at most 65,536 -- ci
+// then points to two-byte offsets from xlo and x is gathered from memory
+// -- else a mode-1 tile), G in {2, 4, ..., 64} = G lanes per
 // row straight from memory.  The tile carries its matrix's arrays and the
 // offset of the matrix's vectors inside the launch's x / y / w, so a
 // wavefront needs one 64-byte descriptor load before it can start

@@ -221,13 +221,16 @@ inline int batch_wave_entries(const BatchEntry &e) { return e.tile / (e.block / 
 // The x windows of mode-1 and mode-3 tiles: for each such tile with
 // entries, the smallest and largest column of its entries; the window is
 // recorded (xlo, xn) when it spans at most `cap` columns, else xn = 0.
-// Mode-3 tiles (compact columns) need a window that fits and cap <= 256:
-// each such tile writes its entries' offsets in the window, one byte each,
-// to c8 at the place its column array ci0 + d has (c8 + d), and points its
-// ci there; a mode-3 tile without a fitting window (or with c8 NULL)
-// becomes a mode-1 tile.  One wavefront per tile.
+// Mode-3 tiles (compact columns): one whose window fits (cap <= 256)
+// writes its entries' offsets in the window, one byte each, to c8 at the
+// place its column array ci0 + d has (c8 + d), and points its ci there;
+// one whose columns span at most 65,536 writes two-byte offsets from its
+// first column (xlo) to c16 the same way and becomes a mode-5 tile, or,
+// with c16 NULL, adds 1 to *need16 (when not NULL) and becomes a mode-1
+// tile; any other becomes a mode-1 tile.  One wavefront per tile.
 hipError_t launch_tile_windows(BatchTile *tiles, int64_t ntiles, int cap, hipStream_t s,
-                               const int32_t *ci0 = nullptr, uint8_t *c8 = nullptr);
+                               const int32_t *ci0 = nullptr, uint8_t *c8 = nullptr, uint16_t *c16 = nullptr,
+                               int *need16 = nullptr);
 
 // The same for the row-stream blocks of the single-matrix row-block kernel:
 // bx[2b], bx[2b+1] = first column and length of block b's window (length 0

@@ -60,6 +60,10 @@ __device__ __forceinline__ void run_wave_tile(const BatchArgs<T> &a, const Batch
                                                                            td.r1, td.k0, td.k1, sp, srp, td.xlo,
                                                                            td.xn, xs);
         break;
+    case 5:  // compact columns of a wider tile: two-byte offsets from xlo, x gathered from memory
+        wave_stream<T, WaveTiles<T, BS, TILE>::ITEMS, false, XW, 2>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1,
+                                                                       td.k0, td.k1, sp, srp, td.xlo, 0, xs);
+        break;
     case 2: wave_group_rows<T, 2>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
     case 4: wave_group_rows<T, 4>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
     case 8: wave_group_rows<T, 8>(rp, ci, val, x, y, w, a.alpha, td.r0, td.r1); break;
@@ -162,10 +166,12 @@ __global__ __launch_bounds__(BS) void k_batch_persistent(BatchArgs<T> a)
 // wavefront per tile.  A mode-3 tile whose window fits writes its entries'
 // offsets in the window to c8 (at the entries' own positions: instance
 // arrays at ci + d map to c8 + d) and takes c8 as its column array; one
-// whose window does not fit becomes a mode-1 tile that gathers x from
-// memory.
+// whose columns span at most 65,536 does the same with two-byte offsets
+// from its first column in c16 and becomes a mode-5 tile (x gathered from
+// memory), or, while c16 is NULL, counts itself in *need16 and becomes a
+// mode-1 tile; any other becomes a mode-1 tile.
 __global__ __launch_bounds__(256) void k_tile_windows(BatchTile *tiles, int64_t ntiles, int cap, const int32_t *ci0,
-                                                      uint8_t *c8)
+                                                      uint8_t *c8, uint16_t *c16, int *need16)
 {
     const int64_t t = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
     if (t >= ntiles) return;
@@ -187,16 +193,23 @@ __global__ __launch_bounds__(256) void k_tile_windows(BatchTile *tiles, int64_t 
         hi = max(hi, __shfl_xor(hi, d));
     }
     const bool fits = hi >= lo && (int64_t)hi - lo + 1 <= cap;
-    const bool compact = mode == 3 && fits && cap <= 256 && c8 != nullptr;
-    uint8_t *cb = compact ? c8 + (ci - ci0) : nullptr;
-    if (compact)
+    const bool span16 = hi >= lo && (int64_t)hi - lo < 65536;
+    const bool one = mode == 3 && fits && cap <= 256 && c8 != nullptr;
+    const bool two = mode == 3 && !one && span16 && c16 != nullptr;
+    uint8_t *cb = one ? c8 + (ci - ci0) : nullptr;
+    uint16_t *cw = two ? c16 + (ci - ci0) : nullptr;
+    if (one)
         for (int k = k0 + l; k < k1; k += kWave) cb[k] = (uint8_t)(ci[k] - lo);
+    if (two)
+        for (int k = k0 + l; k < k1; k += kWave) cw[k] = (uint16_t)(ci[k] - lo);
     if (l == 0) {
-        td.xlo = fits ? lo : 0;
-        td.xn = fits ? hi - lo + 1 : 0;
+        td.xlo = fits || two ? lo : 0;
+        td.xn = fits && !two ? hi - lo + 1 : 0;
         if (mode == 3) {
-            td.mode = compact ? 3 : 1;
-            if (compact) td.ci = reinterpret_cast<const int32_t *>(cb);
+            td.mode = one ? 3 : two ? 5 : 1;
+            if (one) td.ci = reinterpret_cast<const int32_t *>(cb);
+            if (two) td.ci = reinterpret_cast<const int32_t *>(cw);
+            if (!one && !two && span16 && c16 == nullptr && need16 != nullptr) atomicAdd(need16, 1);
         }
     }
 }
@@ -249,11 +262,11 @@ const BatchEntry *batch_table(int *count)
 }
 
 hipError_t launch_tile_windows(BatchTile *tiles, int64_t ntiles, int cap, hipStream_t s, const int32_t *ci0,
-                               uint8_t *c8)
+                               uint8_t *c8, uint16_t *c16, int *need16)
 {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_tile_windows, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, tiles, ntiles, cap, ci0,
-                       c8);
+                       c8, c16, need16);
     return hipGetLastError();
 }
 

@@ -87,12 +87,14 @@ __global__ __launch_bounds__(kBS) void k_tiles_absum(const BatchTile *tiles, con
     const BatchTile td = tiles[blockIdx.x];
     const T *val = (const T *)td.val;
     const T *xi = x + td.vec_off;
-    // mode-3 tiles hold each entry's column as a byte offset from xlo
+    // mode-3 and mode-5 tiles hold each entry's column as a one- or
+    // two-byte offset from xlo
     const uint8_t *c8 = td.mode == 3 ? reinterpret_cast<const uint8_t *>(td.ci) : nullptr;
+    const uint16_t *c16 = td.mode == 5 ? reinterpret_cast<const uint16_t *>(td.ci) : nullptr;
     for (int r = td.r0 + (int)threadIdx.x; r < td.r1; r += kBS) {
         double s = 0.0;
         for (int k = td.rp[r]; k < td.rp[r + 1]; ++k) {
-            const int c = c8 ? td.xlo + c8[k] : td.ci[k];
+            const int c = c8 ? td.xlo + c8[k] : c16 ? td.xlo + c16[k] : td.ci[k];
             s += __builtin_fabs((double)val[k] * (double)xi[c]);
         }
         scale[td.vec_off + r] = s;

@@ -313,8 +313,9 @@ def test_batch_x_window_mode(spk, dev, dt):
             modes = b.tile_modes()
             say(f"  tiles per mode: {modes}")
             if mode == 3:
-                # windows that fit take compact columns; the Zipf instance's do not
-                assert modes.get(3, 0) > 0 and modes.get(1, 0) > 0
+                # windows that fit take one-byte columns; the Zipf instance's
+                # wider ones (3,000 columns) two-byte columns (mode 5)
+                assert modes.get(3, 0) > 0 and modes.get(5, 0) > 0
             b.run(0.5, xd, y, w)
             torch.cuda.synchronize()
             _check_batch(B, x, y, w, 0.5, dt)
@@ -324,6 +325,48 @@ def test_batch_x_window_mode(spk, dev, dt):
             h.close()
     for mode in (1, 3):
         assert torch.equal(outs[0][0], outs[mode][0]) and torch.equal(outs[0][1], outs[mode][1]), mode
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_batch_compact_columns_one_two_four_bytes(spk, dev, dt):
+    """A batch planned to compact columns (mode 3) whose tiles take all three
+    column widths: banded instances one byte (windows within the kernel's
+    room), a 3,000-column Zipf instance two bytes (mode 5: wider windows,
+    spans under 65,536), an 80,000-column Zipf instance four (mode 1: its
+    tiles span more than 65,536 columns).  Every instance against the
+    oracle, and the bits of the plain row stream (mode 0) on the same batch."""
+    insts = [I.banded(int(m), int(b), 0.6, seed_struct=13, seed_val=14, stream=i, dtype=dt)
+             for i, (m, b) in enumerate(((3000, 5), (700, 32), (12000, 1)))]
+    insts.append(I.zipf(3000, n=3000, kmax=300, seed_struct=15, seed_val=16, dtype=dt))
+    insts.append(I.zipf(80000, n=80000, kmax=64, seed_struct=17, seed_val=18, dtype=dt))
+    B = I.batch_from_instances(insts)
+    x = I.batch_vector(B, seed=23, dtype=dt)
+    arrs = _dev_batch(B, dev)
+    xd = torch.from_numpy(x).to(dev)
+    outs = {}
+    dname = "f64" if dt == np.float64 else "f32"
+    for mode in (0, 3):
+        h = spk.Handle(0)
+        for c in range(21):
+            spk.spk_plan_put(f"batch:{dname}:c{c}",
+                             spk.make_variant(format=spk.SPK_FMT_ADAPTIVE, block=256, group=mode, unroll=1,
+                                              streams=1, lds=2048), handle=h)
+        b = spk.Batch(B, arrs, handle=h, block=256, x_window=256)
+        try:
+            modes = b.tile_modes()
+            say(f"compact columns, mode {mode}, dtype={dname}: tiles per mode {modes}")
+            if mode == 3:
+                assert modes.get(3, 0) > 0 and modes.get(5, 0) > 0 and modes.get(1, 0) > 0
+            y = torch.full((x.size,), float("nan"), dtype=xd.dtype, device=dev)
+            w = torch.full_like(y, float("nan"))
+            b.run(0.5, xd, y, w)
+            torch.cuda.synchronize()
+            _check_batch(B, x, y, w, 0.5, dt)
+            outs[mode] = (y.clone(), w.clone())
+        finally:
+            b.free()
+            h.close()
+    assert torch.equal(outs[0][0], outs[3][0]) and torch.equal(outs[0][1], outs[3][1])
 
 
 def test_batch_tune_resume(spk, dev, tmp_path):
