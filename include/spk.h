@@ -581,8 +581,9 @@ spk_status spk_batch_run(spk_handle h, spk_batch b, double alpha, const void *x,
  * the whole batch, then the tile kernel of each shape class under it (LDS
  * row stream, the same with the tile's x window staged in LDS when the
  * kernel has room for it, the same again with compact columns -- one byte
- * per entry, its offset in the window, instead of four: a storage-format
- * choice of the tuner, not a knob the paper lists -- or G lanes per row),
+ * per entry, its offset in the window, instead of four, or two bytes for
+ * tiles whose window is wider than the room: a storage-format choice of
+ * the tuner, not a knob the paper lists -- or G lanes per row),
  * then the launch shape again
  * with the tuned kernels.  Every candidate is validated before it is timed
  * against the unannotated program's output: the plain kernel (one lane per
