@@ -407,7 +407,8 @@ const CgEntry kCg[] = {
     TILES(256, 256), TILES(256, 512), TILES(256, 1024),
     TILES(512, 256), TILES(512, 512), TILES(512, 1024),
     // two-byte columns
-    TILES16(256, 256), TILES16(256, 512), TILES16(512, 256), TILES16(512, 512),
+    TILES16(256, 256), TILES16(256, 512), TILES16(512, 256), TILES16(512, 512), TILES16(512, 1024),
+    TILES16(256, 1024),
     // matrix-free: `entries` = rows per lane; lds = p staged through LDS
     {6, 256, 1, 0, L_stencil_dot<256, 1>}, {6, 256, 2, 0, L_stencil_dot<256, 2>},
     {6, 256, 4, 0, L_stencil_dot<256, 4>}, {6, 512, 1, 0, L_stencil_dot<512, 1>},

@@ -390,7 +390,8 @@ const SpmvEntry kSpmv[] = {
     VECTOR_V(256, 4, 2, 2), VECTOR_V(256, 8, 2, 2), VECTOR_V(256, 16, 2, 2), VECTOR_V(256, 32, 2, 2),
     VECTOR_V(256, 64, 2, 2), VECTOR_V(256, 8, 4, 4), VECTOR_V(256, 16, 4, 4), VECTOR_V(256, 64, 4, 4),
     // row blocks with two-byte columns
-    ADAPT_C16(64, 256), ADAPT_C16(64, 512), ADAPT_C16(128, 256), ADAPT_C16(256, 256), ADAPT_C16(256, 512),
+    ADAPT_C16(64, 256), ADAPT_C16(64, 512), ADAPT_C16(64, 1024), ADAPT_C16(128, 256), ADAPT_C16(128, 512),
+    ADAPT_C16(256, 256), ADAPT_C16(256, 512), ADAPT_C16(512, 256),
     ADAPT_C16_X(256, 256), ADAPT_C16_X(64, 256),
 };
 

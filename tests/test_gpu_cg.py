@@ -83,7 +83,7 @@ def test_cg_every_tile_shape(spk, dev):
         M = spk.Matrix(A, handle=H)
         key = "cg:" + spk.spk_class_key(spk.problem(spk.SPK_OP_SPMV, A=M), handle=H)
         shapes = [(bs, e, 0) for bs in (128, 256, 512) for e in (256, 512, 1024)]
-        shapes += [(bs, e, 2) for bs in (256, 512) for e in (256, 512)]   # two-byte columns
+        shapes += [(bs, e, 2) for bs in (256, 512) for e in (256, 512, 1024)]   # two-byte columns
         got = {}
         for bs, e, vec in shapes:
             say("cg tile shape", bs, e, vec)
@@ -112,13 +112,13 @@ def test_cg_tune_records_a_validated_shape(spk, dev):
         bd = torch.from_numpy(b).to(dev)
         say("cg tune lap3d 24")
         rep = spk.spk_cg_tune(M, bd, 10, reps=3, warmup=1)
-        # nine tile shapes, four more with two-byte columns, and ten
+        # nine tile shapes, six more with two-byte columns, and ten
         # matrix-free stencil kernels (four of them staging p through LDS)
-        assert rep.tried == 23 and rep.rejected == 0
+        assert rep.tried == 25 and rep.rejected == 0
         assert rep.best.format in (spk.SPK_FMT_ADAPTIVE, spk.SPK_FMT_STENCIL)
         assert rep.best_us > 0 and rep.plain_us > 0
         tiles = spk.spk_cg_tune(M, bd, 10, reps=2, warmup=1, record=False, formats=1 << spk.SPK_FMT_ADAPTIVE)
-        assert tiles.tried == 13 and tiles.best.format == spk.SPK_FMT_ADAPTIVE
+        assert tiles.tried == 15 and tiles.best.format == spk.SPK_FMT_ADAPTIVE
         key = "cg:" + spk.spk_class_key(spk.problem(spk.SPK_OP_SPMV, A=M), handle=H)
         assert rep.class_key.decode() == key
         got = spk.spk_plan_get(key, handle=H)

@@ -372,8 +372,8 @@ def test_row_blocks_two_byte_columns_equal_four_byte(spk, dev, dt):
         xd = torch.from_numpy(x).to(dev)
         say(f"row blocks, two-byte columns: m={A.nrows} n={A.ncols} nnz={A.nnz} dtype={dt}")
         try:
-            for bs, g, e in ((64, 1, 256), (64, 1, 512), (128, 1, 256), (256, 1, 256), (256, 1, 512),
-                             (256, 256, 256), (64, 256, 256)):
+            for bs, g, e in ((64, 1, 256), (64, 1, 512), (64, 1, 1024), (128, 1, 256), (128, 1, 512),
+                             (256, 1, 256), (256, 1, 512), (512, 1, 256), (256, 256, 256), (64, 256, 256)):
                 outs = []
                 for vec in (0, 2):
                     v = spk.make_variant(format=spk.SPK_FMT_ADAPTIVE, block=bs, group=g, unroll=1, streams=1, lds=e,
