@@ -232,3 +232,38 @@ def test_serve_one_launch_in_flight_batches_arrivals(spk, dev):
         srv.close()
     for i in range(nreq):
         _check(pool[mats[i]], xs[i], ys[i], ws[i])
+
+
+def test_serve_classes_planned_to_compact_columns(spk, dev):
+    """Serving keeps four-byte columns: a class whose recorded batch plan is
+    compact columns (mode 3) is served with the same tiles run as mode 1
+    (x window in LDS) -- every request against the oracle and equal bit
+    for bit to the same request under a plan of mode 1."""
+    pool = pool_mats()
+    nreq = 60
+    mats = (I.u64(73, 0, 0, nreq) % np.uint64(len(pool))).astype(int)
+    xs = [I.uniform(74, i, pool[m].ncols, pool[m].val.dtype) for i, m in enumerate(mats)]
+    outs = {}
+    for mode in (3, 1):
+        H = spk.Handle(0)
+        for dn in ("f64", "f32"):
+            for c in range(21):
+                spk.spk_plan_put(f"batch:{dn}:c{c}",
+                                 spk.make_variant(format=spk.SPK_FMT_ADAPTIVE, block=256, group=mode, unroll=1,
+                                                  streams=1, lds=2048), handle=H)
+        ys = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
+        ws = [np.empty(pool[m].nrows, pool[m].val.dtype) for m in mats]
+        say(f"serve with classes planned to mode {mode}: {nreq} requests")
+        srv = spk.Server(streams=2, max_inflight=32, max_batch=8, mode=0, alpha=0.5, handle=H)
+        try:
+            ids = [srv.add_matrix(A) for A in pool]
+            srv.replay(I.poisson_arrivals(nreq, 20000.0, seed=75), [ids[m] for m in mats], xs, ys, ws)
+            st = srv.stats()
+            assert st["completed"] == nreq and st["rejected"] == 0
+        finally:
+            srv.close()
+            H.close()
+        outs[mode] = (ys, ws)
+    for i in range(nreq):
+        _check(pool[mats[i]], xs[i], outs[3][0][i], outs[3][1][i])
+        assert np.array_equal(outs[3][0][i], outs[1][0][i]) and np.array_equal(outs[3][1][i], outs[1][1][i]), i
