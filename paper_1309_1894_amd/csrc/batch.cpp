@@ -48,7 +48,6 @@ struct spk_batch_s {
     uint8_t *c8 = nullptr;                // one-byte compact columns (laid out like the caller's col_idx)
     uint16_t *c16 = nullptr;              // two-byte compact columns (the same layout), made when needed
     int *d_need16 = nullptr;              // tiles that would take two-byte columns, while c16 is absent
-    int64_t c8_len = 0;
     int64_t grid_persistent = 0;
     std::mutex mu;                        // guards `streams`
     std::map<hipStream_t, BatchStream> streams;
@@ -269,7 +268,6 @@ spk_status upload_tiles(spk_batch b, const std::vector<BatchTile> &tiles)
     if (any3 && !b->c8) {
         SPK_HIP(hipMalloc(&b->c8, (size_t)len));
         SPK_HIP(hipMalloc(&b->d_need16, sizeof(int)));
-        b->c8_len = len;
     }
     if (tiles.empty()) return SPK_OK;
     // the x windows of mode-1 and mode-3 tiles, for a kernel with room for
