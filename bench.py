@@ -7,9 +7,11 @@ CSR instances (row counts log-uniform in [64, 16384), half-bandwidth 1..32,
 60% fill inside the band), all instances in one hipGraph-replayed launch of
 the tile kernel, autotuned per shape class (the tuner picks the launch kind:
 one workgroup per tile group, or a persistent grid pulling tiles from
-per-XCD queues).  Bytes are the
-algorithmic ones: every array once (values, column indices, row pointers, x,
-y, w), no re-reads, no padding.
+per-XCD queues; and per class the tile kernel, compact one-byte columns
+among them).  Bytes are the algorithmic ones of the CSR statement: every
+array once (values, 4-byte column indices, row pointers, x, y, w), no
+re-reads, no padding; the bytes the tuned plan's own form moves (fewer,
+with compact columns) are reported beside them (``roofline.form_*``).
 
 Also reported on the same JSON line: the plain (untuned) kernels on the same
 batch (two launches over the batch as one block-diagonal matrix, and one
