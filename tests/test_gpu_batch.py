@@ -419,3 +419,58 @@ def test_batch_tune_resume(spk, dev, tmp_path):
     assert points() == k + first.tried
     assert second.tried == 0 and second.resumed == first.resumed + first.tried
     assert second.best_us == first.best_us
+
+
+def _diag_plus(m, extra, dt, seed):
+    """m x m diagonal plus `extra` (row, col) entries, values seeded uniform."""
+    rows = np.concatenate([np.arange(m), np.array([r for r, _ in extra], np.int64)])
+    cols = np.concatenate([np.arange(m), np.array([c for _, c in extra], np.int64)])
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    rp = np.zeros(m + 1, np.int64)
+    np.add.at(rp, rows + 1, 1)
+    val = I.uniform(seed, 0, rows.size, dt)
+    return I.CSR(m, m, np.cumsum(rp).astype(np.int32), cols.astype(np.int32), val)
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_batch_compact_columns_width_boundaries(spk, dev, dt):
+    """The compact encodings at their limits: a first tile whose window is
+    exactly the kernel's room of 256 columns (one-byte offsets up to 255),
+    one whose columns span exactly 65,536 (two-byte offsets up to 65,535)
+    and one spanning 65,537 (four-byte columns).  Each instance's first
+    tile (its first 128 rows) holds the wide entries, the rest are diagonal
+    tiles; against the oracle and bit-equal to the plain row stream."""
+    insts = [_diag_plus(256, [(0, 255), (99, 0)], dt, 31),          # window 0..255
+             _diag_plus(70000, [(0, 65535), (50, 0)], dt, 32),       # span 65,536
+             _diag_plus(70000, [(0, 65536), (50, 0)], dt, 33)]       # span 65,537
+    B = I.batch_from_instances(insts)
+    x = I.batch_vector(B, seed=24, dtype=dt)
+    arrs = _dev_batch(B, dev)
+    xd = torch.from_numpy(x).to(dev)
+    dname = "f64" if dt == np.float64 else "f32"
+    outs = {}
+    for mode in (0, 3):
+        h = spk.Handle(0)
+        for c in range(21):
+            spk.spk_plan_put(f"batch:{dname}:c{c}",
+                             spk.make_variant(format=spk.SPK_FMT_ADAPTIVE, block=256, group=mode, unroll=1,
+                                              streams=1, lds=2048), handle=h)
+        b = spk.Batch(B, arrs, handle=h, block=256, x_window=256)
+        try:
+            modes = b.tile_modes()
+            say(f"compact width boundaries, mode {mode}, dtype={dname}: tiles per mode {modes}")
+            if mode == 3:
+                # the 256-column window and the diagonal tiles take one byte,
+                # the 65,536-column span two, the 65,537-column span four
+                assert modes.get(3, 0) > 0 and modes.get(5, 0) == 1 and modes.get(1, 0) == 1
+            y = torch.full((x.size,), float("nan"), dtype=xd.dtype, device=dev)
+            w = torch.full_like(y, float("nan"))
+            b.run(0.5, xd, y, w)
+            torch.cuda.synchronize()
+            _check_batch(B, x, y, w, 0.5, dt)
+            outs[mode] = (y.clone(), w.clone())
+        finally:
+            b.free()
+            h.close()
+    assert torch.equal(outs[0][0], outs[3][0]) and torch.equal(outs[0][1], outs[3][1])

@@ -391,3 +391,33 @@ def test_row_blocks_two_byte_columns_equal_four_byte(spk, dev, dt):
                 assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1]), (bs, g, e)
         finally:
             M.release()
+
+
+@pytest.mark.parametrize("dt", [1, 0])
+def test_row_blocks_two_byte_columns_at_the_width_limit(spk, dev, dt):
+    """Two-byte row-block columns at their limit: the first block of a
+    70,000-row diagonal matrix also holds column 65,535 (span 65,536:
+    offsets up to 65,535) or column 65,536 (span 65,537: that block keeps
+    the four-byte columns); bit-equal to the four-byte kernel and against
+    the oracle."""
+    for far in (65535, 65536):
+        m = 70000
+        ents = [(i, i, float(v)) for i, v in enumerate(I.uniform(44, 0, m))] + [(0, far, 0.75), (1, 0, -0.5)]
+        A = csr_from_entries(m, m, ents, NP[dt])
+        M = spk.Matrix(A)
+        x = I.uniform(45, 0, m, NP[dt])
+        xd = torch.from_numpy(x).to(dev)
+        say(f"row blocks, two-byte columns at the limit: far column {far}, dtype={dt}")
+        try:
+            outs = []
+            for vec in (0, 2):
+                v = spk.make_variant(format=spk.SPK_FMT_ADAPTIVE, block=256, group=1, unroll=1, streams=1, lds=256,
+                                     vec=vec)
+                y = torch.full((m,), float("nan"), dtype=M.torch_dtype, device=dev)
+                w = torch.full_like(y, float("nan"))
+                spk.spk_run(spk.problem(spk.SPK_OP_SPMV_WAXPY, A=M, x=xd, y=y, w=w, alpha=0.5), v)
+                _check(A, x, y, w, 0.5, dt)
+                outs.append((y, w))
+            assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1]), far
+        finally:
+            M.release()
